@@ -1,0 +1,204 @@
+/*
+ * qlg.h -- C ABI of libqlg, the MI355X (gfx950) spin-2 quantum-lattice-gas step.
+ *
+ * The method is the unitary QLG algorithm for the spin-2 Gross-Pitaevskii
+ * equation of Taylor, Smith and Yepez (arXiv:1907.12834):
+ *   - equation of motion: Sec. II, eq. (eomspin2) with the spin-2 matrices
+ *     f_x, f_y, f_z printed there, couplings g0 (density), g1 (spin F.f),
+ *     g2 (singlet pair);
+ *   - encoding: two qubit amplitudes (a_m, b_m) per m_f level, psi = a + b
+ *     (Sec. III "Local quantum entanglement": 10 qubits per site);
+ *   - step: I'_q = S_q C S_q^T C, plain split psi(t+tau) = I'_1 I'_1 I'_2 I'_2 U psi(t)
+ *     and the interleaved split I'_1 U^{1/4} I'_1 U^{1/4} I'_2 U^{1/4} I'_2 U^{1/4}
+ *     (Lie product n = 4 in 1D, n = 8 in 2D) of Sec. VII "Operator interleaving";
+ *   - lattice scaling x -> a x, t -> a^2 t (Sec. VII "Scaling"): one step
+ *     advances physical time eps^2 on a lattice of spacing eps.
+ * The definitions of C, S and U that the paper defers to its references are
+ * fixed by the readings documented with the repository: C = sqrt(SWAP) with
+ * entries (1 -+ i)/2, S_q shifts qubit q by one site along +axis, and U is the
+ * per-site frozen-field unitary exp(-i th g0 n) exp(-i th g1 F.f)
+ * (I + (exp(-i th g2 n/5) - 1) v v^H / n), v_m = (-1)^m conj(psi_{-m}).
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers on the current HIP device;
+ *     *_host are host pointers.  The library never frees caller memory.
+ *   - Calls return a qlg_status.  Argument, shape and dtype errors are detected
+ *     on the host before any launch and leave the context unchanged.  A failed
+ *     HIP launch or copy returns QLG_ERR_DEVICE and puts the context into an
+ *     error state in which every later call except qlg_destroy and
+ *     qlg_last_error returns QLG_ERR_STATE.
+ *   - Work is enqueued on the caller's stream given at qlg_init (hipStream_t,
+ *     passed as void*; NULL is the default stream).  Calls that return host
+ *     data (qlg_observables, qlg_objective_grad, qlg_adjoint_step) synchronise
+ *     that stream; the others are asynchronous.
+ *   - No C++ exception crosses this interface.
+ *
+ * Field layout (the canonical layout for psi_dev / qubits_dev arguments):
+ *   complex numbers are interleaved (re, im), float for QLG_C64 and double for
+ *   QLG_C128.  Instances follow one another; within instance i,
+ *     psi[m][y][x]        m index 0..4 <-> m_f = 2, 1, 0, -1, -2, x fastest;
+ *     qubits[q][m][y][x]  q = 0 for a (the paper's qubit 1), 1 for b (qubit 2).
+ *   ny == 1 for 1D instances.
+ */
+#ifndef QLG_H
+#define QLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QLG_OK = 0,
+  QLG_ERR_ARG = 1,      /* NULL pointer, bad enum, non-finite coupling, buffer too small */
+  QLG_ERR_SHAPE = 2,    /* ndim not 1 or 2, extent < 1, lattice too large */
+  QLG_ERR_DTYPE = 3,    /* dtype not QLG_C64 / QLG_C128 */
+  QLG_ERR_DEVICE = 4,   /* a HIP call failed; message in qlg_last_error */
+  QLG_ERR_OOM = 5,      /* the library's own small metadata allocation failed */
+  QLG_ERR_STATE = 6,    /* context is in an error state, or call out of order */
+  QLG_ERR_NUMERIC = 7   /* non-finite values, or qubit norm drift above threshold */
+} qlg_status;
+
+typedef enum { QLG_C64 = 0, QLG_C128 = 1 } qlg_dtype;
+
+typedef enum {
+  QLG_SPLIT_INTERLEAVED = 0, /* U^{1/(4d)} before every I' (Sec. VII, Lie product n = 4d) */
+  QLG_SPLIT_PLAIN = 1        /* one U, then all I' (Sec. VII, the non-interleaved step) */
+} qlg_split;
+
+typedef struct qlg_params {
+  int32_t ndim;          /* 1 or 2 */
+  int32_t dtype;         /* qlg_dtype */
+  int32_t split;         /* qlg_split */
+  int32_t nbatch;        /* >= 1 independent lattices; they may differ in size */
+  const int64_t* nx;     /* [nbatch] x extents (host memory, copied at qlg_init) */
+  const int64_t* ny;     /* [nbatch] y extents, or NULL for ndim == 1 */
+  double g0, g1, g2;     /* couplings of eq. (eomspin2), shared by all instances */
+  double eps;            /* lattice spacing: one step = physical time eps^2; norms use eps^ndim */
+} qlg_params;
+
+typedef struct qlg_obs {
+  double norm_q;         /* eps^d sum (|a|^2 + |b|^2): conserved exactly by the method */
+  double norm_psi;       /* eps^d sum |a + b|^2 */
+  double pop[5];         /* eps^d sum |psi_m|^2, m = 2..-2 */
+  double energy;         /* eps^d sum [ sum_axis |psi(x+e)-psi(x)|^2/eps^2
+                                        + (g0 n^2 + g1 |F|^2 + g2 |sigma|^2/5)/2 ] */
+  double overlap_re;     /* eps^d <psi_t | psi_{t-1}> over the last step of the last qlg_step */
+  double overlap_im;
+  double e_overlap_re;   /* i (<psi_t|psi_t> - <psi_t|psi_{t-1}>) / <psi_t|psi_t>, Sec. IV
+                            eq. (disecrete_energy); ~ E eps^2 for an eigenstate */
+  double e_overlap_im;
+  int64_t step;          /* steps taken since the last qlg_set_psi / qlg_set_qubits */
+  int32_t has_overlap;   /* 1 if overlap_* refer to the last step, else 0 */
+  int32_t reserved;
+} qlg_obs;
+
+/* Launch plan of the fused step; chosen by qlg_autotune or set by the caller. */
+typedef struct qlg_tuning {
+  int32_t steps_per_pass; /* 1D: steps fused per HBM pass (1..4); 2D: must be 1 */
+  int32_t tile_rows;      /* 2D: rows per streaming tile (8..256); 1D: ignored */
+  int32_t use_graph;      /* 1: replay qlg_step's launches from a captured hipGraph */
+  int32_t reserved;
+} qlg_tuning;
+
+typedef struct qlg_ctx qlg_ctx;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t qlg_version(void);
+
+/* Bytes the caller must provide for a lattice described by *params:
+ *   state_bytes:   two copies (ping-pong) of all qubit planes, padded;
+ *   scratch_bytes: reduction partials for observables and overlaps.
+ * Errors: QLG_ERR_ARG / SHAPE / DTYPE as for qlg_init. */
+qlg_status qlg_query_sizes(const qlg_params* params, size_t* state_bytes, size_t* scratch_bytes);
+
+/* Create a context over caller-owned device buffers.  state_dev and
+ * scratch_dev must be 256-byte aligned and at least the sizes reported by
+ * qlg_query_sizes.  hip_stream is a hipStream_t (or NULL).  The state is
+ * undefined until qlg_set_psi or qlg_set_qubits.  The library allocates only
+ * a small device table of per-instance descriptors (freed by qlg_destroy). */
+qlg_status qlg_init(const qlg_params* params, void* state_dev, size_t state_bytes,
+                    void* scratch_dev, size_t scratch_bytes, void* hip_stream, qlg_ctx** out);
+
+/* Load psi (canonical layout) and encode a = b = psi / 2.  Resets the step counter. */
+qlg_status qlg_set_psi(qlg_ctx* ctx, const void* psi_dev);
+/* Decode psi = a + b into psi_dev (canonical layout). */
+qlg_status qlg_get_psi(qlg_ctx* ctx, void* psi_dev);
+/* Load / store both qubit amplitudes (canonical qubits layout). */
+qlg_status qlg_set_qubits(qlg_ctx* ctx, const void* qubits_dev);
+qlg_status qlg_get_qubits(qlg_ctx* ctx, void* qubits_dev);
+
+/* Advance every instance by nsteps >= 0 QLG steps (Sec. VII), asynchronously. */
+qlg_status qlg_step(qlg_ctx* ctx, int64_t nsteps);
+
+/* Norms, populations, energy and (if the last qlg_step call ended with a
+ * single-step pass) the overlap energy, per instance, into out_host[nbatch].
+ * Synchronises the stream.  Returns QLG_ERR_NUMERIC (after filling out_host)
+ * if any value is non-finite or |norm_q / norm_q(at set) - 1| exceeds 1e-4
+ * (C64) or 1e-10 (C128). */
+qlg_status qlg_observables(qlg_ctx* ctx, qlg_obs* out_host);
+
+/* Plan control.  qlg_autotune times the candidate plans on the context's own
+ * lattice without changing its state and keeps the fastest. */
+qlg_status qlg_set_tuning(qlg_ctx* ctx, const qlg_tuning* tuning);
+qlg_status qlg_get_tuning(const qlg_ctx* ctx, qlg_tuning* tuning);
+qlg_status qlg_autotune(qlg_ctx* ctx);
+
+/* Average device time in milliseconds of one launch of the fused step
+ * kernel over the last qlg_step call, measured with HIP events on the
+ * context's stream (0 if not measured).  Enabled by qlg_set_timing(ctx, 1). */
+qlg_status qlg_set_timing(qlg_ctx* ctx, int32_t enable);
+qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_host);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative of a final-state objective).
+ *
+ * Cotangents use the convention lambda = dL/dRe z + i dL/dIm z for every
+ * complex amplitude z (so d|z|^2 has cotangent 2 z).  Adjoint vectors are
+ * complex128 in the qubits layout, whatever the forward dtype; the
+ * self-interaction Jacobian is evaluated in FP64.
+ * ------------------------------------------------------------------------- */
+
+/* Sizes for recording a forward run of nsteps with a checkpoint every
+ * checkpoint_every steps (>= 1), and for the adjoint workspace. */
+qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t checkpoint_every,
+                             size_t* ckpt_bytes, size_t* work_bytes);
+
+/* Run nsteps forward from the current state, storing the state at steps
+ * 0, K, 2K, ... (K = checkpoint_every) into ckpt_dev. */
+qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every,
+                              void* ckpt_dev, size_t ckpt_bytes);
+
+/* Objective of the current state and its cotangent lambda (complex128 qubits layout):
+ *   kind 0: energy E of qlg_obs (per instance, summed over instances);
+ *   kind 1: fidelity |<target|psi>|^2 with target_dev in the canonical psi layout
+ *           (forward dtype), summed over instances.
+ * value_host[0] receives L; dg_host[3] (may be NULL) receives the explicit
+ * dL/d(g0, g1, g2).  Synchronises the stream. */
+qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev,
+                              void* lambda_dev, double* value_host, double* dg_host);
+
+/* Pull lambda back through the nsteps recorded by qlg_forward_record
+ * (same nsteps and checkpoint_every): on entry lambda_dev holds dL/d(state at
+ * the end), on exit dL/d(state at the start).  dg_host[3] is incremented by
+ * dL/d(g0, g1, g2) accumulated over the steps.  work_dev must hold work_bytes
+ * from qlg_adjoint_query.  The context's current state is left at the end
+ * state of the recorded run.  Synchronises the stream. */
+qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every,
+                            const void* ckpt_dev, void* lambda_dev, void* work_dev,
+                            size_t work_bytes, double* dg_host);
+
+/* Human-readable status name, and the last error message of a context. */
+const char* qlg_status_string(qlg_status status);
+const char* qlg_last_error(const qlg_ctx* ctx);
+
+/* Release the context (never the caller's buffers).  NULL is allowed. */
+void qlg_destroy(qlg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLG_H */

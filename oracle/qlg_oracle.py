@@ -138,6 +138,32 @@ def invariants(psi: torch.Tensor):
     return n, F, time_reverse(psi)
 
 
+def expm(M: torch.Tensor, max_terms: int = 18) -> torch.Tensor:
+    """Matrix exponential of a batch (..., k, k) by its power series.
+
+    exp(M) = (sum_{j<=N} (M/2^s)^j / j!)^(2^s), with s chosen so that
+    r = ||M/2^s||_1 <= 1/2 for every matrix of the batch and N the smallest
+    number of terms whose remainder bound r^(N+1)/(N+1)! * 2 is below 1e-18.
+    (torch.linalg.matrix_exp was not used: for a batch of one matrix of norm
+    ~0.01-0.02 it is only accurate to ~1e-12.)
+    """
+    norm = float(M.abs().sum(-2).amax()) if M.numel() else 0.0
+    s = max(0, int(math.ceil(math.log2(norm / 0.5)))) if norm > 0.5 else 0
+    r = norm / (2.0 ** s)
+    N, term = 1, r
+    while N < max_terms and 2.0 * term * r / (N + 1) > 1e-18:
+        N += 1
+        term *= r / N
+    A = M / (2.0 ** s)
+    eye = torch.eye(M.shape[-1], dtype=M.dtype).expand_as(M)
+    T = eye
+    for j in range(N, 0, -1):              # Horner: I + A/1 (I + A/2 (I + ... ))
+        T = eye + (A @ T) / j
+    for _ in range(s):
+        T = T @ T
+    return T
+
+
 def potential(a: torch.Tensor, b: torch.Tensor, theta: float, g: Sequence[float]):
     """Apply W = e^{-i th g0 n} exp(-i th g1 F.f) P_A to a and b (same frozen W)."""
     g0, g1, g2 = g
@@ -150,7 +176,7 @@ def potential(a: torch.Tensor, b: torch.Tensor, theta: float, g: Sequence[float]
                       torch.zeros_like(n, dtype=CDT))
     # spin factor R = exp(-i th g1 F.f), one 5x5 matrix exponential per site
     H = (F[0].reshape(-1, 1, 1) * FX + F[1].reshape(-1, 1, 1) * FY + F[2].reshape(-1, 1, 1) * FZ)
-    R = torch.linalg.matrix_exp(-1j * theta * g1 * H)           # (sites, 5, 5)
+    R = expm(-1j * theta * g1 * H)                               # (sites, 5, 5)
     dens = torch.exp(-1j * theta * g0 * n).reshape(-1)
 
     out = []

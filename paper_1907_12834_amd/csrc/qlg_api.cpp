@@ -1,0 +1,649 @@
+// C ABI of libqlg (include/qlg.h): context, validation, layout tables, the
+// step schedule, hipGraph replay, kernel timing, observables and autotuning.
+#include "../../include/qlg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qlg_internal.hpp"
+#include "qlg_adjoint.hpp"
+
+using qlg::InstDesc;
+using qlg::LaunchGeom;
+
+namespace {
+
+constexpr int64_t kMaxExtent = int64_t(1) << 30;
+constexpr int64_t kMaxSites = (int64_t(1) << 31) - 1;
+constexpr int kMaxSteps1D = 4;
+constexpr int kMinTileRows = 8, kMaxTileRows = 256;
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  std::vector<InstDesc> inst;
+  int64_t elems_per_copy = 0;     // complex elements in one state copy
+  int64_t psi_elems = 0;
+  int32_t nchunks = 0;
+  int32_t max_tiles = 0;          // tiles at the densest plan (used to size scratch)
+};
+
+int tiles_1d(int64_t nx, int steps) {
+  const int tv = qlg::kLanes - 8 * steps;
+  return (int)((nx + tv - 1) / tv);
+}
+
+void tiles_2d(int64_t nx, int64_t ny, int rows, int* ntx, int* nty) {
+  *ntx = (int)((nx + qlg::kValid2D - 1) / qlg::kValid2D);
+  *nty = (int)((ny + rows - 1) / rows);
+}
+
+qlg_status validate(const qlg_params* p, std::string* msg) {
+  if (!p) { *msg = "params is NULL"; return QLG_ERR_ARG; }
+  if (p->ndim != 1 && p->ndim != 2) { *msg = "ndim must be 1 or 2"; return QLG_ERR_SHAPE; }
+  if (p->dtype != QLG_C64 && p->dtype != QLG_C128) { *msg = "dtype must be QLG_C64 or QLG_C128"; return QLG_ERR_DTYPE; }
+  if (p->split != QLG_SPLIT_INTERLEAVED && p->split != QLG_SPLIT_PLAIN) { *msg = "unknown split"; return QLG_ERR_ARG; }
+  if (p->nbatch < 1) { *msg = "nbatch must be >= 1"; return QLG_ERR_SHAPE; }
+  if (!p->nx) { *msg = "nx is NULL"; return QLG_ERR_ARG; }
+  if (p->ndim == 2 && !p->ny) { *msg = "ny is NULL for a 2D lattice"; return QLG_ERR_ARG; }
+  if (!std::isfinite(p->g0) || !std::isfinite(p->g1) || !std::isfinite(p->g2)) { *msg = "couplings must be finite"; return QLG_ERR_ARG; }
+  if (!std::isfinite(p->eps) || !(p->eps > 0)) { *msg = "eps must be finite and > 0"; return QLG_ERR_ARG; }
+  for (int i = 0; i < p->nbatch; ++i) {
+    const int64_t nx = p->nx[i];
+    const int64_t ny = p->ndim == 2 ? p->ny[i] : (p->ny ? p->ny[i] : 1);
+    if (nx < 1 || ny < 1 || nx > kMaxExtent || ny > kMaxExtent) { *msg = "extents must be in [1, 2^30]"; return QLG_ERR_SHAPE; }
+    if (p->ndim == 1 && ny != 1) { *msg = "ny must be 1 (or NULL) for ndim == 1"; return QLG_ERR_SHAPE; }
+    if (nx * ny > kMaxSites) { *msg = "an instance exceeds 2^31-1 sites"; return QLG_ERR_SHAPE; }
+  }
+  return QLG_OK;
+}
+
+Layout make_layout(const qlg_params* p) {
+  Layout L;
+  int64_t off = 0, poff = 0;
+  int32_t chunk = 0;
+  int32_t maxt = 0;
+  for (int i = 0; i < p->nbatch; ++i) {
+    InstDesc d{};
+    d.nx = (int32_t)p->nx[i];
+    d.ny = p->ndim == 2 ? (int32_t)p->ny[i] : 1;
+    d.sites = d.nx * d.ny;
+    d.stride = round_up(d.sites, 64);
+    d.off = off;
+    d.psi_off = poff;
+    d.qb_off = 2 * poff;
+    d.chunk_begin = chunk;
+    d.nchunks = (d.sites + qlg::kChunk - 1) / qlg::kChunk;
+    off += 10 * d.stride;
+    poff += 5 * (int64_t)d.sites;
+    chunk += d.nchunks;
+    if (p->ndim == 1) maxt += tiles_1d(d.nx, kMaxSteps1D);
+    else { int a, b; tiles_2d(d.nx, d.ny, kMinTileRows, &a, &b); maxt += a * b; }
+    L.inst.push_back(d);
+  }
+  L.elems_per_copy = off;
+  L.psi_elems = poff;
+  L.nchunks = chunk;
+  L.max_tiles = maxt;
+  return L;
+}
+
+struct ScratchLayout {
+  size_t obs_part, obs_res, norm0, ov_part, ov_res, total;  // byte offsets
+};
+
+ScratchLayout scratch_layout(const Layout& L, int nbatch) {
+  ScratchLayout s;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+  s.obs_part = take(sizeof(double) * qlg::kNObs * (size_t)std::max(L.nchunks, 1));
+  s.obs_res = take(sizeof(double) * qlg::kNObs * nbatch);
+  s.norm0 = take(sizeof(double) * qlg::kNObs * nbatch);
+  s.ov_part = take(sizeof(double) * 2 * (size_t)std::max(L.max_tiles, 1));
+  s.ov_res = take(sizeof(double) * 2 * nbatch);
+  s.total = o;
+  return s;
+}
+
+// Process-wide autotune cache keyed by (arch, dtype, ndim, split, size class).
+std::mutex g_tune_mu;
+std::map<std::string, qlg_tuning> g_tune_cache;
+
+}  // namespace
+
+struct qlg_ctx {
+  qlg_params p{};
+  std::vector<int64_t> nx, ny;
+  Layout L;
+  ScratchLayout S{};
+  char* state = nullptr;
+  size_t state_bytes = 0;
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipStream_t stream = nullptr;
+  int cur = 0;
+  size_t elem_bytes = 8;
+  // device tables
+  InstDesc* d_inst = nullptr;
+  int32_t* d_tile2inst = nullptr;
+  int32_t* d_chunk2inst = nullptr;
+  int32_t ntiles = 0;
+  qlg_tuning tuning{1, 32, 0, 0};
+  bool tuned = false;
+  // bookkeeping
+  int64_t step_count = 0;
+  bool has_overlap = false;
+  bool norm0_valid = false;
+  bool broken = false;
+  std::string err;
+  // graphs keyed by (nsteps, start copy)
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  double last_ms = 0.0;
+  int64_t last_launches = 0;
+
+  LaunchGeom geom() const {
+    LaunchGeom g;
+    g.inst = d_inst;
+    g.tile2inst = d_tile2inst;
+    g.chunk2inst = d_chunk2inst;
+    g.ntiles = ntiles;
+    g.nchunks = L.nchunks;
+    g.nbatch = p.nbatch;
+    return g;
+  }
+  char* copy(int c) const { return state + (size_t)c * L.elems_per_copy * elem_bytes; }
+  double* sc(size_t off) const { return reinterpret_cast<double*>(scratch + off); }
+};
+
+namespace {
+
+qlg_status fail(qlg_ctx* c, qlg_status s, const std::string& m) {
+  if (c) {
+    c->err = m;
+    if (s == QLG_ERR_DEVICE) c->broken = true;
+  }
+  return s;
+}
+
+qlg_status hip_check(qlg_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QLG_OK;
+  return fail(c, QLG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void drop_graphs(qlg_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+// Rebuild the wave-tile tables for the current plan.
+qlg_status build_tiles(qlg_ctx* c) {
+  std::vector<int32_t> t2i;
+  for (int i = 0; i < c->p.nbatch; ++i) {
+    InstDesc& d = c->L.inst[i];
+    d.tile_begin = (int32_t)t2i.size();
+    if (c->p.ndim == 1) {
+      d.ntx = tiles_1d(d.nx, c->tuning.steps_per_pass);
+      d.nty = 1;
+    } else {
+      tiles_2d(d.nx, d.ny, c->tuning.tile_rows, &d.ntx, &d.nty);
+    }
+    for (int k = 0; k < d.ntx * d.nty; ++k) t2i.push_back(i);
+  }
+  if ((int32_t)t2i.size() > c->L.max_tiles) return fail(c, QLG_ERR_ARG, "tile table overflow");
+  c->ntiles = (int32_t)t2i.size();
+  c->has_overlap = false;   // overlap partials refer to the previous tile layout
+  qlg_status s = hip_check(c, hipMemcpyAsync(c->d_inst, c->L.inst.data(), sizeof(InstDesc) * c->L.inst.size(),
+                                             hipMemcpyHostToDevice, c->stream), "copy instance table");
+  if (s) return s;
+  s = hip_check(c, hipMemcpyAsync(c->d_tile2inst, t2i.data(), sizeof(int32_t) * t2i.size(),
+                                  hipMemcpyHostToDevice, c->stream), "copy tile table");
+  if (s) return s;
+  // the host vectors must outlive the async copies
+  s = hip_check(c, hipStreamSynchronize(c->stream), "sync after table upload");
+  drop_graphs(c);
+  return s;
+}
+
+qlg_status check_ctx(qlg_ctx* c) {
+  if (!c) return QLG_ERR_ARG;
+  if (c->broken) return QLG_ERR_STATE;
+  return QLG_OK;
+}
+
+double angle_scale(const qlg_ctx* c) {   // interleaved theta = eps^2 / (4 d)
+  return c->p.eps * c->p.eps / (4.0 * c->p.ndim);
+}
+
+hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void* out) {
+  const double th = angle_scale(c);
+  const LaunchGeom g = c->geom();
+  double* ov = c->sc(c->S.ov_part);
+  const bool plain = c->p.split == QLG_SPLIT_PLAIN;
+  if (c->p.ndim == 1)
+    return qlg::launch_step1d(c->p.dtype, steps, plain, overlap, in, out, g, th * c->p.g0, th * c->p.g1,
+                              th * c->p.g2 / 5.0, ov, c->stream);
+  return qlg::launch_step2d(c->p.dtype, plain, overlap, c->tuning.tile_rows, in, out, g, th * c->p.g0,
+                            th * c->p.g1, th * c->p.g2 / 5.0, ov, c->stream);
+}
+
+// Enqueue nsteps as passes of steps_per_pass (1D) or single steps (2D), ping-ponging
+// between the two copies.  The last pass records the overlap partials.
+qlg_status enqueue_steps(qlg_ctx* c, int64_t nsteps, int* cur, bool timed) {
+  const int S = c->p.ndim == 1 ? c->tuning.steps_per_pass : 1;
+  int64_t left = nsteps;
+  int64_t launch = 0;
+  while (left > 0) {
+    const int s = (int)std::min<int64_t>(S, left);
+    const bool last = left == s;
+    if (timed) {
+      const size_t k = 2 * (size_t)launch;
+      if (k + 1 < c->ev.size()) (void)hipEventRecord(c->ev[k], c->stream);
+    }
+    hipError_t e = launch_pass(c, s, last, c->copy(*cur), c->copy(1 - *cur));
+    if (e != hipSuccess) return hip_check(c, e, "step kernel launch");
+    if (timed) {
+      const size_t k = 2 * (size_t)launch;
+      if (k + 1 < c->ev.size()) (void)hipEventRecord(c->ev[k + 1], c->stream);
+    }
+    *cur = 1 - *cur;
+    left -= s;
+    ++launch;
+  }
+  return QLG_OK;
+}
+
+std::string tune_key(const qlg_ctx* c) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, dev);
+  int64_t sites = 0;
+  for (auto& d : c->L.inst) sites += d.sites;
+  int sclass = 0;
+  while ((int64_t(1) << sclass) < sites) ++sclass;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|%d|%d|%d|%d|%d", prop.gcnArchName, c->p.dtype, c->p.ndim, c->p.split,
+           c->p.nbatch > 1 ? 1 : 0, sclass);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t qlg_version(void) { return 10000; }
+
+const char* qlg_status_string(qlg_status s) {
+  switch (s) {
+    case QLG_OK: return "QLG_OK";
+    case QLG_ERR_ARG: return "QLG_ERR_ARG";
+    case QLG_ERR_SHAPE: return "QLG_ERR_SHAPE";
+    case QLG_ERR_DTYPE: return "QLG_ERR_DTYPE";
+    case QLG_ERR_DEVICE: return "QLG_ERR_DEVICE";
+    case QLG_ERR_OOM: return "QLG_ERR_OOM";
+    case QLG_ERR_STATE: return "QLG_ERR_STATE";
+    case QLG_ERR_NUMERIC: return "QLG_ERR_NUMERIC";
+  }
+  return "QLG_ERR_UNKNOWN";
+}
+
+const char* qlg_last_error(const qlg_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+qlg_status qlg_query_sizes(const qlg_params* p, size_t* state_bytes, size_t* scratch_bytes) {
+  std::string msg;
+  qlg_status s = validate(p, &msg);
+  if (s) return s;
+  if (!state_bytes || !scratch_bytes) return QLG_ERR_ARG;
+  const Layout L = make_layout(p);
+  const size_t eb = p->dtype == QLG_C64 ? 8 : 16;
+  *state_bytes = 2 * (size_t)L.elems_per_copy * eb;
+  *scratch_bytes = scratch_layout(L, p->nbatch).total;
+  return QLG_OK;
+}
+
+qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, void* scratch_dev,
+                    size_t scratch_bytes, void* hip_stream, qlg_ctx** out) {
+  if (!out) return QLG_ERR_ARG;
+  *out = nullptr;
+  std::string msg;
+  qlg_status s = validate(p, &msg);
+  if (s) return s;
+  if (!state_dev || !scratch_dev) return QLG_ERR_ARG;
+  if (((uintptr_t)state_dev & 255) || ((uintptr_t)scratch_dev & 255)) return QLG_ERR_ARG;
+  size_t need_state = 0, need_scratch = 0;
+  qlg_query_sizes(p, &need_state, &need_scratch);
+  if (state_bytes < need_state || scratch_bytes < need_scratch) return QLG_ERR_ARG;
+
+  qlg_ctx* c = new (std::nothrow) qlg_ctx();
+  if (!c) return QLG_ERR_OOM;
+  c->p = *p;
+  c->nx.assign(p->nx, p->nx + p->nbatch);
+  if (p->ndim == 2) c->ny.assign(p->ny, p->ny + p->nbatch);
+  else c->ny.assign(p->nbatch, 1);
+  c->p.nx = c->nx.data();
+  c->p.ny = c->ny.data();
+  c->L = make_layout(&c->p);
+  c->S = scratch_layout(c->L, p->nbatch);
+  c->state = (char*)state_dev;
+  c->state_bytes = state_bytes;
+  c->scratch = (char*)scratch_dev;
+  c->scratch_bytes = scratch_bytes;
+  c->stream = (hipStream_t)hip_stream;
+  c->elem_bytes = p->dtype == QLG_C64 ? 8 : 16;
+  if (p->ndim == 2) c->tuning = qlg_tuning{1, 32, 0, 0};
+  else c->tuning = qlg_tuning{1, 0, 0, 0};
+
+  hipError_t e = hipMalloc(&c->d_inst, sizeof(InstDesc) * p->nbatch);
+  if (e == hipSuccess) e = hipMalloc(&c->d_tile2inst, sizeof(int32_t) * std::max(c->L.max_tiles, 1));
+  if (e == hipSuccess) e = hipMalloc(&c->d_chunk2inst, sizeof(int32_t) * std::max(c->L.nchunks, 1));
+  if (e != hipSuccess) {
+    qlg_destroy(c);
+    return e == hipErrorOutOfMemory ? QLG_ERR_OOM : QLG_ERR_DEVICE;
+  }
+  std::vector<int32_t> c2i;
+  for (int i = 0; i < p->nbatch; ++i)
+    for (int k = 0; k < c->L.inst[i].nchunks; ++k) c2i.push_back(i);
+  e = hipMemcpy(c->d_chunk2inst, c2i.data(), sizeof(int32_t) * c2i.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    qlg_destroy(c);
+    return QLG_ERR_DEVICE;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(c));
+    if (it != g_tune_cache.end()) { c->tuning = it->second; c->tuned = true; }
+  }
+  s = build_tiles(c);
+  if (s) {
+    qlg_destroy(c);
+    return s;
+  }
+  *out = c;
+  return QLG_OK;
+}
+
+void qlg_destroy(qlg_ctx* c) {
+  if (!c) return;
+  drop_graphs(c);
+  for (auto ev : c->ev) (void)hipEventDestroy(ev);
+  if (c->d_inst) (void)hipFree(c->d_inst);
+  if (c->d_tile2inst) (void)hipFree(c->d_tile2inst);
+  if (c->d_chunk2inst) (void)hipFree(c->d_chunk2inst);
+  delete c;
+}
+
+static qlg_status after_set(qlg_ctx* c) {
+  c->step_count = 0;
+  c->has_overlap = false;
+  // reference norm for the drift check, kept on the device
+  hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), c->geom(), c->p.g0, c->p.g1,
+                                         c->p.g2, c->sc(c->S.obs_part), c->sc(c->S.norm0), c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "observables kernel");
+  c->norm0_valid = true;
+  return QLG_OK;
+}
+
+qlg_status qlg_set_psi(qlg_ctx* c, const void* psi) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!psi) return fail(c, QLG_ERR_ARG, "psi is NULL");
+  hipError_t e = qlg::launch_set_psi(c->p.dtype, psi, c->copy(c->cur), c->geom(), c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "set_psi kernel");
+  return after_set(c);
+}
+
+qlg_status qlg_get_psi(qlg_ctx* c, void* psi) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!psi) return fail(c, QLG_ERR_ARG, "psi is NULL");
+  return hip_check(c, qlg::launch_get_psi(c->p.dtype, c->copy(c->cur), psi, c->geom(), c->stream), "get_psi kernel");
+}
+
+qlg_status qlg_set_qubits(qlg_ctx* c, const void* qb) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!qb) return fail(c, QLG_ERR_ARG, "qubits is NULL");
+  hipError_t e = qlg::launch_set_qubits(c->p.dtype, qb, c->copy(c->cur), c->geom(), c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "set_qubits kernel");
+  return after_set(c);
+}
+
+qlg_status qlg_get_qubits(qlg_ctx* c, void* qb) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!qb) return fail(c, QLG_ERR_ARG, "qubits is NULL");
+  return hip_check(c, qlg::launch_get_qubits(c->p.dtype, c->copy(c->cur), qb, c->geom(), c->stream),
+                   "get_qubits kernel");
+}
+
+qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (nsteps < 0) return fail(c, QLG_ERR_ARG, "nsteps must be >= 0");
+  if (nsteps == 0) return QLG_OK;
+  const int S = c->p.ndim == 1 ? c->tuning.steps_per_pass : 1;
+  const int64_t launches = (nsteps + S - 1) / S;
+  if (c->timing) {
+    const size_t need = 2 * (size_t)std::min<int64_t>(launches, 4096);
+    while (c->ev.size() < need) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) break;
+      c->ev.push_back(ev);
+    }
+    int cur = c->cur;
+    s = enqueue_steps(c, nsteps, &cur, true);
+    if (s) return s;
+    c->cur = cur;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "sync for timing");
+    if (s) return s;
+    double tot = 0.0;
+    int64_t n = 0;
+    for (int64_t k = 0; k < launches && 2 * (size_t)k + 1 < c->ev.size(); ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) { tot += ms; ++n; }
+    }
+    c->last_ms = n ? tot / n : 0.0;
+    c->last_launches = n;
+  } else if (c->tuning.use_graph && launches > 1) {
+    auto key = std::make_pair(nsteps, c->cur);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      hipStream_t cap = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_check(c, e, "create capture stream");
+      hipStream_t saved = c->stream;
+      c->stream = cap;
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      int cur = c->cur;
+      if (e == hipSuccess) s = enqueue_steps(c, nsteps, &cur, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(cap, &graph);
+      c->stream = saved;
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess) return hip_check(c, e, "begin capture");
+      if (s) { if (graph) (void)hipGraphDestroy(graph); return s; }
+      if (e2 != hipSuccess) return hip_check(c, e2, "end capture");
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_check(c, e, "instantiate graph");
+      it = c->graphs.emplace(key, exec).first;
+    }
+    s = hip_check(c, hipGraphLaunch(it->second, c->stream), "graph launch");
+    if (s) return s;
+    if (launches % 2) c->cur = 1 - c->cur;
+  } else {
+    int cur = c->cur;
+    s = enqueue_steps(c, nsteps, &cur, false);
+    if (s) return s;
+    c->cur = cur;
+  }
+  c->step_count += nsteps;
+  c->has_overlap = true;
+  return QLG_OK;
+}
+
+qlg_status qlg_observables(qlg_ctx* c, qlg_obs* out) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!out) return fail(c, QLG_ERR_ARG, "out is NULL");
+  const LaunchGeom g = c->geom();
+  hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), g, c->p.g0, c->p.g1, c->p.g2,
+                                         c->sc(c->S.obs_part), c->sc(c->S.obs_res), c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "observables kernel");
+  if (c->has_overlap) {
+    e = qlg::launch_overlap_reduce(g, c->sc(c->S.ov_part), c->sc(c->S.ov_res), c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "overlap reduce kernel");
+  }
+  const int nb = c->p.nbatch;
+  std::vector<double> res((size_t)nb * qlg::kNObs), n0((size_t)nb * qlg::kNObs), ov((size_t)nb * 2, 0.0);
+  e = hipMemcpyAsync(res.data(), c->sc(c->S.obs_res), res.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && c->norm0_valid)
+    e = hipMemcpyAsync(n0.data(), c->sc(c->S.norm0), n0.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && c->has_overlap)
+    e = hipMemcpyAsync(ov.data(), c->sc(c->S.ov_res), ov.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "copy observables");
+  const double meas = std::pow(c->p.eps, c->p.ndim);
+  const double tol = c->p.dtype == QLG_C64 ? 1e-4 : 1e-10;
+  bool bad = false;
+  for (int i = 0; i < nb; ++i) {
+    const double* r = &res[(size_t)i * qlg::kNObs];
+    qlg_obs& o = out[i];
+    std::memset(&o, 0, sizeof o);
+    o.norm_q = meas * r[0];
+    o.norm_psi = meas * r[1];
+    for (int m = 0; m < 5; ++m) o.pop[m] = meas * r[2 + m];
+    o.energy = meas * (r[7] / (c->p.eps * c->p.eps) + r[8]);
+    o.step = c->step_count;
+    o.has_overlap = c->has_overlap ? 1 : 0;
+    if (c->has_overlap) {
+      o.overlap_re = meas * ov[2 * i];
+      o.overlap_im = meas * ov[2 * i + 1];
+      const double nn = o.norm_psi;
+      if (nn > 0) {   // i (nn - ov) / nn
+        o.e_overlap_re = o.overlap_im / nn;
+        o.e_overlap_im = (nn - o.overlap_re) / nn;
+      }
+    }
+    for (int k = 0; k < qlg::kNObs; ++k) bad |= !std::isfinite(r[k]);
+    if (c->norm0_valid && n0[(size_t)i * qlg::kNObs] > 0) {
+      const double drift = r[0] / n0[(size_t)i * qlg::kNObs] - 1.0;
+      bad |= !(std::fabs(drift) <= tol);
+    }
+  }
+  if (bad) return fail(c, QLG_ERR_NUMERIC, "non-finite observable or qubit-norm drift above threshold");
+  return QLG_OK;
+}
+
+qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!t) return fail(c, QLG_ERR_ARG, "tuning is NULL");
+  qlg_tuning n = *t;
+  if (c->p.ndim == 1) {
+    if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..4 in 1D");
+    n.tile_rows = 0;
+  } else {
+    if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D");
+    if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return fail(c, QLG_ERR_ARG, "tile_rows must be 8..256");
+  }
+  n.use_graph = n.use_graph ? 1 : 0;
+  c->tuning = n;
+  return build_tiles(c);
+}
+
+qlg_status qlg_get_tuning(const qlg_ctx* c, qlg_tuning* t) {
+  if (!c || !t) return QLG_ERR_ARG;
+  *t = c->tuning;
+  return QLG_OK;
+}
+
+qlg_status qlg_autotune(qlg_ctx* c) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  std::vector<qlg_tuning> cand;
+  if (c->p.ndim == 1)
+    for (int S = 1; S <= kMaxSteps1D; ++S) cand.push_back(qlg_tuning{S, 0, c->tuning.use_graph, 0});
+  else
+    for (int r : {16, 32, 64, 128}) cand.push_back(qlg_tuning{1, r, c->tuning.use_graph, 0});
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(c, QLG_ERR_DEVICE, "event create");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(c, QLG_ERR_DEVICE, "event create"); }
+  double best = 1e300;
+  qlg_tuning best_t = c->tuning;
+  for (const auto& t : cand) {
+    c->tuning = t;
+    if ((s = build_tiles(c))) break;
+    const int S = c->p.ndim == 1 ? t.steps_per_pass : 1;
+    // passes read the current copy and write the other one without swapping: the state is unchanged
+    hipError_t e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur));
+    const int reps = 5;
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur));
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { s = hip_check(c, e, "autotune"); break; }
+    const double per_step = ms / (reps * (double)S);
+    if (per_step < best) { best = per_step; best_t = t; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) return s;
+  c->tuning = best_t;
+  c->tuned = true;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(c)] = best_t;
+  }
+  return build_tiles(c);
+}
+
+qlg_status qlg_set_timing(qlg_ctx* c, int32_t enable) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  c->timing = enable != 0;
+  return QLG_OK;
+}
+
+qlg_status qlg_last_kernel_ms(qlg_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return QLG_ERR_ARG;
+  *ms = c->last_ms;
+  *launches = c->last_launches;
+  return QLG_OK;
+}
+
+}  // extern "C"
+
+// Accessors used by the adjoint implementation (qlg_adjoint.cpp).
+namespace qlg {
+CtxView ctx_view(qlg_ctx* c) {
+  CtxView v;
+  v.p = &c->p;
+  v.L_inst = c->L.inst.data();
+  v.elems_per_copy = c->L.elems_per_copy;
+  v.state = c->state;
+  v.elem_bytes = c->elem_bytes;
+  v.stream = c->stream;
+  v.cur = &c->cur;
+  v.geom = c->geom();
+  return v;
+}
+qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg) { return fail(c, s, msg); }
+qlg_status ctx_step(qlg_ctx* c, int64_t nsteps) { return qlg_step(c, nsteps); }
+bool ctx_broken(const qlg_ctx* c) { return c->broken; }
+}  // namespace qlg

@@ -1,0 +1,55 @@
+// Internal declarations shared by the kernels (qlg_kernels.hip) and the C ABI
+// implementation (qlg_api.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qlg {
+
+// One lattice instance inside a batch.  Offsets are in complex elements.
+struct InstDesc {
+  int64_t off;        // first element of the instance's 10 qubit planes in one state copy
+  int64_t psi_off;    // first element of the instance in the canonical psi layout
+  int64_t qb_off;     // first element of the instance in the canonical qubits layout
+  int64_t stride;     // plane stride (>= sites, multiple of 64)
+  int32_t nx, ny;     // extents (ny = 1 in 1D)
+  int32_t sites;      // nx * ny
+  int32_t tile_begin; // first global wave tile of the fused step
+  int32_t ntx, nty;   // tiles along x and y (nty = 1 in 1D)
+  int32_t chunk_begin;// first 256-site chunk for elementwise / reduction kernels
+  int32_t nchunks;
+};
+
+constexpr int kChunk = 256;      // sites per chunk of the elementwise / reduction kernels
+constexpr int kNObs = 10;        // norm_q, norm_psi, pop[5], e_kin, e_pot, spare
+constexpr int kLanes = 64;       // wavefront width on gfx950
+constexpr int kHalo2D = 4;       // x halo of the 2D kernel (4 I' per axis per step)
+constexpr int kValid2D = kLanes - 2 * kHalo2D;
+
+struct LaunchGeom {
+  const InstDesc* inst;      // device [nbatch]
+  const int32_t* tile2inst;  // device [ntiles]
+  const int32_t* chunk2inst; // device [nchunks]
+  int32_t ntiles, nchunks, nbatch;
+};
+
+// Kernel launchers (qlg_kernels.hip).  All return the hipError_t of the launch.
+// dtype: 0 = complex64, 1 = complex128.  Angles are theta*g0, theta*g1, theta*g2/5.
+hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
+                         hipStream_t st);
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
+                         hipStream_t st);
+hipError_t launch_set_psi(int dtype, const void* psi, void* state, const LaunchGeom& g, hipStream_t st);
+hipError_t launch_get_psi(int dtype, const void* state, void* psi, const LaunchGeom& g, hipStream_t st);
+hipError_t launch_set_qubits(int dtype, const void* qb, void* state, const LaunchGeom& g, hipStream_t st);
+hipError_t launch_get_qubits(int dtype, const void* state, void* qb, const LaunchGeom& g, hipStream_t st);
+// Per-instance sums of the kNObs observables into res[nbatch][kNObs] (unscaled sums).
+hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
+                              double g1, double g2, double* part, double* res, hipStream_t st);
+// Per-instance sums of the per-tile overlap partials into res[nbatch][2].
+hipError_t launch_overlap_reduce(const LaunchGeom& g, const double* ovpart, double* res, hipStream_t st);
+
+}  // namespace qlg

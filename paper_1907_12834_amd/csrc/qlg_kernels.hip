@@ -1,0 +1,572 @@
+// HIP kernels of the spin-2 QLG step for gfx950 (CDNA4).
+//
+// Fused step, 1D: one wavefront owns a tile of 64 consecutive sites, one site
+// per lane, with 4*S halo sites on each side for S fused steps (each I' has
+// dependency radius one site).  All five (a_m, b_m) pairs of a site stay in
+// registers for the whole pass; the +-1 site streams are cross-lane moves.
+// Interior lanes are written back once per pass.
+//
+// Fused step, 2D: one wavefront owns 64 columns (56 interior + 4 halo each
+// side) and streams down a band of rows.  The y half of the step (Sec. VII
+// schedule: U, I'_{y,b}, U, I'_{y,b}, U, I'_{y,a}, U, I'_{y,a}) is a four-stage
+// software pipeline along the row loop: each stage keeps one row of pending
+// amplitudes in registers, so the y streams never leave the lane.  A row that
+// leaves the last stage runs the x half (U, I'_{x,b}, ..., I'_{x,a}) across
+// lanes and is stored.  One HBM read and one write per site per step, plus
+// the halo rows and columns.
+//
+// The self-interaction U (qlg_math.hpp) is the arithmetic core: the path is
+// bound by the vector ALUs, not by HBM, and uses no matrix cores.
+
+#include "qlg_internal.hpp"
+#include "qlg_math.hpp"
+
+namespace qlg {
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_from_next(cx<T> v) {   // value of lane + 1
+  return cx<T>{__shfl_down(v.re, 1, kLanes), __shfl_down(v.im, 1, kLanes)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_from_prev(cx<T> v) {   // value of lane - 1
+  return cx<T>{__shfl_up(v.re, 1, kLanes), __shfl_up(v.im, 1, kLanes)};
+}
+
+// I'_{x,q} = S_q C S_q^T C with lanes along x; qb selects the moving qubit
+// (false: a, the paper's qubit 1; true: b, qubit 2).  qb is wave-uniform.
+template <typename T>
+__device__ __forceinline__ void iprime_lanes(cx<T> (&a)[5], cx<T> (&b)[5], bool qb) {
+  collide2(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {   // S^T: q(x) <- q(x + 1)
+    const cx<T> v = shfl_from_next(sel(qb, b[m], a[m]));
+    a[m] = sel(qb, a[m], v);   // value selects keep a and b in registers
+    b[m] = sel(qb, v, b[m]);
+  }
+  collide2(a, b);
+  scale_quarter(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {   // S: q(x) <- q(x - 1)
+    const cx<T> v = shfl_from_prev(sel(qb, b[m], a[m]));
+    a[m] = sel(qb, a[m], v);
+    b[m] = sel(qb, v, b[m]);
+  }
+}
+
+__device__ __forceinline__ int64_t wrap64(int64_t x, int64_t n) {
+  int64_t r = x % n;
+  return r < 0 ? r + n : r;
+}
+
+// Sum over the 64 lanes of a wavefront (every lane returns the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kLanes);
+  return v;
+}
+
+// Kernel arguments shared by the fused step kernels.
+template <typename T>
+struct StepArgs {
+  const cx<T>* __restrict__ in;
+  cx<T>* __restrict__ out;
+  const InstDesc* __restrict__ inst;
+  const int32_t* __restrict__ tile2inst;
+  double* __restrict__ ovpart;   // [ntiles][2] overlap partials (written when overlap != 0)
+  Angles<T> ang;                 // interleaved U^{1/(4d)}: theta = eps^2 / (4 d)
+  Angles<T> ang_full;            // plain split: theta = eps^2
+  int32_t ntiles;
+  int32_t steps;                 // 1D: steps fused in this pass
+  int32_t tile_rows;             // 2D: rows per streaming tile
+  int32_t plain;                 // 1: plain split, 0: interleaved
+  int32_t overlap;               // 1: record <psi_t|psi_{t-1}> of the last step
+};
+
+// ---------------------------------------------------------------------------
+// 1D fused step: `steps` steps per pass, 4*steps halo sites on each side
+// ---------------------------------------------------------------------------
+// Substep k = 0..3 of a 1D step is [U] I'_{x,q} with q = b, b, a, a (Sec. VII:
+// psi(t+tau) = I'_1 U I'_1 U I'_2 U I'_2 U psi(t), rightmost first); the plain
+// split applies one U with theta = eps^2 before the first I' only.
+template <typename T>
+__global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= A.ntiles) return;   // whole wavefronts only; no block-level synchronisation below
+  const int lane = threadIdx.x & (kLanes - 1);
+  const InstDesc d = A.inst[A.tile2inst[w]];
+  const int H = 4 * A.steps;
+  const int TV = kLanes - 2 * H;
+  const int64_t L = d.nx;
+  const int64_t x = (int64_t)(w - d.tile_begin) * TV - H + lane;
+  const int64_t xw = wrap64(x, L);
+  const cx<T>* src = A.in + d.off + xw;
+  cx<T> a[5], b[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[m] = src[m * d.stride];
+    b[m] = src[(5 + m) * d.stride];
+  }
+  const bool plain = A.plain != 0;
+  const Angles<T> an{plain ? A.ang_full.tg0 : A.ang.tg0, plain ? A.ang_full.tg1 : A.ang.tg1,
+                     plain ? A.ang_full.tg25 : A.ang.tg25};
+  cx<T> pold[5];
+  const int nsub = 4 * A.steps;
+#pragma unroll 1
+  for (int k = 0; k < nsub; ++k) {
+    const int sub = k & 3;
+    if (A.overlap && k == nsub - 4) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) pold[m] = a[m] + b[m];
+    }
+    if (!plain || sub == 0) potential(a, b, an);
+    iprime_lanes(a, b, sub < 2);
+  }
+  const bool valid = lane >= H && lane < kLanes - H && x < L;
+  if (valid) {
+    cx<T>* dst = A.out + d.off + x;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      dst[m * d.stride] = a[m];
+      dst[(5 + m) * d.stride] = b[m];
+    }
+  }
+  if (A.overlap) {
+    double ore = 0.0, oim = 0.0;
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const cx<T> c = cmulc(a[m] + b[m], pold[m]);   // conj(psi_t) psi_{t-1}
+        ore += (double)c.re;
+        oim += (double)c.im;
+      }
+    }
+    ore = wave_sum(ore);
+    oim = wave_sum(oim);
+    if (lane == 0) {
+      A.ovpart[2 * w] = ore;
+      A.ovpart[2 * w + 1] = oim;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2D fused step: y half as a 4-stage register pipeline along rows, x half across lanes
+// ---------------------------------------------------------------------------
+// Stage k of the y half is [U] I'_{y,q}, q = b, b, a, a.  The streaming row
+// enters stage k as row r of the stage input and leaves as row r - 1 of its
+// output.  Each stage keeps two pending 5-vectors per lane:
+//   cn: the non-moving qubit of C(input) at row r - 1,
+//   mq: the moving qubit after the second collide at row r - 2.
+template <typename T>
+__device__ __forceinline__ void y_stage_core(cx<T> (&a)[5], cx<T> (&b)[5], cx<T> (&cn)[5], cx<T> (&mq)[5],
+                                             bool qb) {
+  collide2(a, b);                     // c(r)
+  cx<T> ta[5], tb[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {       // t(r-1) = (c(r-1).nonq, c(r).q)   [S^T: q(y) <- q(y+1)]
+    const cx<T> keep = sel(qb, a[m], b[m]);
+    ta[m] = sel(qb, cn[m], a[m]);
+    tb[m] = sel(qb, b[m], cn[m]);
+    cn[m] = keep;
+  }
+  collide2(ta, tb);                   // m(r-1)
+  scale_quarter(ta, tb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {       // out(r-1) = (m(r-1).nonq, m(r-2).q)  [S: q(y) <- q(y-1)]
+    const cx<T> moved = sel(qb, tb[m], ta[m]);
+    a[m] = sel(qb, ta[m], mq[m]);
+    b[m] = sel(qb, mq[m], tb[m]);
+    mq[m] = moved;
+  }
+}
+
+// LDS words per wavefront for the y pipeline: 4 stages x (cn[5], mq[5]) x 64 lanes.
+constexpr int kStageSlots = 4 * 10;
+constexpr int k2DWaves = 2;   // wavefronts per workgroup of the 2D kernel
+
+template <typename T>
+__global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
+  // Per-lane pipeline buffers live in LDS; every lane reads back only the
+  // slots it wrote itself, so no barrier is needed anywhere in the kernel.
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int wv = threadIdx.x >> 6;
+  const int w = blockIdx.x * k2DWaves + wv;
+  if (w >= A.ntiles) return;
+  const int lane = threadIdx.x & (kLanes - 1);
+  cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStageSlots * kLanes) + lane;
+  const InstDesc d = A.inst[A.tile2inst[w]];
+  const int t = w - d.tile_begin;
+  const int tx = t % d.ntx, ty = t / d.ntx;
+  const int nx = d.nx, ny = d.ny;
+  const int x = tx * kValid2D - kHalo2D + lane;
+  const int xw = (int)wrap64(x, nx);
+  const int y0 = ty * A.tile_rows;
+  const bool xvalid = lane >= kHalo2D && lane < kLanes - kHalo2D && x < nx;
+  const bool plain = A.plain != 0;
+  const Angles<T> an{plain ? A.ang_full.tg0 : A.ang.tg0, plain ? A.ang_full.tg1 : A.ang.tg1,
+                     plain ? A.ang_full.tg25 : A.ang.tg25};
+#pragma unroll
+  for (int j = 0; j < kStageSlots; ++j) my[j * kLanes] = cx<T>{T(0), T(0)};
+
+  double ore = 0.0, oim = 0.0;
+  const int nrows = A.tile_rows + 8;
+#pragma unroll 1
+  for (int r = 0; r < nrows; ++r) {
+    const int yw = (int)wrap64(y0 - 4 + r, ny);
+    const cx<T>* src = A.in + d.off + (int64_t)yw * nx + xw;
+    cx<T> a[5], b[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      a[m] = src[m * d.stride];
+      b[m] = src[(5 + m) * d.stride];
+    }
+    // substeps 0..3: y stages (b, b, a, a); 4..7: x half (b, b, a, a).  Rows that
+    // leave the y pipeline before r = 8 are incomplete and skip the x half.
+    const int nsub = r < 8 ? 4 : 8;
+#pragma unroll 1
+    for (int k = 0; k < nsub; ++k) {
+      if (!plain || k == 0) potential(a, b, an);
+      if (k < 4) {
+        cx<T>* slot = my + k * 10 * kLanes;
+        cx<T> cn[5], mq[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          cn[m] = slot[m * kLanes];
+          mq[m] = slot[(5 + m) * kLanes];
+        }
+        y_stage_core(a, b, cn, mq, k < 2);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          slot[m * kLanes] = cn[m];
+          slot[(5 + m) * kLanes] = mq[m];
+        }
+      } else {
+        iprime_lanes(a, b, k < 6);
+      }
+    }
+    if (r < 8) continue;
+    const int yo = y0 - 8 + r;           // row leaving the pipeline
+    if (xvalid && yo < ny) {
+      const int64_t o = d.off + (int64_t)yo * nx + x;
+      cx<T>* dst = A.out + o;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        dst[m * d.stride] = a[m];
+        dst[(5 + m) * d.stride] = b[m];
+      }
+      if (A.overlap) {
+        const cx<T>* old = A.in + o;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const cx<T> po = old[m * d.stride] + old[(5 + m) * d.stride];
+          const cx<T> c = cmulc(a[m] + b[m], po);
+          ore += (double)c.re;
+          oim += (double)c.im;
+        }
+      }
+    }
+  }
+  if (A.overlap) {
+    ore = wave_sum(ore);
+    oim = wave_sum(oim);
+    if (lane == 0) {
+      A.ovpart[2 * w] = ore;
+      A.ovpart[2 * w + 1] = oim;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise layout kernels (one thread per site, 256-site chunks per instance)
+// ---------------------------------------------------------------------------
+struct SiteRef {
+  InstDesc d;
+  int s;
+  bool ok;
+};
+
+__device__ __forceinline__ SiteRef site_of(const LaunchGeom& g) {
+  SiteRef r;
+  const int c = blockIdx.x;
+  r.d = g.inst[g.chunk2inst[c]];
+  r.s = (c - r.d.chunk_begin) * kChunk + threadIdx.x;
+  r.ok = r.s < r.d.sites;
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_set_psi(const cx<T>* __restrict__ psi, cx<T>* __restrict__ st,
+                                                   LaunchGeom g) {
+  const SiteRef r = site_of(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> v = T(0.5) * psi[r.d.psi_off + (int64_t)m * r.d.sites + r.s];
+    st[r.d.off + m * r.d.stride + r.s] = v;
+    st[r.d.off + (5 + m) * r.d.stride + r.s] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_get_psi(const cx<T>* __restrict__ st, cx<T>* __restrict__ psi,
+                                                   LaunchGeom g) {
+  const SiteRef r = site_of(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+    psi[r.d.psi_off + (int64_t)m * r.d.sites + r.s] =
+        st[r.d.off + m * r.d.stride + r.s] + st[r.d.off + (5 + m) * r.d.stride + r.s];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_set_qubits(const cx<T>* __restrict__ qb, cx<T>* __restrict__ st,
+                                                      LaunchGeom g) {
+  const SiteRef r = site_of(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int p = 0; p < 10; ++p)
+    st[r.d.off + p * r.d.stride + r.s] = qb[r.d.qb_off + (int64_t)p * r.d.sites + r.s];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_get_qubits(const cx<T>* __restrict__ st, cx<T>* __restrict__ qb,
+                                                      LaunchGeom g) {
+  const SiteRef r = site_of(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int p = 0; p < 10; ++p)
+    qb[r.d.qb_off + (int64_t)p * r.d.sites + r.s] = st[r.d.off + p * r.d.stride + r.s];
+}
+
+// ---------------------------------------------------------------------------
+// Observables: per-chunk partial sums (FP64), then per-instance sums
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum_store(double (&v)[kNObs], double* __restrict__ dst) {
+  __shared__ double red[kNObs][kChunk / kLanes];
+  const int lane = threadIdx.x & (kLanes - 1), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kNObs; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNObs) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kChunk / kLanes; ++j) s += red[threadIdx.x][j];
+    dst[threadIdx.x] = s;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_psi_d(const cx<T>* __restrict__ st, const InstDesc& d, int s,
+                                           double (&pr)[5], double (&pi)[5], double* nq) {
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> a = st[d.off + m * d.stride + s];
+    const cx<T> b = st[d.off + (5 + m) * d.stride + s];
+    acc += (double)a.re * a.re + (double)a.im * a.im + (double)b.re * b.re + (double)b.im * b.im;
+    pr[m] = (double)a.re + (double)b.re;
+    pi[m] = (double)a.im + (double)b.im;
+  }
+  if (nq) *nq = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict__ st, LaunchGeom g, int ndim,
+                                                       double g0, double g1, double g2,
+                                                       double* __restrict__ part) {
+  const SiteRef r = site_of(g);
+  double v[kNObs];
+#pragma unroll
+  for (int k = 0; k < kNObs; ++k) v[k] = 0.0;
+  if (r.ok) {
+    const InstDesc& d = r.d;
+    double pr[5], pi[5], nq;
+    load_psi_d(st, d, r.s, pr, pi, &nq);
+    const int x = r.s % d.nx, y = r.s / d.nx;
+    double q[5], n = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      q[m] = pr[m] * pr[m] + pi[m] * pi[m];
+      n += q[m];
+    }
+    v[0] = nq;
+    v[1] = n;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) v[2 + m] = q[m];
+    // kinetic: forward differences along x (and y), periodic
+    double ek = 0.0;
+    {
+      double nr[5], ni[5];
+      const int sx = y * d.nx + (x + 1 == d.nx ? 0 : x + 1);
+      load_psi_d<T>(st, d, sx, nr, ni, nullptr);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double dr = nr[m] - pr[m], di = ni[m] - pi[m];
+        ek += dr * dr + di * di;
+      }
+    }
+    if (ndim == 2) {
+      double nr[5], ni[5];
+      const int sy = (y + 1 == d.ny ? 0 : y + 1) * d.nx + x;
+      load_psi_d<T>(st, d, sy, nr, ni, nullptr);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double dr = nr[m] - pr[m], di = ni[m] - pi[m];
+        ek += dr * dr + di * di;
+      }
+    }
+    v[7] = ek;
+    // interaction energy density (g0 n^2 + g1 |F|^2 + g2 |sigma|^2 / 5) / 2
+    const double r6 = Consts::r6;
+    const double Fz = 2.0 * (q[0] - q[4]) + (q[1] - q[3]);
+    // F_x + i F_y = 2 p2* p1 + sqrt6 p1* p0 + sqrt6 p0* p-1 + 2 p-1* p-2
+    auto cre = [&](int i, int j) { return pr[i] * pr[j] + pi[i] * pi[j]; };
+    auto cim = [&](int i, int j) { return pr[i] * pi[j] - pi[i] * pr[j]; };
+    const double Fx = 2.0 * (cre(0, 1) + cre(3, 4)) + r6 * (cre(1, 2) + cre(2, 3));
+    const double Fy = 2.0 * (cim(0, 1) + cim(3, 4)) + r6 * (cim(1, 2) + cim(2, 3));
+    // sigma = 2 p2 p-2 - 2 p1 p-1 + p0^2
+    const double sr = 2.0 * (pr[0] * pr[4] - pi[0] * pi[4]) - 2.0 * (pr[1] * pr[3] - pi[1] * pi[3]) +
+                      (pr[2] * pr[2] - pi[2] * pi[2]);
+    const double si = 2.0 * (pr[0] * pi[4] + pi[0] * pr[4]) - 2.0 * (pr[1] * pi[3] + pi[1] * pr[3]) +
+                      2.0 * pr[2] * pi[2];
+    v[8] = 0.5 * (g0 * n * n + g1 * (Fx * Fx + Fy * Fy + Fz * Fz) + g2 * (sr * sr + si * si) / 5.0);
+  }
+  block_sum_store(v, part + (int64_t)blockIdx.x * kNObs);
+}
+
+// One block per instance: sum its chunk partials in a fixed order.
+__global__ __launch_bounds__(kChunk) void k_reduce_obs(LaunchGeom g, const double* __restrict__ part,
+                                                      double* __restrict__ res) {
+  const InstDesc d = g.inst[blockIdx.x];
+  double v[kNObs];
+#pragma unroll
+  for (int k = 0; k < kNObs; ++k) v[k] = 0.0;
+  for (int c = threadIdx.x; c < d.nchunks; c += kChunk) {
+    const double* p = part + (int64_t)(d.chunk_begin + c) * kNObs;
+#pragma unroll
+    for (int k = 0; k < kNObs; ++k) v[k] += p[k];
+  }
+  block_sum_store(v, res + (int64_t)blockIdx.x * kNObs);
+}
+
+__global__ __launch_bounds__(kChunk) void k_reduce_ov(LaunchGeom g, const double* __restrict__ ovpart,
+                                                     double* __restrict__ res) {
+  const InstDesc d = g.inst[blockIdx.x];
+  double v[kNObs];
+#pragma unroll
+  for (int k = 0; k < kNObs; ++k) v[k] = 0.0;
+  const int nt = d.ntx * d.nty;
+  for (int t = threadIdx.x; t < nt; t += kChunk) {
+    v[0] += ovpart[2 * (d.tile_begin + t)];
+    v[1] += ovpart[2 * (d.tile_begin + t) + 1];
+  }
+  __shared__ double tmp[kNObs];
+  double* dst = tmp;
+  block_sum_store(v, dst);
+  __syncthreads();
+  if (threadIdx.x < 2) res[2 * blockIdx.x + threadIdx.x] = tmp[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+static Angles<T> angles(double a, double b, double c) {
+  return Angles<T>{T(a), T(b), T(c)};
+}
+
+template <typename T>
+static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, double tg0, double tg1,
+                             double tg25, double full_factor, double* ovpart, int steps, int rows,
+                             bool plain, bool overlap) {
+  StepArgs<T> A;
+  A.in = (const cx<T>*)in;
+  A.out = (cx<T>*)out;
+  A.inst = g.inst;
+  A.tile2inst = g.tile2inst;
+  A.ovpart = ovpart;
+  A.ang = angles<T>(tg0, tg1, tg25);
+  A.ang_full = angles<T>(full_factor * tg0, full_factor * tg1, full_factor * tg25);
+  A.ntiles = g.ntiles;
+  A.steps = steps;
+  A.tile_rows = rows;
+  A.plain = plain ? 1 : 0;
+  A.overlap = overlap ? 1 : 0;
+  return A;
+}
+
+hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
+                         hipStream_t st) {
+  if (g.ntiles == 0) return hipSuccess;
+  if (steps < 1 || 8 * steps >= kLanes) return hipErrorInvalidValue;
+  const dim3 grid((g.ntiles + 3) / 4), block(256);
+  // the plain split's single U uses theta = eps^2 = 4x the interleaved 1D angle
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_step1d<float>, grid, block, 0, st,
+                       step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+  else
+    hipLaunchKernelGGL(k_step1d<double>, grid, block, 0, st,
+                       step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+  return hipGetLastError();
+}
+
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
+                         hipStream_t st) {
+  if (g.ntiles == 0) return hipSuccess;
+  if (tile_rows < 1) return hipErrorInvalidValue;
+  const dim3 grid((g.ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
+  // 2D interleaved angles are eps^2/8; the plain split's single U uses eps^2 = 8x
+  if (dtype == 0) {
+    const size_t lds = sizeof(cx<float>) * kStageSlots * kLanes * k2DWaves;
+    hipLaunchKernelGGL(k_step2d<float>, grid, block, lds, st,
+                       step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+  } else {
+    const size_t lds = sizeof(cx<double>) * kStageSlots * kLanes * k2DWaves;
+    hipLaunchKernelGGL(k_step2d<double>, grid, block, lds, st,
+                       step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+  }
+  return hipGetLastError();
+}
+
+#define QLG_ELEMWISE(NAME, KERNEL, SRC_T, DST_T)                                                    \
+  hipError_t NAME(int dtype, SRC_T src, DST_T dst, const LaunchGeom& g, hipStream_t st) {           \
+    if (g.nchunks == 0) return hipSuccess;                                                          \
+    if (dtype == 0)                                                                                 \
+      hipLaunchKernelGGL(KERNEL<float>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<float>*)src, \
+                         (cx<float>*)dst, g);                                                       \
+    else                                                                                            \
+      hipLaunchKernelGGL(KERNEL<double>, dim3(g.nchunks), dim3(kChunk), 0, st,                      \
+                         (const cx<double>*)src, (cx<double>*)dst, g);                              \
+    return hipGetLastError();                                                                       \
+  }
+
+QLG_ELEMWISE(launch_set_psi, k_set_psi, const void*, void*)
+QLG_ELEMWISE(launch_get_psi, k_get_psi, const void*, void*)
+QLG_ELEMWISE(launch_set_qubits, k_set_qubits, const void*, void*)
+QLG_ELEMWISE(launch_get_qubits, k_get_qubits, const void*, void*)
+
+hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
+                              double g1, double g2, double* part, double* res, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_observables<float>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<float>*)state,
+                       g, ndim, g0, g1, g2, part);
+  else
+    hipLaunchKernelGGL(k_observables<double>, dim3(g.nchunks), dim3(kChunk), 0, st,
+                       (const cx<double>*)state, g, ndim, g0, g1, g2, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_obs, dim3(g.nbatch), dim3(kChunk), 0, st, g, (const double*)part, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap_reduce(const LaunchGeom& g, const double* ovpart, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_ov, dim3(g.nbatch), dim3(kChunk), 0, st, g, ovpart, res);
+  return hipGetLastError();
+}
+
+}  // namespace qlg

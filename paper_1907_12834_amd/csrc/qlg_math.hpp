@@ -1,0 +1,259 @@
+// Per-site arithmetic of the spin-2 QLG step: collide and the self-interaction U.
+//
+// Everything here is __host__ __device__ so that the same code can be
+// exercised on the CPU (hostcheck.cpp) before it runs on gfx950.
+//
+// Component order inside a site: index 0..4 <-> m_f = 2, 1, 0, -1, -2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#define QLG_HD __host__ __device__ __forceinline__
+
+namespace qlg {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T> QLG_HD cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> QLG_HD cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> QLG_HD cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> QLG_HD cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> QLG_HD cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> QLG_HD cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T> QLG_HD cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// acc + a * b
+template <typename T> QLG_HD cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+  return {acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re};
+}
+// c ? x : y, component-wise (a select of values, never of addresses)
+template <typename T> QLG_HD cx<T> sel(bool c, cx<T> x, cx<T> y) {
+  return {c ? x.re : y.re, c ? x.im : y.im};
+}
+// acc + s * a (s real)
+template <typename T> QLG_HD cx<T> rfma(T s, cx<T> a, cx<T> acc) {
+  return {acc.re + s * a.re, acc.im + s * a.im};
+}
+
+QLG_HD void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+QLG_HD void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+QLG_HD float sqrt_t(float x) { return sqrtf(x); }
+QLG_HD double sqrt_t(double x) { return sqrt(x); }
+
+// Angles of one application of U(theta): theta*g0, theta*g1, theta*g2/5.
+template <typename T>
+struct Angles {
+  T tg0, tg1, tg25;
+};
+
+// ---------------------------------------------------------------------------
+// Collide (sqrt SWAP on each (a_m, b_m) pair), without its factor 1/2:
+//   2 a' = (a + b) - i (a - b),   2 b' = (a + b) + i (a - b).
+// Two collides and one exact multiplication by 1/4 give C C exactly as the
+// scaled form would (scaling by powers of two commutes with rounding).
+// ---------------------------------------------------------------------------
+template <typename T>
+QLG_HD void collide2(cx<T> (&a)[5], cx<T> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const T sr = a[m].re + b[m].re, si = a[m].im + b[m].im;
+    const T dr = a[m].re - b[m].re, di = a[m].im - b[m].im;
+    a[m] = cx<T>{sr + di, si - dr};
+    b[m] = cx<T>{sr - di, si + dr};
+  }
+}
+
+template <typename T>
+QLG_HD void scale_quarter(cx<T> (&a)[5], cx<T> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[m] = T(0.25) * a[m];
+    b[m] = T(0.25) * b[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Frozen-field self-interaction U(theta) applied to x = a and x = b:
+//   x <- exp(-i th g0 n) R P x,
+//   P = I + (exp(-i th g2 n/5) - 1) v v^H / n,   v_m = (-1)^m conj(psi_{-m}),
+//   R = exp(-i th g1 F.f) = Phi d(beta) diag(exp(-i phi k)) d(beta)^T Phi^*,
+// with psi = a + b, n = |psi|^2, F_nu = psi^H f_nu psi, phi = th g1 |F|,
+// F = |F| (sin b cos al, sin b sin al, cos b), Phi = diag(exp(-i al m)) and
+// d(beta) the real spin-2 rotation exp(-i beta f_y).
+//
+// Every factor is applied as "identity + small correction": the corrections
+// use e^{-i x} - 1 = -2 sin^2(x/2) - 2i sin(x/2) cos(x/2), so the part of the
+// state that the identity carries is never rounded and the norm error per
+// application is second order in the phase angles.
+// ---------------------------------------------------------------------------
+struct Consts {
+  static constexpr double r6 = 2.449489742783178098197284;    // sqrt(6)
+  static constexpr double r32 = 1.224744871391589049098642;   // sqrt(3/2)
+  static constexpr double r38 = 0.6123724356957945245493210;  // sqrt(3/8)
+};
+
+// Coefficients of W for one site, computed once and applied to a and to b.
+template <typename T>
+struct WCoef {
+  cx<T> p[5];                                  // psi = a + b
+  cx<T> cs;                                    // (exp(-i th g2 n/5) - 1) / n (0/0 -> -i th g2/5)
+  cx<T> dl[5];                                 // exp(-i (th g0 n + k phi)) - 1, k = 2..-2
+  cx<T> u, u2;                                 // e^{i alpha}, e^{2 i alpha}
+  T d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;   // d^2_{m'm}(beta), m' >= |m|
+};
+
+template <typename T>
+QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angles<T> ang, WCoef<T>& W) {
+  const T r6 = T(Consts::r6), r32 = T(Consts::r32), r38 = T(Consts::r38);
+  T q[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    W.p[m] = a[m] + b[m];
+    q[m] = W.p[m].re * W.p[m].re + W.p[m].im * W.p[m].im;
+  }
+  const T n = q[0] + q[1] + q[2] + q[3] + q[4];
+  const T Fz = T(2) * (q[0] - q[4]) + (q[1] - q[3]);
+  // F_x + i F_y = psi^H f_+ psi = 2 p2* p1 + sqrt6 p1* p0 + sqrt6 p0* p-1 + 2 p-1* p-2
+  const cx<T> f1 = cmulc(W.p[0], W.p[1]) + cmulc(W.p[3], W.p[4]);
+  const cx<T> f2 = cmulc(W.p[1], W.p[2]) + cmulc(W.p[2], W.p[3]);
+  const T Fx = T(2) * f1.re + r6 * f2.re;
+  const T Fy = T(2) * f1.im + r6 * f2.im;
+  const T Fp2 = Fx * Fx + Fy * Fy;
+  const T Fn = sqrt_t(Fp2 + Fz * Fz);
+  const T Fperp = sqrt_t(Fp2);
+
+  // half-angle phases: mu = exp(-i x) - 1 = -2 sin(x/2) (sin(x/2) + i cos(x/2))
+  T s0, c0, s1, c1, s2, c2;
+  const T h2 = T(0.5) * ang.tg25 * n;
+  sincos_t(T(0.5) * ang.tg0 * n, &s0, &c0);
+  sincos_t(T(0.5) * ang.tg1 * Fn, &s1, &c1);
+  sincos_t(h2, &s2, &c2);
+  const cx<T> mu0{T(-2) * s0 * s0, T(-2) * s0 * c0};
+  const cx<T> mu1{T(-2) * s1 * s1, T(-2) * s1 * c1};
+  // nu_k = exp(-i k phi) - 1 for k = 2, 1, -1, -2
+  const cx<T> nu2 = T(2) * mu1 + mu1 * mu1;
+  const cx<T> mu1c = conj(mu1), nu2c = conj(nu2);
+  // E_k - 1 = exp(-i (phi0 + k phi)) - 1 = mu0 + nu_k + mu0 nu_k
+  W.dl[0] = mu0 + nu2 + mu0 * nu2;
+  W.dl[1] = mu0 + mu1 + mu0 * mu1;
+  W.dl[2] = mu0;
+  W.dl[3] = mu0 + mu1c + mu0 * mu1c;
+  W.dl[4] = mu0 + nu2c + mu0 * nu2c;
+
+  // singlet coefficient (exp(-i th g2 n/5) - 1) / n = th g2/5 * sinc(h) * (-sin h - i cos h),
+  // h = th g2 n / 10: no division by n, so empty or denormal sites stay finite
+  const T sinc = fabs(h2) < T(1e-4) ? T(1) - h2 * h2 * T(1.0 / 6.0) : s2 / h2;
+  W.cs = cx<T>{-ang.tg25 * sinc * s2, -ang.tg25 * sinc * c2};
+
+  // frame of F: u = e^{i alpha}, cos beta, sin beta, 1 +- cos beta without cancellation.
+  // Below `tiny` the direction is immaterial (phi ~ 0) and F is taken along z.
+  const T tiny = sizeof(T) == 4 ? T(1e-30) : T(1e-280);
+  cx<T> u{T(1), T(0)};
+  T cb = T(1), sb = T(0), opc = T(2), omc = T(0);
+  if (Fperp > tiny) {
+    const T ip = T(1) / Fperp;
+    u = cx<T>{Fx * ip, Fy * ip};
+  }
+  if (Fn > tiny) {
+    const T iF = T(1) / Fn;
+    cb = Fz * iF;
+    sb = Fperp * iF;
+    if (Fz >= T(0)) {
+      const T A = Fn + Fz;           // |F| (1 + cos beta)
+      opc = A * iF;
+      omc = Fp2 / A * iF;            // |F|(1 - cos beta) = F_perp^2 / (|F| + F_z)
+    } else {
+      const T B = Fn - Fz;
+      omc = B * iF;
+      opc = Fp2 / B * iF;
+    }
+  }
+  W.u = u;
+  W.u2 = u * u;
+  // spin-2 Wigner small-d entries d_{m'm}(beta) for m' >= |m| (the rest by symmetry)
+  W.d22 = T(0.25) * opc * opc;
+  W.d21 = T(-0.5) * sb * opc;
+  W.d20 = r38 * sb * sb;
+  W.d2m1 = T(-0.5) * sb * omc;
+  W.d2m2 = T(0.25) * omc * omc;
+  W.d11 = T(0.5) * opc * (T(2) * cb - T(1));
+  W.d10 = -r32 * sb * cb;
+  W.d1m1 = T(0.5) * omc * (T(2) * cb + T(1));
+  W.d00 = T(0.5) * (T(3) * cb * cb - T(1));
+}
+
+// x <- exp(-i th g0 n) R P x for one 5-vector x (a or b).
+template <typename T>
+QLG_HD void w_apply(cx<T> (&x)[5], const WCoef<T>& W) {
+  // full d matrix D[row m'][col m], rows/cols ordered m = 2..-2, from
+  // d_{m'm} = (-1)^{m-m'} d_{mm'} = d_{-m,-m'}
+  const T D[5][5] = {
+      {W.d22, W.d21, W.d20, W.d2m1, W.d2m2},
+      {-W.d21, W.d11, W.d10, W.d1m1, W.d2m1},
+      {W.d20, -W.d10, W.d00, W.d10, W.d20},
+      {-W.d2m1, W.d1m1, -W.d10, W.d11, W.d21},
+      {W.d2m2, -W.d2m1, W.d20, -W.d21, W.d22},
+  };
+  const cx<T> uc = conj(W.u), u2c = conj(W.u2);
+  // singlet factor: y = x + cs (v^H x) v, conj(v_m) = (-1)^m psi_{-m}, v_m = (-1)^m conj(psi_{-m})
+  cx<T> s = W.p[4] * x[0];
+  s = cfma(T(-1) * W.p[3], x[1], s);
+  s = cfma(W.p[2], x[2], s);
+  s = cfma(T(-1) * W.p[1], x[3], s);
+  s = cfma(W.p[0], x[4], s);
+  const cx<T> tt = W.cs * s;
+  cx<T> y[5];
+  y[0] = cfma(tt, conj(W.p[4]), x[0]);
+  y[1] = cfma(tt, T(-1) * conj(W.p[3]), x[1]);
+  y[2] = cfma(tt, conj(W.p[2]), x[2]);
+  y[3] = cfma(tt, T(-1) * conj(W.p[1]), x[3]);
+  y[4] = cfma(tt, conj(W.p[0]), x[4]);
+  // w = Phi^* y
+  cx<T> w[5];
+  w[0] = y[0] * W.u2;
+  w[1] = y[1] * W.u;
+  w[2] = y[2];
+  w[3] = y[3] * uc;
+  w[4] = y[4] * u2c;
+  // z = (Lambda' - I) d^T w
+  cx<T> z[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    cx<T> acc = D[0][k] * w[0];
+#pragma unroll
+    for (int m = 1; m < 5; ++m) acc = rfma(D[m][k], w[m], acc);
+    z[k] = W.dl[k] * acc;
+  }
+  // t = d z; x = y + Phi t
+  cx<T> t5[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    cx<T> acc = D[m][0] * z[0];
+#pragma unroll
+    for (int k = 1; k < 5; ++k) acc = rfma(D[m][k], z[k], acc);
+    t5[m] = acc;
+  }
+  x[0] = cfma(t5[0], u2c, y[0]);
+  x[1] = cfma(t5[1], uc, y[1]);
+  x[2] = y[2] + t5[2];
+  x[3] = cfma(t5[3], W.u, y[3]);
+  x[4] = cfma(t5[4], W.u2, y[4]);
+}
+
+template <typename T>
+QLG_HD void potential(cx<T> (&a)[5], cx<T> (&b)[5], const Angles<T> ang) {
+  WCoef<T> W;
+  w_coefficients(a, b, ang, W);
+  w_apply(a, W);
+  w_apply(b, W);
+}
+
+}  // namespace qlg

@@ -1,0 +1,289 @@
+"""ctypes binding of libqlg (include/qlg.h).
+
+This module only marshals arguments: every step of the QLG path runs in the
+HIP kernels of libqlg.so.  PyTorch provides device memory and the stream.
+There is no CPU fallback; if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqlg.so")
+
+QLG_OK = 0
+STATUS_NAMES = {0: "QLG_OK", 1: "QLG_ERR_ARG", 2: "QLG_ERR_SHAPE", 3: "QLG_ERR_DTYPE",
+                4: "QLG_ERR_DEVICE", 5: "QLG_ERR_OOM", 6: "QLG_ERR_STATE", 7: "QLG_ERR_NUMERIC"}
+C64, C128 = 0, 1
+INTERLEAVED, PLAIN = 0, 1
+
+# every symbol declared in include/qlg.h
+EXPORTED = [
+    "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
+    "qlg_get_qubits", "qlg_step", "qlg_observables", "qlg_set_tuning", "qlg_get_tuning",
+    "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
+    "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
+    "qlg_last_error", "qlg_destroy",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("nbatch", ctypes.c_int32), ("nx", ctypes.POINTER(ctypes.c_int64)),
+                ("ny", ctypes.POINTER(ctypes.c_int64)), ("g0", ctypes.c_double),
+                ("g1", ctypes.c_double), ("g2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("norm_q", ctypes.c_double), ("norm_psi", ctypes.c_double),
+                ("pop", ctypes.c_double * 5), ("energy", ctypes.c_double),
+                ("overlap_re", ctypes.c_double), ("overlap_im", ctypes.c_double),
+                ("e_overlap_re", ctypes.c_double), ("e_overlap_im", ctypes.c_double),
+                ("step", ctypes.c_int64), ("has_overlap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {"norm_q": self.norm_q, "norm_psi": self.norm_psi, "pop": list(self.pop),
+             "energy": self.energy, "step": int(self.step)}
+        if self.has_overlap:
+            d["overlap"] = complex(self.overlap_re, self.overlap_im)
+            d["e_overlap"] = complex(self.e_overlap_re, self.e_overlap_im)
+        return d
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("steps_per_pass", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class QLGError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__("%s failed with %s%s" % (where, STATUS_NAMES.get(status, status),
+                                                 (": " + detail) if detail else ""))
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("libqlg.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_1907_12834_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    P, vp, sz = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "qlg_version": (i32, []),
+        "qlg_query_sizes": (i32, [P(Params), P(sz), P(sz)]),
+        "qlg_init": (i32, [P(Params), vp, sz, vp, sz, vp, P(vp)]),
+        "qlg_set_psi": (i32, [vp, vp]),
+        "qlg_get_psi": (i32, [vp, vp]),
+        "qlg_set_qubits": (i32, [vp, vp]),
+        "qlg_get_qubits": (i32, [vp, vp]),
+        "qlg_step": (i32, [vp, i64]),
+        "qlg_observables": (i32, [vp, P(Obs)]),
+        "qlg_set_tuning": (i32, [vp, P(Tuning)]),
+        "qlg_get_tuning": (i32, [vp, P(Tuning)]),
+        "qlg_autotune": (i32, [vp]),
+        "qlg_set_timing": (i32, [vp, i32]),
+        "qlg_last_kernel_ms": (i32, [vp, P(dbl), P(i64)]),
+        "qlg_adjoint_query": (i32, [P(Params), i64, i32, P(sz), P(sz)]),
+        "qlg_forward_record": (i32, [vp, i64, i32, vp, sz]),
+        "qlg_objective_grad": (i32, [vp, i32, vp, vp, P(dbl), P(dbl)]),
+        "qlg_adjoint_step": (i32, [vp, i64, i32, vp, vp, vp, sz, P(dbl)]),
+        "qlg_status_string": (ctypes.c_char_p, [i32]),
+        "qlg_last_error": (ctypes.c_char_p, [vp]),
+        "qlg_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def make_params(ndim: int, nx: Sequence[int], ny: Optional[Sequence[int]], g, eps: float,
+                dtype: int = C128, split: int = INTERLEAVED):
+    nb = len(nx)
+    nx_arr = (ctypes.c_int64 * nb)(*[int(v) for v in nx])
+    ny_arr = (ctypes.c_int64 * nb)(*[int(v) for v in ny]) if ny is not None else None
+    p = Params(ndim, dtype, split, nb, nx_arr,
+               ctypes.cast(ny_arr, ctypes.POINTER(ctypes.c_int64)) if ny_arr is not None else None,
+               float(g[0]), float(g[1]), float(g[2]), float(eps))
+    return p, (nx_arr, ny_arr)
+
+
+def query_sizes(params: Params):
+    s, c = ctypes.c_size_t(), ctypes.c_size_t()
+    st = lib().qlg_query_sizes(ctypes.byref(params), ctypes.byref(s), ctypes.byref(c))
+    if st != QLG_OK:
+        raise QLGError(st, "qlg_query_sizes")
+    return s.value, c.value
+
+
+def _device_bytes(nbytes: int, device) -> torch.Tensor:
+    # 256-byte alignment is guaranteed by the caching allocator
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+class Lattice:
+    """One context over caller-owned (torch) device buffers.
+
+    ``psi`` arguments use the canonical layout: a complex tensor per instance
+    of shape (5, nx) in 1D or (5, ny, nx) in 2D, components ordered m = 2..-2;
+    batches are passed as lists.
+    """
+
+    def __init__(self, ndim: int, nx: Sequence[int], ny: Optional[Sequence[int]] = None,
+                 g=(1.0, -0.5, 0.5), eps: float = 0.1, dtype: str = "c128",
+                 split: str = "interleaved", device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libqlg needs a HIP device; none is visible")
+        self.ndim = ndim
+        self.nx = [int(v) for v in nx]
+        self.ny = [int(v) for v in ny] if ny is not None else [1] * len(self.nx)
+        self.g = tuple(float(v) for v in g)
+        self.eps = float(eps)
+        self.dtype_code = {"c64": C64, "c128": C128}[dtype]
+        self.torch_dtype = torch.complex64 if self.dtype_code == C64 else torch.complex128
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params, self._keep = make_params(ndim, self.nx, ny if ndim == 2 else None, self.g, self.eps,
+                                              self.dtype_code,
+                                              {"interleaved": INTERLEAVED, "plain": PLAIN}[split])
+        sb, cb = query_sizes(self.params)
+        self.state_buf = _device_bytes(sb, self.device)
+        self.scratch_buf = _device_bytes(cb, self.device)
+        ctx = ctypes.c_void_p()
+        st = lib().qlg_init(ctypes.byref(self.params), self.state_buf.data_ptr(), sb,
+                            self.scratch_buf.data_ptr(), cb, ctypes.c_void_p(self.stream.cuda_stream),
+                            ctypes.byref(ctx))
+        if st != QLG_OK:
+            raise QLGError(st, "qlg_init")
+        self.ctx = ctx
+
+    # -- helpers -------------------------------------------------------------
+    @property
+    def nbatch(self) -> int:
+        return len(self.nx)
+
+    @property
+    def sites(self) -> int:
+        return int(sum(a * b for a, b in zip(self.nx, self.ny)))
+
+    def _check(self, st: int, where: str):
+        if st != QLG_OK:
+            msg = lib().qlg_last_error(self.ctx)
+            raise QLGError(st, where, msg.decode() if msg else "")
+
+    def _shape(self, i: int):
+        return (5, self.nx[i]) if self.ndim == 1 else (5, self.ny[i], self.nx[i])
+
+    def _flat(self, fields: List, per_site: int) -> torch.Tensor:
+        parts = []
+        for i, f in enumerate(fields):
+            t = torch.as_tensor(f) if not isinstance(f, torch.Tensor) else f
+            t = t.to(device=self.device, dtype=self.torch_dtype)
+            if t.numel() != per_site * self.nx[i] * self.ny[i]:
+                raise ValueError("field %d has %d elements, expected %d" %
+                                 (i, t.numel(), per_site * self.nx[i] * self.ny[i]))
+            parts.append(t.reshape(-1))
+        return torch.cat(parts).contiguous()
+
+    def _unflat(self, flat: torch.Tensor, per_site: int):
+        out, o = [], 0
+        for i in range(self.nbatch):
+            n = per_site * self.nx[i] * self.ny[i]
+            shape = self._shape(i)
+            shape = shape if per_site == 5 else (2,) + shape
+            out.append(flat[o:o + n].reshape(shape))
+            o += n
+        return out
+
+    # -- API -----------------------------------------------------------------
+    def set_psi(self, psi):
+        fields = psi if isinstance(psi, (list, tuple)) else [psi]
+        self._psi_in = self._flat(fields, 5)
+        self._check(lib().qlg_set_psi(self.ctx, self._psi_in.data_ptr()), "qlg_set_psi")
+
+    def get_psi(self) -> List[torch.Tensor]:
+        flat = torch.empty(5 * self.sites, dtype=self.torch_dtype, device=self.device)
+        self._check(lib().qlg_get_psi(self.ctx, flat.data_ptr()), "qlg_get_psi")
+        return self._unflat(flat, 5)
+
+    def set_qubits(self, qubits):
+        """qubits: per instance a tensor (2, 5, ...) = (a, b)."""
+        fields = qubits if isinstance(qubits, (list, tuple)) else [qubits]
+        self._qb_in = self._flat(fields, 10)
+        self._check(lib().qlg_set_qubits(self.ctx, self._qb_in.data_ptr()), "qlg_set_qubits")
+
+    def get_qubits(self) -> List[torch.Tensor]:
+        flat = torch.empty(10 * self.sites, dtype=self.torch_dtype, device=self.device)
+        self._check(lib().qlg_get_qubits(self.ctx, flat.data_ptr()), "qlg_get_qubits")
+        return self._unflat(flat, 10)
+
+    def step(self, nsteps: int = 1):
+        self._check(lib().qlg_step(self.ctx, int(nsteps)), "qlg_step")
+
+    def observables(self, check: bool = True) -> List[dict]:
+        arr = (Obs * self.nbatch)()
+        st = lib().qlg_observables(self.ctx, arr)
+        if check:
+            self._check(st, "qlg_observables")
+        return [o.as_dict() for o in arr]
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().qlg_get_tuning(self.ctx, ctypes.byref(t)), "qlg_get_tuning")
+        return {"steps_per_pass": t.steps_per_pass, "tile_rows": t.tile_rows, "use_graph": t.use_graph}
+
+    def set_tuning(self, steps_per_pass: Optional[int] = None, tile_rows: Optional[int] = None,
+                   use_graph: Optional[bool] = None):
+        cur = self.tuning()
+        t = Tuning(steps_per_pass if steps_per_pass is not None else cur["steps_per_pass"],
+                   tile_rows if tile_rows is not None else cur["tile_rows"],
+                   int(use_graph) if use_graph is not None else cur["use_graph"], 0)
+        self._check(lib().qlg_set_tuning(self.ctx, ctypes.byref(t)), "qlg_set_tuning")
+
+    def autotune(self) -> dict:
+        self._check(lib().qlg_autotune(self.ctx), "qlg_autotune")
+        return self.tuning()
+
+    def set_timing(self, enable: bool):
+        self._check(lib().qlg_set_timing(self.ctx, int(bool(enable))), "qlg_set_timing")
+
+    def last_kernel_ms(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().qlg_last_kernel_ms(self.ctx, ctypes.byref(ms), ctypes.byref(n)),
+                    "qlg_last_kernel_ms")
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().qlg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_numpy_fields(tensors: List[torch.Tensor]) -> List[np.ndarray]:
+    return [t.detach().to("cpu").numpy().astype(np.complex128) for t in tensors]

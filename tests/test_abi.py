@@ -1,0 +1,94 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+symbol include/qlg.h declares, and rejects bad parameters on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qlg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qlg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1907_12834_amd import qlg
+    return qlg
+
+
+def test_header_and_binding_agree(Q):
+    assert declared_functions() == sorted(Q.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(Q):
+    lib = Q.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings(Q):
+    lib = Q.lib()
+    assert lib.qlg_version() >= 10000
+    for code, name in Q.STATUS_NAMES.items():
+        assert lib.qlg_status_string(code).decode() == name
+
+
+def _sizes(Q, **kw):
+    args = dict(ndim=1, nx=[100], ny=None, g=(1, -0.5, 0.5), eps=0.1, dtype=Q.C128, split=Q.INTERLEAVED)
+    args.update(kw)
+    p, keep = Q.make_params(args["ndim"], args["nx"], args["ny"], args["g"], args["eps"], args["dtype"],
+                            args["split"])
+    s, c = ctypes.c_size_t(), ctypes.c_size_t()
+    st = Q.lib().qlg_query_sizes(ctypes.byref(p), ctypes.byref(s), ctypes.byref(c))
+    return st, s.value, c.value
+
+
+def test_query_sizes_layout(Q):
+    st, s, c = _sizes(Q, nx=[100])
+    assert st == 0
+    # two copies x 10 planes x stride 128 (padded to 64) x 16 bytes
+    assert s == 2 * 10 * 128 * 16
+    st, s64, _ = _sizes(Q, nx=[100], dtype=Q.C64)
+    assert st == 0 and s64 == s // 2
+    st, s2, _ = _sizes(Q, ndim=2, nx=[30, 7], ny=[10, 3])
+    assert st == 0 and s2 == 2 * 10 * (320 + 64) * 16
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ndim=3), 2), (dict(ndim=0), 2), (dict(nx=[0]), 2), (dict(nx=[-5]), 2),
+    (dict(nx=[1 << 31]), 2), (dict(ndim=2, nx=[70000], ny=[70000]), 2),
+    (dict(dtype=5), 3), (dict(split=9), 1), (dict(eps=0.0), 1), (dict(eps=float("nan")), 1),
+    (dict(g=(float("inf"), 0, 0)), 1), (dict(ndim=2, nx=[4], ny=None), 1),
+])
+def test_query_sizes_rejects_bad_params(Q, kw, code):
+    st, _, _ = _sizes(Q, **kw)
+    assert st == code
+
+
+def test_init_rejects_before_any_device_call(Q):
+    lib = Q.lib()
+    p, keep = Q.make_params(1, [100], None, (1, -0.5, 0.5), 0.1)
+    ctx = ctypes.c_void_p()
+    # NULL buffers and misaligned buffers are rejected on the host
+    assert lib.qlg_init(ctypes.byref(p), None, 0, None, 0, None, ctypes.byref(ctx)) == 1
+    assert lib.qlg_init(ctypes.byref(p), ctypes.c_void_p(8), 1 << 20, ctypes.c_void_p(256), 1 << 20, None,
+                        ctypes.byref(ctx)) == 1
+    # too-small buffers
+    assert lib.qlg_init(ctypes.byref(p), ctypes.c_void_p(256), 16, ctypes.c_void_p(512), 16, None,
+                        ctypes.byref(ctx)) == 1
+    assert lib.qlg_init(None, None, 0, None, 0, None, ctypes.byref(ctx)) == 1
+    assert ctx.value is None
+    lib.qlg_destroy(None)   # NULL is allowed
+
+
+def test_null_context_calls(Q):
+    lib = Q.lib()
+    assert lib.qlg_step(None, 1) == 1
+    assert lib.qlg_get_tuning(None, None) == 1
+    assert lib.qlg_last_error(None).decode() == "NULL context"

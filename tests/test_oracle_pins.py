@@ -58,6 +58,22 @@ def t(x):
 
 
 # ---------------------------------------------------------------------------
+# The oracle's matrix exponential against scipy's (independent Pade algorithm)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("batch", [1, 2, 7])
+@pytest.mark.parametrize("scale", [1e-6, 0.005, 0.013, 0.02, 0.1, 0.7, 3.0, 40.0])
+def test_expm_matches_scipy(batch, scale):
+    rng = np.random.default_rng(int(scale * 1000) + batch)
+    H = rng.normal(size=(batch, 5, 5)) + 1j * rng.normal(size=(batch, 5, 5))
+    H = H + H.conj().transpose(0, 2, 1)
+    M = -1j * scale * H / np.abs(H).sum(-2).max()
+    got = O.expm(torch.from_numpy(M)).numpy()
+    for i in range(batch):
+        want = sl.expm(M[i])
+        assert np.abs(got[i] - want).max() < 2e-15 * max(1.0, np.abs(want).max()) * (1 + scale)
+
+
+# ---------------------------------------------------------------------------
 # P1: unitarity of every operator and norm conservation
 # ---------------------------------------------------------------------------
 def test_collide_is_sqrt_swap():
