@@ -147,7 +147,7 @@ def expm(M: torch.Tensor, max_terms: int = 18) -> torch.Tensor:
     (torch.linalg.matrix_exp was not used: for a batch of one matrix of norm
     ~0.01-0.02 it is only accurate to ~1e-12.)
     """
-    norm = float(M.abs().sum(-2).amax()) if M.numel() else 0.0
+    norm = float(M.detach().abs().sum(-2).amax()) if M.numel() else 0.0
     s = max(0, int(math.ceil(math.log2(norm / 0.5)))) if norm > 0.5 else 0
     r = norm / (2.0 ** s)
     N, term = 1, r

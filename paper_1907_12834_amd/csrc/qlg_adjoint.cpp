@@ -1,31 +1,225 @@
-// Adjoint entry points of include/qlg.h.
+// Adjoint entry points of include/qlg.h: checkpointed forward recording, the
+// objective cotangents and the reverse sweep.
+//
+// Reverse sweep over a recorded run of nsteps with a checkpoint every K steps:
+//   for each segment, last to first:
+//     recompute the segment's step states from its checkpoint (fused step kernel);
+//     for each step of the segment, last to first:
+//       recompute the inputs of the step's self-interaction substeps (per-substep kernels);
+//       for each substep k, last to first:
+//         lambda <- I'_k^H lambda          (exact inverse of the unitary kinetic factor)
+//         lambda <- (dU/dz)^H lambda       (FP64 Jacobian at the recomputed substep input)
+//   (plain split: one U with theta = eps^2 before the I' list, so only the step input is needed.)
+// dL/dg accumulates in FP64 on the device in a fixed order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "qlg_adjoint.hpp"
+#include "qlg_adjoint_kernels.hpp"
+
+namespace {
+
+struct Sizes {
+  size_t copy = 0;     // bytes of one padded state copy (forward dtype)
+  size_t lam = 0;      // bytes of one padded complex128 cotangent
+  int64_t nck = 0;     // checkpoints
+  int nsub = 4;        // substeps per step
+  size_t off_steps = 0, off_zs = 0, off_lam = 0, off_part = 0, off_acc = 0, work = 0;
+};
+
+size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
+  if (nsteps < 0 || K < 1) return QLG_ERR_ARG;
+  size_t state_bytes = 0, scratch_bytes = 0;
+  qlg_status st = qlg_query_sizes(p, &state_bytes, &scratch_bytes);
+  if (st) return st;
+  const size_t eb = p->dtype == QLG_C64 ? 8 : 16;
+  s->copy = state_bytes / 2;
+  s->lam = s->copy / eb * 16;
+  s->nck = (nsteps + K - 1) / K;
+  s->nsub = 4 * p->ndim;
+  int64_t sites = 0;
+  for (int i = 0; i < p->nbatch; ++i) sites += p->nx[i] * (p->ndim == 2 ? p->ny[i] : 1);
+  (void)sites;
+  // chunk count bound: one chunk per 256 sites per instance
+  int64_t nchunks = 0;
+  for (int i = 0; i < p->nbatch; ++i) nchunks += (p->nx[i] * (p->ndim == 2 ? p->ny[i] : 1) + 255) / 256;
+  size_t o = 0;
+  s->off_steps = o; o += up256((size_t)K * s->copy);
+  s->off_zs = o;    o += up256((size_t)s->nsub * s->copy);
+  s->off_lam = o;   o += up256(2 * s->lam);
+  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)std::max<int64_t>(nchunks, 1));
+  s->off_acc = o;   o += up256(sizeof(double) * 4);
+  s->work = o;
+  return QLG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t checkpoint_every,
                              size_t* ckpt_bytes, size_t* work_bytes) {
-  (void)params; (void)nsteps; (void)checkpoint_every; (void)ckpt_bytes; (void)work_bytes;
-  return QLG_ERR_STATE;
+  if (!ckpt_bytes || !work_bytes) return QLG_ERR_ARG;
+  Sizes s;
+  qlg_status st = sizes_for(params, nsteps, checkpoint_every, &s);
+  if (st) return st;
+  *ckpt_bytes = (size_t)s.nck * s.copy;
+  *work_bytes = s.work;
+  return QLG_OK;
 }
 
-qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every, void* ckpt_dev,
-                              size_t ckpt_bytes) {
-  (void)nsteps; (void)checkpoint_every; (void)ckpt_dev; (void)ckpt_bytes;
-  return qlg::ctx_fail(ctx, QLG_ERR_STATE, "adjoint not available in this build");
+qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t K, void* ckpt_dev, size_t ckpt_bytes) {
+  if (!ctx) return QLG_ERR_ARG;
+  if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  qlg::CtxView v = qlg::ctx_view(ctx);
+  Sizes s;
+  qlg_status st = sizes_for(v.p, nsteps, K, &s);
+  if (st) return qlg::ctx_fail(ctx, st, "bad nsteps or checkpoint_every");
+  if (s.nck > 0 && (!ckpt_dev || ckpt_bytes < (size_t)s.nck * s.copy))
+    return qlg::ctx_fail(ctx, QLG_ERR_ARG, "checkpoint buffer missing or too small");
+  for (int64_t j = 0; j < nsteps; j += K) {
+    v = qlg::ctx_view(ctx);
+    const char* cur = v.state + (size_t)v.cur * s.copy;
+    hipError_t e = hipMemcpyAsync((char*)ckpt_dev + (size_t)(j / K) * s.copy, cur, s.copy,
+                                  hipMemcpyDeviceToDevice, v.stream);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "checkpoint copy");
+    st = qlg::ctx_step(ctx, std::min<int64_t>(K, nsteps - j));
+    if (st) return st;
+  }
+  return QLG_OK;
 }
 
 qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev, void* lambda_dev,
                               double* value_host, double* dg_host) {
-  (void)kind; (void)target_dev; (void)lambda_dev; (void)value_host; (void)dg_host;
-  return qlg::ctx_fail(ctx, QLG_ERR_STATE, "adjoint not available in this build");
+  if (!ctx) return QLG_ERR_ARG;
+  if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  if (!lambda_dev || !value_host) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or value pointer is NULL");
+  if (kind != 0 && kind != 1) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "kind must be 0 (energy) or 1 (fidelity)");
+  if (kind == 1 && !target_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "fidelity needs a target");
+  const qlg::CtxView v = qlg::ctx_view(ctx);
+  const qlg_params& p = *v.p;
+  const void* cur = v.state + (size_t)v.cur * v.elems_per_copy * v.elem_bytes;
+  const int nc = v.geom.nchunks, nb = v.geom.nbatch;
+  const double meas = std::pow(p.eps, p.ndim);
+  hipError_t e;
+  if (kind == 0) {
+    e = qlg::launch_energy_grad(p.dtype, p.ndim, cur, lambda_dev, v.geom, p.eps, p.g0, p.g1, p.g2, v.part, v.stream);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "energy gradient kernel");
+    std::vector<double> part((size_t)nc * 6);
+    e = hipMemcpyAsync(part.data(), v.part, part.size() * 8, hipMemcpyDeviceToHost, v.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(v.stream);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "copy energy partials");
+    double tot[4] = {0, 0, 0, 0};
+    for (int c = 0; c < nc; ++c)
+      for (int k = 0; k < 4; ++k) tot[k] += part[(size_t)6 * c + k];
+    *value_host = tot[0];
+    if (dg_host) { dg_host[0] = tot[1]; dg_host[1] = tot[2]; dg_host[2] = tot[3]; }
+  } else {
+    e = qlg::launch_fidelity_grad(p.dtype, cur, target_dev, lambda_dev, v.geom, meas, v.part, v.res, v.stream);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "fidelity gradient kernels");
+    std::vector<double> ov((size_t)nb * 3);
+    e = hipMemcpyAsync(ov.data(), v.res, ov.size() * 8, hipMemcpyDeviceToHost, v.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(v.stream);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "copy overlaps");
+    double tot = 0.0;
+    for (int i = 0; i < nb; ++i) tot += ov[3 * i] * ov[3 * i] + ov[3 * i + 1] * ov[3 * i + 1];
+    *value_host = tot;
+    if (dg_host) { dg_host[0] = dg_host[1] = dg_host[2] = 0.0; }
+  }
+  for (double x : {*value_host})
+    if (!std::isfinite(x)) return qlg::ctx_fail(ctx, QLG_ERR_NUMERIC, "objective is not finite");
+  return QLG_OK;
 }
 
-qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every, const void* ckpt_dev,
-                            void* lambda_dev, void* work_dev, size_t work_bytes, double* dg_host) {
-  (void)nsteps; (void)checkpoint_every; (void)ckpt_dev; (void)lambda_dev; (void)work_dev; (void)work_bytes;
-  (void)dg_host;
-  return qlg::ctx_fail(ctx, QLG_ERR_STATE, "adjoint not available in this build");
+qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void* ckpt_dev, void* lambda_dev,
+                            void* work_dev, size_t work_bytes, double* dg_host) {
+  if (!ctx) return QLG_ERR_ARG;
+  if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  const qlg::CtxView v = qlg::ctx_view(ctx);
+  const qlg_params& p = *v.p;
+  Sizes s;
+  qlg_status st = sizes_for(v.p, nsteps, K, &s);
+  if (st) return qlg::ctx_fail(ctx, st, "bad nsteps or checkpoint_every");
+  if (!lambda_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda is NULL");
+  if (nsteps == 0) return QLG_OK;
+  if (!ckpt_dev || !work_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "checkpoint or work buffer is NULL");
+  if (work_bytes < s.work) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "work buffer too small");
+  if (((uintptr_t)work_dev & 255) || ((uintptr_t)ckpt_dev & 255))
+    return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
+
+  char* W = (char*)work_dev;
+  char* steps = W + s.off_steps;
+  char* zs = W + s.off_zs;                 // zs[0..nsub-2] = inputs of substeps 1..nsub-1; zs[nsub-1] = temp
+  char* lam[2] = {W + s.off_lam, W + s.off_lam + s.lam};
+  double* part = (double*)(W + s.off_part);
+  double* acc = (double*)(W + s.off_acc);
+  const qlg::LaunchGeom& g = v.geom;
+  const hipStream_t str = v.stream;
+  const int nd = p.ndim, dt = p.dtype, nsub = s.nsub;
+  const bool plain = p.split == QLG_SPLIT_PLAIN;
+  const double theta = p.eps * p.eps / (4.0 * nd);
+  const double theta_u = plain ? p.eps * p.eps : theta;
+  auto axis_of = [&](int k) { return nd == 1 ? 0 : (k < 4 ? 1 : 0); };
+  auto qb_of = [&](int k) { return (k % 4) < 2 ? 1 : 0; };
+  auto zbuf = [&](int i) { return zs + (size_t)i * s.copy; };
+
+  hipError_t e = qlg::launch_zero(acc, 4, str);
+  if (e == hipSuccess) e = qlg::launch_lam_layout(true, lambda_dev, lam[0], g, str);
+  if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint setup");
+  int lc = 0;
+  const int64_t nseg = s.nck;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t t0 = seg * K;
+    const int n_in = (int)std::min<int64_t>(K, nsteps - t0);
+    const char* ck = (const char*)ckpt_dev + (size_t)seg * s.copy;
+    auto state_at = [&](int j) -> const void* { return j == 0 ? (const void*)ck : steps + (size_t)j * s.copy; };
+    for (int j = 1; j < n_in; ++j) {
+      e = qlg::ctx_launch_step(ctx, state_at(j - 1), steps + (size_t)j * s.copy);
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+    }
+    for (int j = n_in - 1; j >= 0; --j) {
+      const void* z = state_at(j);
+      // inputs of the self-interaction substeps 1..nsub-1 (interleaved split only)
+      if (!plain) {
+        const void* in = z;
+        for (int k = 0; k + 1 < nsub; ++k) {
+          e = qlg::launch_sub_potential(dt, in, zbuf(nsub - 1), g, theta * p.g0, theta * p.g1, theta * p.g2 / 5.0,
+                                        str);
+          if (e == hipSuccess) e = qlg::launch_sub_iprime(dt, zbuf(nsub - 1), zbuf(k), g, axis_of(k), qb_of(k), str);
+          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep recompute");
+          in = zbuf(k);
+        }
+      }
+      for (int k = nsub - 1; k >= 0; --k) {
+        e = qlg::launch_sub_iprime_adj(lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), str);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint kinetic kernel");
+        lc = 1 - lc;
+        if (!plain) {
+          const void* zk = k == 0 ? z : (const void*)zbuf(k - 1);
+          e = qlg::launch_sub_vjp(dt, zk, lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
+          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
+        }
+      }
+      if (plain) {
+        e = qlg::launch_sub_vjp(dt, z, lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
+      }
+    }
+  }
+  e = qlg::launch_lam_layout(false, lam[lc], lambda_dev, g, str);
+  double hacc[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, str);
+  if (e == hipSuccess) e = hipStreamSynchronize(str);
+  if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint finish");
+  if (dg_host)
+    for (int k = 0; k < 3; ++k) dg_host[k] += hacc[k];
+  if (!std::isfinite(hacc[0]) || !std::isfinite(hacc[1]) || !std::isfinite(hacc[2]))
+    return qlg::ctx_fail(ctx, QLG_ERR_NUMERIC, "non-finite parameter gradient");
+  return QLG_OK;
 }
 
 }  // extern "C"

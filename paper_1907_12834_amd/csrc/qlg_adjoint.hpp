@@ -8,18 +8,22 @@ namespace qlg {
 
 struct CtxView {
   const qlg_params* p;
-  const InstDesc* L_inst;
-  int64_t elems_per_copy;
-  char* state;
+  int64_t elems_per_copy;   // complex elements of one padded state copy
+  char* state;              // current copy = state + cur * elems_per_copy * elem_bytes
   size_t elem_bytes;
   hipStream_t stream;
-  int* cur;
+  int cur;
   LaunchGeom geom;
+  double* part;             // scratch: >= nchunks * 10 doubles
+  double* res;              // scratch: >= nbatch * 10 doubles
 };
 
 CtxView ctx_view(qlg_ctx* c);
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg);
 qlg_status ctx_step(qlg_ctx* c, int64_t nsteps);
+// one fused step from `in` to `out` (padded layout), no overlap recording
+hipError_t ctx_launch_step(qlg_ctx* c, const void* in, void* out);
+qlg_status ctx_hip(qlg_ctx* c, hipError_t e, const char* what);
 bool ctx_broken(const qlg_ctx* c);
 
 }  // namespace qlg

@@ -1,0 +1,469 @@
+// Kernels of the reverse-mode (adjoint) QLG step.
+//
+// The adjoint walks each step's substeps backwards.  The kinetic factors are
+// linear and unitary, so their pull-back is the exact inverse I'^H = C^H S C^H S^T
+// applied to the cotangent (no stored state).  The self-interaction is
+// nonlinear: its pull-back (qlg_vjp.hpp, FP64) needs the substep's input
+// state, which is recomputed from the step's input with the per-substep
+// kernels below (same per-site arithmetic as the fused forward kernels).
+//
+// All kernels are one thread per site over 256-site chunks of each instance.
+
+#include "qlg_adjoint_kernels.hpp"
+#include "qlg_math.hpp"
+#include "qlg_vjp.hpp"
+
+namespace qlg {
+
+namespace {
+
+struct Site {
+  InstDesc d;
+  int s, x, y;
+  bool ok;
+};
+
+__device__ __forceinline__ Site site_here(const LaunchGeom& g) {
+  Site r;
+  const int c = blockIdx.x;
+  r.d = g.inst[g.chunk2inst[c]];
+  r.s = (c - r.d.chunk_begin) * kChunk + threadIdx.x;
+  r.ok = r.s < r.d.sites;
+  r.x = r.ok ? r.s % r.d.nx : 0;
+  r.y = r.ok ? r.s / r.d.nx : 0;
+  return r;
+}
+
+// site index of the neighbour at offset dir (+1 / -1) along axis (0 = x, 1 = y), periodic
+__device__ __forceinline__ int neighbour(const Site& r, int axis, int dir) {
+  if (axis == 0) {
+    int x = r.x + dir;
+    x = x < 0 ? x + r.d.nx : (x >= r.d.nx ? x - r.d.nx : x);
+    return r.y * r.d.nx + x;
+  }
+  int y = r.y + dir;
+  y = y < 0 ? y + r.d.ny : (y >= r.d.ny ? y - r.d.ny : y);
+  return y * r.d.nx + r.x;
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ void load_site(const cx<T>* __restrict__ st, const InstDesc& d, int s,
+                                          cx<S> (&a)[5], cx<S> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> va = st[d.off + m * d.stride + s];
+    const cx<T> vb = st[d.off + (5 + m) * d.stride + s];
+    a[m] = cx<S>{(S)va.re, (S)va.im};
+    b[m] = cx<S>{(S)vb.re, (S)vb.im};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_site(cx<T>* __restrict__ st, const InstDesc& d, int s, const cx<T> (&a)[5],
+                                           const cx<T> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    st[d.off + m * d.stride + s] = a[m];
+    st[d.off + (5 + m) * d.stride + s] = b[m];
+  }
+}
+
+// C^H without its factor 1/2:  2 a' = (a + b) + i (a - b),  2 b' = (a + b) - i (a - b)
+__device__ __forceinline__ void collide2_adj(cx<double> (&a)[5], cx<double> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double sr = a[m].re + b[m].re, si = a[m].im + b[m].im;
+    const double dr = a[m].re - b[m].re, di = a[m].im - b[m].im;
+    a[m] = cx<double>{sr - di, si + dr};
+    b[m] = cx<double>{sr + di, si - dr};
+  }
+}
+
+}  // namespace
+
+// U(theta) on every site, out of place.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_sub_potential(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                         LaunchGeom g, Angles<T> ang) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+  cx<T> a[5], b[5];
+  load_site(in, r.d, r.s, a, b);
+  potential(a, b, ang);
+  store_site(out, r.d, r.s, a, b);
+}
+
+// I'_{axis,q} = S_q C S_q^T C, out of place, with the fused kernels' operation order:
+//   c = C(in) at x-1, x, x+1;  t(y) = (c.nonq(y), c.q(y+1));  m(y) = C t(y) (two unscaled
+//   collides and an exact 1/4);  out.nonq(x) = m(x).nonq,  out.q(x) = m(x-1).q.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_sub_iprime(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                      LaunchGeom g, int axis, int qb) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+  const int sm = neighbour(r, axis, -1), sp = neighbour(r, axis, +1);
+  cx<T> a0[5], b0[5], a1[5], b1[5], a2[5], b2[5];   // x-1, x, x+1
+  load_site(in, r.d, sm, a0, b0);
+  load_site(in, r.d, r.s, a1, b1);
+  load_site(in, r.d, sp, a2, b2);
+  collide2(a0, b0);
+  collide2(a1, b1);
+  collide2(a2, b2);
+  cx<T> ta[5], tb[5], ua[5], ub[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    // t(x) = (nonq of c(x), q of c(x+1));  t(x-1) = (nonq of c(x-1), q of c(x))
+    ta[m] = sel(qb != 0, a1[m], a2[m]);
+    tb[m] = sel(qb != 0, b2[m], b1[m]);
+    ua[m] = sel(qb != 0, a0[m], a1[m]);
+    ub[m] = sel(qb != 0, b1[m], b0[m]);
+  }
+  collide2(ta, tb);
+  scale_quarter(ta, tb);
+  collide2(ua, ub);
+  scale_quarter(ua, ub);
+  cx<T> oa[5], ob[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    oa[m] = sel(qb != 0, ta[m], ua[m]);   // moving qubit from m(x-1), the other from m(x)
+    ob[m] = sel(qb != 0, ub[m], tb[m]);
+  }
+  store_site(out, r.d, r.s, oa, ob);
+}
+
+// lambda <- I'^H lambda = C^H S_q C^H S_q^T lambda (FP64), out of place:
+//   w(y) = C^H(lambda.nonq(y), lambda.q(y+1));  out(x) = C^H(w(x).nonq, w(x-1).q).
+__global__ __launch_bounds__(kChunk) void k_sub_iprime_adj(const cx<double>* __restrict__ in,
+                                                          cx<double>* __restrict__ out, LaunchGeom g, int axis,
+                                                          int qb) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+  const int sm = neighbour(r, axis, -1), sp = neighbour(r, axis, +1);
+  cx<double> a0[5], b0[5], a1[5], b1[5], a2[5], b2[5];
+  load_site(in, r.d, sm, a0, b0);
+  load_site(in, r.d, r.s, a1, b1);
+  load_site(in, r.d, sp, a2, b2);
+  cx<double> wa[5], wb[5], va[5], vb[5];   // w(x), w(x-1)
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    wa[m] = sel(qb != 0, a1[m], a2[m]);
+    wb[m] = sel(qb != 0, b2[m], b1[m]);
+    va[m] = sel(qb != 0, a0[m], a1[m]);
+    vb[m] = sel(qb != 0, b1[m], b0[m]);
+  }
+  collide2_adj(wa, wb);
+  collide2_adj(va, vb);
+  cx<double> oa[5], ob[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    oa[m] = sel(qb != 0, wa[m], va[m]);
+    ob[m] = sel(qb != 0, vb[m], wb[m]);
+  }
+  collide2_adj(oa, ob);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    oa[m] = 0.25 * oa[m];
+    ob[m] = 0.25 * ob[m];
+  }
+  store_site(out, r.d, r.s, oa, ob);
+}
+
+// Block sum of three doubles into dst[0..2] (fixed order).
+__device__ __forceinline__ void block_sum3(double v0, double v1, double v2, double* __restrict__ dst) {
+  __shared__ double red[3][kChunk / kLanes];
+  const int lane = threadIdx.x & (kLanes - 1), wv = threadIdx.x >> 6;
+  double v[3] = {v0, v1, v2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kLanes);
+    if (lane == 0) red[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kChunk / kLanes; ++j) s += red[threadIdx.x][j];
+    dst[threadIdx.x] = s;
+  }
+}
+
+// lambda <- (dU)^H lambda at the substep input z (FP64 Jacobian); dg partials per chunk.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z, cx<double>* __restrict__ lam,
+                                                   LaunchGeom g, double theta, double g0, double g1, double g2,
+                                                   double* __restrict__ part) {
+  const Site r = site_here(g);
+  double dg[3] = {0.0, 0.0, 0.0};
+  if (r.ok) {
+    cx<double> a[5], b[5], la[5], lb[5];
+    load_site(z, r.d, r.s, a, b);
+    load_site(lam, r.d, r.s, la, lb);
+    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg);
+    store_site(lam, r.d, r.s, la, lb);
+  }
+  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
+}
+
+// acc[0..2] += sum over chunks of part (single block, fixed order).
+__global__ __launch_bounds__(kChunk) void k_dg_accumulate(const double* __restrict__ part, int nchunks,
+                                                         double* __restrict__ acc) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int c = threadIdx.x; c < nchunks; c += kChunk) {
+    v[0] += part[3 * c];
+    v[1] += part[3 * c + 1];
+    v[2] += part[3 * c + 2];
+  }
+  __shared__ double tot[3];
+  block_sum3(v[0], v[1], v[2], tot);
+  __syncthreads();
+  if (threadIdx.x < 3) acc[threadIdx.x] += tot[threadIdx.x];
+}
+
+// Energy objective: lambda_a = lambda_b = 2 dE/dpsi* written in the canonical
+// complex128 qubits layout; per chunk partials part[6c + 0..3] of
+// eps^d x (E density, n^2/2, |F|^2/2, |sigma|^2/10).
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict__ st, cx<double>* __restrict__ lam,
+                                                       LaunchGeom g, int ndim, double eps, double g0,
+                                                       double g1, double g2, double* __restrict__ part) {
+  const Site r = site_here(g);
+  double e = 0.0, en = 0.0, ef = 0.0, es = 0.0;
+  if (r.ok) {
+    const double meas = ndim == 1 ? eps : eps * eps;
+    const double ie2 = 1.0 / (eps * eps);
+    cx<double> a[5], b[5], p[5], lap[5];
+    load_site(st, r.d, r.s, a, b);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      p[m] = a[m] + b[m];
+      lap[m] = cx<double>{0.0, 0.0};
+    }
+    double ekin = 0.0;
+    for (int axis = 0; axis < ndim; ++axis) {
+      cx<double> pa[5], pb[5], ma[5], mb[5];
+      load_site(st, r.d, neighbour(r, axis, +1), pa, pb);
+      load_site(st, r.d, neighbour(r, axis, -1), ma, mb);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const cx<double> pp = pa[m] + pb[m], pm = ma[m] + mb[m];
+        const cx<double> df = pp - p[m];
+        ekin += df.re * df.re + df.im * df.im;
+        lap[m] = lap[m] + (2.0 * p[m] - pp - pm);
+      }
+    }
+    // H_loc psi = g0 n psi + g1 (F.f) psi + (g2/5) sigma S psi*
+    double q[5], n = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      q[m] = p[m].re * p[m].re + p[m].im * p[m].im;
+      n += q[m];
+    }
+    const double Fz = 2.0 * (q[0] - q[4]) + (q[1] - q[3]);
+    const cx<double> f1 = cmulc(p[0], p[1]) + cmulc(p[3], p[4]);
+    const cx<double> f2 = cmulc(p[1], p[2]) + cmulc(p[2], p[3]);
+    const double Fx = 2.0 * f1.re + Consts::r6 * f2.re, Fy = 2.0 * f1.im + Consts::r6 * f2.im;
+    const cx<double> sig = 2.0 * (p[0] * p[4]) - 2.0 * (p[1] * p[3]) + p[2] * p[2];
+    const double cf[4] = {2.0, Consts::r6, Consts::r6, 2.0};
+    cx<double> fp[5] = {}, fm[5] = {};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fp[i] = cf[i] * p[i + 1];
+      fm[i + 1] = cf[i] * p[i];
+    }
+    const cx<double> cpl{0.5 * Fx, -0.5 * Fy}, cmi{0.5 * Fx, 0.5 * Fy};
+    cx<double> Sp[5];
+    {
+      cx<double> pc[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) pc[m] = conj(p[m]);
+      Sp[0] = pc[4]; Sp[1] = -1.0 * pc[3]; Sp[2] = pc[2]; Sp[3] = -1.0 * pc[1]; Sp[4] = pc[0];
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      cx<double> h = (g0 * n) * p[m] + g1 * ((Fz * (2 - m)) * p[m] + cpl * fp[m] + cmi * fm[m]);
+      h = h + (g2 / 5.0) * (sig * Sp[m]);
+      const cx<double> l = (2.0 * meas) * (ie2 * lap[m] + h);
+      const int64_t o = r.d.qb_off + (int64_t)m * r.d.sites + r.s;
+      lam[o] = l;
+      lam[o + 5 * (int64_t)r.d.sites] = l;
+    }
+    const double f2s = Fx * Fx + Fy * Fy + Fz * Fz, s2 = sig.re * sig.re + sig.im * sig.im;
+    e = ekin * ie2 + 0.5 * (g0 * n * n + g1 * f2s + g2 * s2 / 5.0);
+    en = 0.5 * n * n;
+    ef = 0.5 * f2s;
+    es = 0.1 * s2;
+    e *= meas; en *= meas; ef *= meas; es *= meas;
+  }
+  // four partials in a 6-double slot per chunk: two block sums (e, en, ef) and (es, 0, 0)
+  block_sum3(e, en, ef, part + 6 * (int64_t)blockIdx.x);
+  __syncthreads();
+  block_sum3(es, 0.0, 0.0, part + 6 * (int64_t)blockIdx.x + 3);
+}
+
+// Fidelity objective, pass 1: chunk partials of eps^d <target|psi> (re, im).
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_fid_overlap(const cx<T>* __restrict__ st, const cx<T>* __restrict__ tgt,
+                                                       LaunchGeom g, double meas, double* __restrict__ part) {
+  const Site r = site_here(g);
+  double re = 0.0, im = 0.0;
+  if (r.ok) {
+    cx<double> a[5], b[5];
+    load_site(st, r.d, r.s, a, b);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const cx<T> tv = tgt[r.d.psi_off + (int64_t)m * r.d.sites + r.s];
+      const cx<double> t{(double)tv.re, (double)tv.im};
+      const cx<double> c = cmulc(t, a[m] + b[m]);
+      re += c.re;
+      im += c.im;
+    }
+    re *= meas;
+    im *= meas;
+  }
+  block_sum3(re, im, 0.0, part + 3 * (int64_t)blockIdx.x);
+}
+
+// Per-instance sum of the pass-1 partials into ov[inst][3].
+__global__ __launch_bounds__(kChunk) void k_fid_reduce(LaunchGeom g, const double* __restrict__ part,
+                                                      double* __restrict__ ov) {
+  const InstDesc d = g.inst[blockIdx.x];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int c = threadIdx.x; c < d.nchunks; c += kChunk) {
+    v[0] += part[3 * (d.chunk_begin + c)];
+    v[1] += part[3 * (d.chunk_begin + c) + 1];
+  }
+  block_sum3(v[0], v[1], v[2], ov + 3 * (int64_t)blockIdx.x);
+}
+
+// Pass 2: lambda_a = lambda_b = 2 eps^d <target|psi> target.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_fid_grad(const cx<T>* __restrict__ tgt, cx<double>* __restrict__ lam,
+                                                    LaunchGeom g, double meas, const double* __restrict__ ov) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+  const int inst = g.chunk2inst[blockIdx.x];
+  const cx<double> o{ov[3 * inst], ov[3 * inst + 1]};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> tv = tgt[r.d.psi_off + (int64_t)m * r.d.sites + r.s];
+    const cx<double> l = (2.0 * meas) * (o * cx<double>{(double)tv.re, (double)tv.im});
+    const int64_t off = r.d.qb_off + (int64_t)m * r.d.sites + r.s;
+    lam[off] = l;
+    lam[off + 5 * (int64_t)r.d.sites] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define QLG_GRID dim3(g.nchunks), dim3(kChunk), 0, st
+
+hipError_t launch_sub_potential(int dtype, const void* in, void* out, const LaunchGeom& g, double tg0, double tg1,
+                                double tg25, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sub_potential<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, g,
+                       Angles<float>{(float)tg0, (float)tg1, (float)tg25});
+  else
+    hipLaunchKernelGGL(k_sub_potential<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, g,
+                       Angles<double>{tg0, tg1, tg25});
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_iprime(int dtype, const void* in, void* out, const LaunchGeom& g, int axis, int qb,
+                             hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sub_iprime<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, g, axis, qb);
+  else
+    hipLaunchKernelGGL(k_sub_iprime<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, g, axis, qb);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_iprime_adj(const void* in, void* out, const LaunchGeom& g, int axis, int qb, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_iprime_adj, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, g, axis, qb);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom& g, double theta, double g0,
+                          double g1, double g2, double* part, double* acc, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sub_vjp<float>, QLG_GRID, (const cx<float>*)z, (cx<double>*)lam, g, theta, g0, g1, g2,
+                       part);
+  else
+    hipLaunchKernelGGL(k_sub_vjp<double>, QLG_GRID, (const cx<double>*)z, (cx<double>*)lam, g, theta, g0, g1,
+                       g2, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, (const double*)part, g.nchunks, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_grad(int dtype, int ndim, const void* state, void* lam, const LaunchGeom& g, double eps,
+                              double g0, double g1, double g2, double* part, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_energy_grad<float>, QLG_GRID, (const cx<float>*)state, (cx<double>*)lam, g, ndim, eps,
+                       g0, g1, g2, part);
+  else
+    hipLaunchKernelGGL(k_energy_grad<double>, QLG_GRID, (const cx<double>*)state, (cx<double>*)lam, g, ndim,
+                       eps, g0, g1, g2, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_fidelity_grad(int dtype, const void* state, const void* target, void* lam, const LaunchGeom& g,
+                                double meas, double* part, double* ov, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fid_overlap<float>, QLG_GRID, (const cx<float>*)state, (const cx<float>*)target, g, meas,
+                       part);
+  else
+    hipLaunchKernelGGL(k_fid_overlap<double>, QLG_GRID, (const cx<double>*)state, (const cx<double>*)target, g,
+                       meas, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fid_reduce, dim3(g.nbatch), dim3(kChunk), 0, st, g, (const double*)part, ov);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fid_grad<float>, QLG_GRID, (const cx<float>*)target, (cx<double>*)lam, g, meas,
+                       (const double*)ov);
+  else
+    hipLaunchKernelGGL(k_fid_grad<double>, QLG_GRID, (const cx<double>*)target, (cx<double>*)lam, g, meas,
+                       (const double*)ov);
+  return hipGetLastError();
+}
+
+// complex128 cotangent: canonical qubits layout <-> padded planes
+__global__ __launch_bounds__(kChunk) void k_lam_in(const cx<double>* __restrict__ qb, cx<double>* __restrict__ st,
+                                                  LaunchGeom g) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int p = 0; p < 10; ++p) st[r.d.off + p * r.d.stride + r.s] = qb[r.d.qb_off + (int64_t)p * r.d.sites + r.s];
+}
+__global__ __launch_bounds__(kChunk) void k_lam_out(const cx<double>* __restrict__ st, cx<double>* __restrict__ qb,
+                                                   LaunchGeom g) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int p = 0; p < 10; ++p) qb[r.d.qb_off + (int64_t)p * r.d.sites + r.s] = st[r.d.off + p * r.d.stride + r.s];
+}
+
+hipError_t launch_lam_layout(bool to_planes, const void* src, void* dst, const LaunchGeom& g, hipStream_t st) {
+  if (to_planes)
+    hipLaunchKernelGGL(k_lam_in, QLG_GRID, (const cx<double>*)src, (cx<double>*)dst, g);
+  else
+    hipLaunchKernelGGL(k_lam_out, QLG_GRID, (const cx<double>*)src, (cx<double>*)dst, g);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(double* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace qlg

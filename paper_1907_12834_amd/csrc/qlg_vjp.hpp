@@ -1,0 +1,270 @@
+// Reverse-mode derivative (vector-Jacobian product) of one self-interaction
+// application U(theta) at one site, in FP64.
+//
+// Forward (qlg_math.hpp): for x in {a, b},
+//   y1_x = P x = x + c(n) (v^H x) v,        c(n) = (e^{-i kappa n} - 1)/n, kappa = theta g2/5,
+//   y_x  = e^{-i theta g0 n} R(F) y1_x,      R = exp(-i tau F.f), tau = theta g1,
+// with psi = a + b, n = |psi|^2, F_nu = psi^H f_nu psi, v = S psi* (all frozen
+// at the input).  Cotangents follow lambda = dL/dRe z + i dL/dIm z, so for a
+// complex-linear map y = M z the pull-back is lambda_z = M^H lambda_y.
+//
+// In the frame Q = Phi d(beta) of F (Q^H (F.f) Q = |F| f_z) everything
+// diagonalises: with Y = Q^H y1, Lam = Q^H lambda_y and E_m = e^{-i(th g0 n + m phi)},
+//   lambda_{y1} = Q conj(E) Lam,
+//   dL/dn  (density) = th g0 sum_m Im(conj(Lam_m) E_m Y_m),
+//   dL/dg0            = th n  sum_m Im(conj(Lam_m) E_m Y_m),
+//   dL/dg1            = th |F| sum_m m Im(conj(Lam_m) E_m Y_m),
+// and the derivative of R with respect to F is the Frechet derivative of the
+// exponential, whose divided differences between neighbouring m are
+// e^{-i phi (m_j + m_k)/2} sinc(phi/2) (only neighbours couple through f_x, f_y):
+//   dL/dF = R3 G,  G_mu = Re(-i tau sum_jk conj(M'_jk) Delta_jk (f_mu)_jk),
+//   M' = sum_x (Q^H lambda_{y2,x}) (Q^H y1_x)^H,  lambda_{y2} = e^{i th g0 n} lambda_y,
+// with R3 = R_z(alpha) R_y(beta) the rotation taking z to F.  The singlet
+// factor contributes, per x with s_x = v^H x and l = lambda_{y1,x},
+//   lambda_x  = P^H l = l + conj(c) (v^H l) v,
+//   lambda_psi += conj(c) conj(l^H v) S x* + c s_x S conj(l),
+//   dL/dn += Re(c'(n) s_x (l^H v)),   dL/dg2 += Re(dc/dg2 s_x (l^H v)).
+// Finally lambda_psi += 2 dL/dn psi + 2 sum_nu dL/dF_nu f_nu psi and
+// lambda_a = P^H l_a + lambda_psi, lambda_b = P^H l_b + lambda_psi.
+#pragma once
+
+#include "qlg_math.hpp"
+
+namespace qlg {
+
+// Forward frame and phases of one application (FP64), shared by the VJP.
+struct UFrame {
+  cx<double> p[5];     // psi
+  double n, Fx, Fy, Fz, Fn, Fperp;
+  double phi0, phi;    // theta g0 n, theta g1 |F|
+  cx<double> cs;       // c(n)
+  cx<double> E[5];     // e^{-i (phi0 + m phi)}, m = 2..-2
+  cx<double> u;        // e^{i alpha}
+  double ca, sa, cb, sb;
+  double D[5][5];      // d^2(beta) [m'][m]
+};
+
+QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double theta, double g0,
+                    double g1, double g2, UFrame& f) {
+  const double r6 = Consts::r6, r32 = Consts::r32, r38 = Consts::r38;
+  double q[5];
+  for (int m = 0; m < 5; ++m) {
+    f.p[m] = a[m] + b[m];
+    q[m] = f.p[m].re * f.p[m].re + f.p[m].im * f.p[m].im;
+  }
+  f.n = q[0] + q[1] + q[2] + q[3] + q[4];
+  f.Fz = 2.0 * (q[0] - q[4]) + (q[1] - q[3]);
+  const cx<double> f1 = cmulc(f.p[0], f.p[1]) + cmulc(f.p[3], f.p[4]);
+  const cx<double> f2 = cmulc(f.p[1], f.p[2]) + cmulc(f.p[2], f.p[3]);
+  f.Fx = 2.0 * f1.re + r6 * f2.re;
+  f.Fy = 2.0 * f1.im + r6 * f2.im;
+  const double Fp2 = f.Fx * f.Fx + f.Fy * f.Fy;
+  f.Fperp = sqrt(Fp2);
+  f.Fn = sqrt(Fp2 + f.Fz * f.Fz);
+  f.phi0 = theta * g0 * f.n;
+  f.phi = theta * g1 * f.Fn;
+  for (int i = 0; i < 5; ++i) {
+    const double m = 2 - i;
+    double s, c;
+    sincos(f.phi0 + m * f.phi, &s, &c);
+    f.E[i] = cx<double>{c, -s};
+  }
+  // c(n) = (e^{-i kappa n} - 1)/n = kappa sinc(h) (-sin h - i cos h), h = kappa n / 2
+  const double kappa = theta * g2 / 5.0, h = 0.5 * kappa * f.n;
+  double sh, ch;
+  sincos(h, &sh, &ch);
+  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h / 6.0 : sh / h;
+  f.cs = cx<double>{-kappa * sinc * sh, -kappa * sinc * ch};
+  // frame
+  const double tiny = 1e-280;
+  f.ca = 1.0; f.sa = 0.0; f.cb = 1.0; f.sb = 0.0;
+  double opc = 2.0, omc = 0.0;
+  if (f.Fperp > tiny) { f.ca = f.Fx / f.Fperp; f.sa = f.Fy / f.Fperp; }
+  if (f.Fn > tiny) {
+    f.cb = f.Fz / f.Fn;
+    f.sb = f.Fperp / f.Fn;
+    if (f.Fz >= 0) { const double A = f.Fn + f.Fz; opc = A / f.Fn; omc = Fp2 / A / f.Fn; }
+    else { const double B = f.Fn - f.Fz; omc = B / f.Fn; opc = Fp2 / B / f.Fn; }
+  }
+  f.u = cx<double>{f.ca, f.sa};
+  const double cb = f.cb, sb = f.sb;
+  const double d22 = 0.25 * opc * opc, d21 = -0.5 * sb * opc, d20 = r38 * sb * sb, d2m1 = -0.5 * sb * omc,
+               d2m2 = 0.25 * omc * omc, d11 = 0.5 * opc * (2 * cb - 1), d10 = -r32 * sb * cb,
+               d1m1 = 0.5 * omc * (2 * cb + 1), d00 = 0.5 * (3 * cb * cb - 1);
+  const double Dm[5][5] = {
+      {d22, d21, d20, d2m1, d2m2},
+      {-d21, d11, d10, d1m1, d2m1},
+      {d20, -d10, d00, d10, d20},
+      {-d2m1, d1m1, -d10, d11, d21},
+      {d2m2, -d2m1, d20, -d21, d22},
+  };
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) f.D[i][j] = Dm[i][j];
+}
+
+// Q^H x = d^T Phi^* x (Phi^* multiplies component m by u^m)
+QLG_HD void to_frame(const UFrame& f, const cx<double> (&x)[5], cx<double> (&out)[5]) {
+  const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
+  const cx<double> w[5] = {x[0] * u2, x[1] * u, x[2], x[3] * uc, x[4] * u2c};
+  for (int k = 0; k < 5; ++k) {
+    cx<double> acc = f.D[0][k] * w[0];
+    for (int m = 1; m < 5; ++m) acc = rfma(f.D[m][k], w[m], acc);
+    out[k] = acc;
+  }
+}
+
+// Q z = Phi d z
+QLG_HD void from_frame(const UFrame& f, const cx<double> (&z)[5], cx<double> (&out)[5]) {
+  const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
+  cx<double> t[5];
+  for (int m = 0; m < 5; ++m) {
+    cx<double> acc = f.D[m][0] * z[0];
+    for (int k = 1; k < 5; ++k) acc = rfma(f.D[m][k], z[k], acc);
+    t[m] = acc;
+  }
+  out[0] = t[0] * u2c;
+  out[1] = t[1] * uc;
+  out[2] = t[2];
+  out[3] = t[3] * u;
+  out[4] = t[4] * u2;
+}
+
+// (S z)_m = (-1)^m z_{-m}
+QLG_HD void apply_S(const cx<double> (&z)[5], cx<double> (&out)[5]) {
+  out[0] = z[4];
+  out[1] = -1.0 * z[3];
+  out[2] = z[2];
+  out[3] = -1.0 * z[1];
+  out[4] = z[0];
+}
+
+QLG_HD double sinc_d(double x) { return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x; }
+
+// c'(n) for c(n) = (e^{-i k n} - 1)/n
+QLG_HD cx<double> dc_dn(double kappa, double n) {
+  const double z = kappa * n;
+  if (fabs(z) < 0.1) {
+    // sum_{j>=2} (-i kappa)^j (j-1) n^{j-2} / j!
+    cx<double> acc{0.0, 0.0};
+    cx<double> mik{0.0, -kappa};            // -i kappa
+    cx<double> pw = mik * mik;              // (-i kappa)^2
+    double npow = 1.0, fact = 2.0;
+    for (int j = 2; j <= 14; ++j) {
+      acc = acc + ((j - 1) * npow / fact) * pw;
+      pw = pw * mik;
+      npow *= n;
+      fact *= (j + 1);
+    }
+    return acc;
+  }
+  double s, c;
+  sincos(z, &s, &c);
+  const cx<double> e{c, -s};                                  // e^{-i k n}
+  const cx<double> cn = (1.0 / n) * (e - cx<double>{1.0, 0.0});
+  const cx<double> t = cx<double>{0.0, -kappa} * e;            // -i k e^{-ikn}
+  return (1.0 / n) * (t - cn);
+}
+
+// In: a, b (input of U), la, lb (cotangents of U's outputs).
+// Out: la, lb replaced by cotangents of a, b; dg[0..2] incremented.
+QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx<double> (&la)[5],
+                          cx<double> (&lb)[5], double theta, double g0, double g1, double g2, double (&dg)[3]) {
+  UFrame f;
+  u_frame(a, b, theta, g0, g1, g2, f);
+  const double tau = theta * g1;
+  cx<double> v[5];
+  {
+    cx<double> pc[5];
+    for (int m = 0; m < 5; ++m) pc[m] = conj(f.p[m]);
+    apply_S(pc, v);                          // v = S psi*
+  }
+  double dn = 0.0;                           // dL/dn
+  double dFx = 0.0, dFy = 0.0, dGz = 0.0;    // G in the frame
+  cx<double> Tdiag[5] = {}, Tup[4] = {}, Tdn[4] = {};
+  cx<double> lpsi[5] = {};
+  const double cfac[4] = {2.0, Consts::r6, Consts::r6, 2.0};
+  const cx<double> e0{cos(f.phi0), -sin(f.phi0)};
+  const double sc = sinc_d(0.5 * f.phi);
+  const double kappa = theta * g2 / 5.0;
+  const cx<double> dcn = dc_dn(kappa, f.n);
+  const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * cx<double>{cos(kappa * f.n), -sin(kappa * f.n)};
+  // one 5-vector x with output cotangent ly; lx receives P^H lambda_{y1}
+  auto one = [&](const cx<double>(&x)[5], const cx<double>(&ly)[5], cx<double>(&lx)[5]) {
+    cx<double> s{0.0, 0.0};
+    for (int m = 0; m < 5; ++m) s = s + cmulc(v[m], x[m]);    // v^H x
+    cx<double> y1[5];
+    for (int m = 0; m < 5; ++m) y1[m] = x[m] + (f.cs * s) * v[m];
+    cx<double> Y[5], Lam[5];
+    to_frame(f, y1, Y);
+    to_frame(f, ly, Lam);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int i = 0; i < 5; ++i) {
+      const cx<double> t = f.E[i] * cmulc(Lam[i], Y[i]);    // conj(Lam) E Y
+      acc0 += t.im;
+      acc1 += (2 - i) * t.im;
+      Tdiag[i] = Tdiag[i] + t;
+    }
+    dn += theta * g0 * acc0;
+    dg[0] += theta * f.n * acc0;
+    dg[1] += theta * f.Fn * acc1;
+    // off-diagonal divided differences: pairs (i, i+1), m_i = 2 - i
+    for (int i = 0; i < 4; ++i) {
+      const double msum = (2 - i) + (1 - i);
+      const cx<double> dlt = sc * (e0 * cx<double>{cos(0.5 * f.phi * msum), -sin(0.5 * f.phi * msum)});
+      Tup[i] = Tup[i] + dlt * cmulc(Lam[i], Y[i + 1]);       // conj(M'_{i,i+1}) Delta
+      Tdn[i] = Tdn[i] + dlt * cmulc(Lam[i + 1], Y[i]);       // conj(M'_{i+1,i}) Delta
+    }
+    // cotangent of y1: Q conj(E) Lam
+    cx<double> z[5], l1[5];
+    for (int i = 0; i < 5; ++i) z[i] = conj(f.E[i]) * Lam[i];
+    from_frame(f, z, l1);
+    // singlet factor
+    cx<double> lv{0.0, 0.0};
+    for (int m = 0; m < 5; ++m) lv = lv + cmulc(l1[m], v[m]);   // l^H v
+    for (int m = 0; m < 5; ++m) lx[m] = l1[m] + (conj(f.cs) * conj(lv)) * v[m];
+    cx<double> xs[5], Sx[5], lc[5], Sl[5];
+    for (int m = 0; m < 5; ++m) { xs[m] = conj(x[m]); lc[m] = conj(l1[m]); }
+    apply_S(xs, Sx);
+    apply_S(lc, Sl);
+    for (int m = 0; m < 5; ++m) lpsi[m] = lpsi[m] + (conj(f.cs) * conj(lv)) * Sx[m] + (f.cs * s) * Sl[m];
+    dn += (dcn * s * lv).re;
+    dg[2] += (dcg * s * lv).re;
+  };
+  cx<double> pa[5], pb[5];
+  one(a, la, pa);
+  one(b, lb, pb);
+  // G in the frame: G_mu = Re(-i tau sum T_jk (f_mu)_jk)
+  for (int i = 0; i < 5; ++i) dGz += (2 - i) * Tdiag[i].im;   // Re(-i z) = Im(z)
+  dGz *= tau;
+  for (int i = 0; i < 4; ++i) {
+    const double ch = 0.5 * cfac[i];
+    // f_x: (i,i+1) and (i+1,i) entries ch;  f_y: (i,i+1) = -i ch, (i+1,i) = +i ch
+    dFx += tau * ch * (Tup[i].im + Tdn[i].im);
+    // Re(-i tau (-i ch Tup + i ch Tdn)) = tau ch Re(-Tup + Tdn)
+    dFy += tau * ch * (-Tup[i].re + Tdn[i].re);
+  }
+  // lab frame: dL/dF = R3 G,  R3 = R_z(alpha) R_y(beta)
+  const double ca = f.ca, sa = f.sa, cb = f.cb, sb = f.sb;
+  const double LFx = ca * cb * dFx - sa * dFy + ca * sb * dGz;
+  const double LFy = sa * cb * dFx + ca * dFy + sa * sb * dGz;
+  const double LFz = -sb * dFx + cb * dGz;
+  // lambda_psi += 2 dn psi + 2 (LFz f_z + (LFx - i LFy)/2 f_+ + (LFx + i LFy)/2 f_-) psi
+  cx<double> fp[5] = {}, fm[5] = {};
+  for (int i = 0; i < 4; ++i) {
+    fp[i] = cfac[i] * f.p[i + 1];       // (f_+ psi)_i
+    fm[i + 1] = cfac[i] * f.p[i];       // (f_- psi)_{i+1}
+  }
+  const cx<double> cpl{0.5 * LFx, -0.5 * LFy}, cmi{0.5 * LFx, 0.5 * LFy};
+  for (int i = 0; i < 5; ++i) {
+    const cx<double> fz = (double)(2 - i) * f.p[i];
+    cx<double> t = (2.0 * dn) * f.p[i] + (2.0 * LFz) * fz;
+    t = t + 2.0 * (cpl * fp[i] + cmi * fm[i]);
+    lpsi[i] = lpsi[i] + t;
+  }
+  for (int m = 0; m < 5; ++m) {
+    la[m] = pa[m] + lpsi[m];
+    lb[m] = pb[m] + lpsi[m];
+  }
+}
+
+}  // namespace qlg

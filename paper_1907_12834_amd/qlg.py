@@ -273,6 +273,48 @@ class Lattice:
                     "qlg_last_kernel_ms")
         return ms.value, n.value
 
+    # -- adjoint ---------------------------------------------------------------
+    def adjoint_sizes(self, nsteps: int, checkpoint_every: int):
+        ck, wk = ctypes.c_size_t(), ctypes.c_size_t()
+        st = lib().qlg_adjoint_query(ctypes.byref(self.params), int(nsteps), int(checkpoint_every),
+                                     ctypes.byref(ck), ctypes.byref(wk))
+        if st != QLG_OK:
+            raise QLGError(st, "qlg_adjoint_query")
+        return ck.value, wk.value
+
+    def forward_record(self, nsteps: int, checkpoint_every: int) -> torch.Tensor:
+        """Run nsteps, keeping a checkpoint every `checkpoint_every` steps (returned buffer)."""
+        ck, _ = self.adjoint_sizes(nsteps, checkpoint_every)
+        buf = _device_bytes(ck, self.device)
+        self._check(lib().qlg_forward_record(self.ctx, int(nsteps), int(checkpoint_every), buf.data_ptr(), ck),
+                    "qlg_forward_record")
+        return buf
+
+    def objective_grad(self, kind: str = "energy", target=None):
+        """(L, lambda, dL/dg explicit): lambda is complex128 in the canonical qubits layout."""
+        lam = torch.empty(10 * self.sites, dtype=torch.complex128, device=self.device)
+        val = ctypes.c_double()
+        dg = (ctypes.c_double * 3)()
+        tptr = None
+        if kind == "fidelity":
+            fields = target if isinstance(target, (list, tuple)) else [target]
+            self._target = self._flat(fields, 5)
+            tptr = self._target.data_ptr()
+        code = {"energy": 0, "fidelity": 1}[kind]
+        self._check(lib().qlg_objective_grad(self.ctx, code, tptr, lam.data_ptr(), ctypes.byref(val), dg),
+                    "qlg_objective_grad")
+        return val.value, lam, list(dg)
+
+    def adjoint_step(self, nsteps: int, checkpoint_every: int, ckpt: torch.Tensor, lam: torch.Tensor):
+        """Pull lam (complex128 canonical qubits) back over the recorded run; returns dL/dg."""
+        _, wk = self.adjoint_sizes(nsteps, checkpoint_every)
+        work = _device_bytes(wk, self.device)
+        dg = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+        lam = lam.contiguous()
+        self._check(lib().qlg_adjoint_step(self.ctx, int(nsteps), int(checkpoint_every), ckpt.data_ptr(),
+                                           lam.data_ptr(), work.data_ptr(), wk, dg), "qlg_adjoint_step")
+        return list(dg)
+
     def close(self):
         if getattr(self, "ctx", None):
             lib().qlg_destroy(self.ctx)
