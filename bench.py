@@ -37,6 +37,15 @@ PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vect
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 
+# HBM traffic of one k_step1d<float> launch of this workload (4 steps per pass), from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by a 256 MiB device copy
+# measured in the same runs (FETCH_SIZE read 131093 KiB for 262144 KiB copied: x2.000;
+# WRITE_SIZE 262144 KiB: x1.000).  Valid only for the kernel sources it was measured on.
+KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
+                  "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
+TRAFFIC = {"sources_sha256_16": "5026fe6614080adc", "steps_per_pass": 4,
+           "fetch_kib": 890.0, "fetch_scale": 262144.0 / 131093.3, "write_kib": 1280.4, "write_scale": 1.0}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -44,33 +53,41 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--secondary", choices=["c64", "c128", "none"], default="c128",
+                    help="also time the other storage precision of the same workload")
     ap.add_argument("--cpu-steps", type=int, default=120,
                     help="steps of the oracle sample for cpu_baseline (0 = skip)")
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500,
+                    help="steps of the batched-vs-one-at-a-time comparison (0 = skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the forward+adjoint vs forward comparison (0 = skip)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device-to-device (a plain copy kernel of known "
+                         "size that rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE runs use to scale their counters)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
-        sys.exit(2)
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    import numpy as np
+
+def measure(dtype, steps, warmup):
+    """Run the workload; return rate, wall time, per-launch kernel time and plan."""
     import torch
-
     import qlg_inputs as qi
     from paper_1907_12834_amd.qlg import Lattice
 
-    w = qi.c2_two_solitons(nsteps=args.steps)
+    w = qi.c2_two_solitons(nsteps=steps)
     L = w.nx[0]
-    lat = Lattice(1, [L], g=w.g, eps=w.eps, dtype=args.dtype)
+    lat = Lattice(1, [L], g=w.g, eps=w.eps, dtype=dtype)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     tuning = lat.autotune()
-    if not args.no_graph:
-        lat.set_tuning(use_graph=True)
+    lat.set_tuning(use_graph=True)
     tuning = lat.tuning()
 
     def run(nsteps):
@@ -82,46 +99,146 @@ def main():
             if done % OBS_EVERY == 0:
                 lat.observables()
 
-    run(args.warmup)
+    run(warmup)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     obs0 = lat.observables()[0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(args.steps)
+    run(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     obs1 = lat.observables()[0]
     wall = t1 - t0
-    value = L * args.steps / wall
-
-    # Average device time of one fused-step launch, from HIP events recorded
-    # around every launch on the library's stream (graphs off while measuring).
-    lat.set_tuning(use_graph=False)
+    # Kernel time: the same run again, now with a pair of HIP events on every fused-step
+    # launch that its dispatch packet stamps at kernel start and end (library stream).
+    # Those events add ~9 us of dispatch gap per launch, so they stay out of the
+    # throughput region above.
+    lat.set_psi([torch.from_numpy(w.psi[0])])
     lat.set_timing(True)
-    meas_steps = min(args.steps, 2000)
-    lat.step(meas_steps)
+    run(min(steps, 4000))
     kern_ms, launches = lat.last_kernel_ms()
     lat.set_timing(False)
-    S = tuning["steps_per_pass"]
+    return {"w": w, "L": L, "value": L * steps / wall, "wall": wall, "kern_ms": kern_ms, "launches": launches,
+            "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0}
+
+
+def batched_ratio(steps):
+    """256 uneven 1D two-soliton runs in one batched context vs the same runs one at a time."""
+    import torch
+    import qlg_inputs as qi
+    from paper_1907_12834_amd.qlg import Lattice
+
+    wb = qi.c4_batched(nsteps=steps)
+    psis = [torch.from_numpy(p) for p in wb.psi]
+    lat = Lattice(1, wb.nx, g=wb.g, eps=wb.eps, dtype="c64")
+    lat.set_psi(psis)
+    plan = lat.autotune()
+    lat.step(steps // 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    singles = []
+    for i in range(wb.nbatch):
+        one = Lattice(1, [wb.nx[i]], g=wb.g, eps=wb.eps, dtype="c64")
+        one.set_psi([psis[i]])
+        one.autotune()
+        one.step(1)
+        singles.append(one)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for one in singles:
+        one.step(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    su = wb.sites * steps
+    return {"workload": "256 1D two-soliton runs, L = 1024..16384 (sum %d sites), c64, %d steps" % (wb.sites, steps),
+            "batched_site_updates_per_s": su / tb, "one_at_a_time_site_updates_per_s": su / ts,
+            "speedup": ts / tb, "plan": plan}
+
+
+def adjoint_ratio(steps, K):
+    """(forward with checkpoints + reverse sweep) vs the plain forward, 2D 512^2 vortex pair, c64."""
+    import torch
+    import qlg_inputs as qi
+    from paper_1907_12834_amd.qlg import Lattice
+
+    w = qi.c5_adjoint(nsteps=steps, checkpoint_every=K)
+    psi = torch.from_numpy(w.psi[0])
+    lat = Lattice(2, w.nx, w.ny, g=w.g, eps=w.eps, dtype="c64")
+    lat.set_psi([psi])
+    lat.autotune()
+    lat.step(10)
+    lat.set_psi([psi])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    lat.set_psi([psi])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ck = lat.forward_record(steps, K)
+    val, lam, dg0 = lat.objective_grad("energy")
+    dg = lat.adjoint_step(steps, K, ck, lam)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    return {"workload": "2D %dx%d vortex pair, c64 forward, FP64 self-interaction Jacobian, %d steps, checkpoint "
+                        "every %d, gradient of the final energy" % (w.nx[0], w.ny[0], steps, K),
+            "forward_s": tf, "forward_plus_adjoint_s": ta, "ratio": ta / tf,
+            "dL_dg": [a + b for a, b in zip(dg, dg0)]}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    m = measure(args.dtype, args.steps, args.warmup)
+    w, L = m["w"], m["L"]
+    S = m["tuning"]["steps_per_pass"]
+    kern_ms = m["kern_ms"]
     sites_per_launch = L * S
     flops_launch = FLOPS_PER_SITE_STEP[1] * sites_per_launch
     achieved_tflops = flops_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L
     hbm_gbs = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    traffic = None
+    if (args.dtype == "c64" and S == TRAFFIC["steps_per_pass"]
+            and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]):
+        traffic = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
-    cpu = None
-    if args.cpu_steps > 0:
-        cpu = cpu_baseline(w, args.cpu_steps)
+    secondary = None
+    if args.secondary not in ("none", args.dtype):
+        m2 = measure(args.secondary, args.steps, min(args.warmup, 200))
+        secondary = {"storage": args.secondary, "value": m2["value"], "unit": "site-updates/s",
+                     "kernel_ms_avg": m2["kern_ms"], "plan": m2["tuning"], "norm_drift": m2["drift"]}
+    batched = batched_ratio(args.batched_steps) if args.batched_steps > 0 else None
+    adjoint = adjoint_ratio(args.adjoint_steps, 64) if args.adjoint_steps > 0 else None
+    cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
 
-    drift = obs1["norm_q"] / obs0["norm_q"] - 1.0
     out = {
         "metric": "QLG site-updates/s + % HBM roofline; batched and fwd+adjoint vs plain step",
-        "value": value,
+        "value": m["value"],
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": m["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -135,7 +252,7 @@ def main():
             "g": list(w.g),
             "eps": w.eps,
             "observables_every": OBS_EVERY,
-            "plan": tuning,
+            "plan": m["tuning"],
         },
         "roofline": {
             "bound": "alu",
@@ -143,15 +260,19 @@ def main():
             "peak": PEAK_TFLOPS[args.dtype],
             "unit": "TFLOP/s",
             "frac": (achieved_tflops / PEAK_TFLOPS[args.dtype]) if achieved_tflops else None,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch",
             "kernel": "k_step1d",
             "kernel_ms_avg": kern_ms,
-            "launches_timed": launches,
+            "launches_timed": m["launches"],
             "flops_per_site_update": FLOPS_PER_SITE_STEP[1],
             "hbm_algorithmic_gbs": hbm_gbs,
             "hbm_frac": (hbm_gbs / PEAK_HBM_GBS) if hbm_gbs else None,
         },
-        "norm_drift": drift,
+        "norm_drift": m["drift"],
+        "secondary": secondary,
+        "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

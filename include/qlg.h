@@ -146,9 +146,12 @@ qlg_status qlg_set_tuning(qlg_ctx* ctx, const qlg_tuning* tuning);
 qlg_status qlg_get_tuning(const qlg_ctx* ctx, qlg_tuning* tuning);
 qlg_status qlg_autotune(qlg_ctx* ctx);
 
-/* Average device time in milliseconds of one launch of the fused step
- * kernel over the last qlg_step call, measured with HIP events on the
- * context's stream (0 if not measured).  Enabled by qlg_set_timing(ctx, 1). */
+/* Kernel timing.  qlg_set_timing(ctx, 1) starts (and resets) it: every
+ * fused-step launch of later qlg_step calls is then dispatched with a pair of
+ * HIP events that the dispatch packet itself stamps at kernel start and end
+ * (no graph replay while timing; each qlg_step call synchronises the stream).
+ * qlg_last_kernel_ms returns the average kernel time in milliseconds over all
+ * launches timed since then, and their number (0 if none). */
 qlg_status qlg_set_timing(qlg_ctx* ctx, int32_t enable);
 qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_host);
 

@@ -150,8 +150,8 @@ struct qlg_ctx {
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
-  double last_ms = 0.0;
-  int64_t last_launches = 0;
+  double time_ms = 0.0;          // summed kernel time since timing was enabled
+  int64_t time_launches = 0;
 
   LaunchGeom geom() const {
     LaunchGeom g;
@@ -226,16 +226,17 @@ double angle_scale(const qlg_ctx* c) {   // interleaved theta = eps^2 / (4 d)
   return c->p.eps * c->p.eps / (4.0 * c->p.ndim);
 }
 
-hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void* out) {
+hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void* out,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const double th = angle_scale(c);
   const LaunchGeom g = c->geom();
   double* ov = c->sc(c->S.ov_part);
   const bool plain = c->p.split == QLG_SPLIT_PLAIN;
   if (c->p.ndim == 1)
     return qlg::launch_step1d(c->p.dtype, steps, plain, overlap, in, out, g, th * c->p.g0, th * c->p.g1,
-                              th * c->p.g2 / 5.0, ov, c->stream);
+                              th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
   return qlg::launch_step2d(c->p.dtype, plain, overlap, c->tuning.tile_rows, in, out, g, th * c->p.g0,
-                            th * c->p.g1, th * c->p.g2 / 5.0, ov, c->stream);
+                            th * c->p.g1, th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
 }
 
 // Enqueue nsteps as passes of steps_per_pass (1D) or single steps (2D), ping-ponging
@@ -247,16 +248,13 @@ qlg_status enqueue_steps(qlg_ctx* c, int64_t nsteps, int* cur, bool timed) {
   while (left > 0) {
     const int s = (int)std::min<int64_t>(S, left);
     const bool last = left == s;
-    if (timed) {
-      const size_t k = 2 * (size_t)launch;
-      if (k + 1 < c->ev.size()) (void)hipEventRecord(c->ev[k], c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed && 2 * (size_t)launch + 1 < c->ev.size()) {
+      e0 = c->ev[2 * (size_t)launch];
+      e1 = c->ev[2 * (size_t)launch + 1];
     }
-    hipError_t e = launch_pass(c, s, last, c->copy(*cur), c->copy(1 - *cur));
+    hipError_t e = launch_pass(c, s, last, c->copy(*cur), c->copy(1 - *cur), e0, e1);
     if (e != hipSuccess) return hip_check(c, e, "step kernel launch");
-    if (timed) {
-      const size_t k = 2 * (size_t)launch;
-      if (k + 1 < c->ev.size()) (void)hipEventRecord(c->ev[k + 1], c->stream);
-    }
     *cur = 1 - *cur;
     left -= s;
     ++launch;
@@ -448,14 +446,13 @@ qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
     c->cur = cur;
     s = hip_check(c, hipStreamSynchronize(c->stream), "sync for timing");
     if (s) return s;
-    double tot = 0.0;
-    int64_t n = 0;
     for (int64_t k = 0; k < launches && 2 * (size_t)k + 1 < c->ev.size(); ++k) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) { tot += ms; ++n; }
+      if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) {
+        c->time_ms += ms;
+        ++c->time_launches;
+      }
     }
-    c->last_ms = n ? tot / n : 0.0;
-    c->last_launches = n;
   } else if (c->tuning.use_graph && launches > 1) {
     auto key = std::make_pair(nsteps, c->cur);
     auto it = c->graphs.find(key);
@@ -617,13 +614,15 @@ qlg_status qlg_set_timing(qlg_ctx* c, int32_t enable) {
   qlg_status s = check_ctx(c);
   if (s) return s;
   c->timing = enable != 0;
+  c->time_ms = 0.0;
+  c->time_launches = 0;
   return QLG_OK;
 }
 
 qlg_status qlg_last_kernel_ms(qlg_ctx* c, double* ms, int64_t* launches) {
   if (!c || !ms || !launches) return QLG_ERR_ARG;
-  *ms = c->last_ms;
-  *launches = c->last_launches;
+  *ms = c->time_launches ? c->time_ms / c->time_launches : 0.0;
+  *launches = c->time_launches;
   return QLG_OK;
 }
 

@@ -36,12 +36,13 @@ struct LaunchGeom {
 
 // Kernel launchers (qlg_kernels.hip).  All return the hipError_t of the launch.
 // dtype: 0 = complex64, 1 = complex128.  Angles are theta*g0, theta*g1, theta*g2/5.
+// ev0/ev1 (optional): events the dispatch packet itself stamps at kernel start/end.
 hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st);
+                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st);
+                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_set_psi(int dtype, const void* psi, void* state, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_get_psi(int dtype, const void* state, void* psi, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_set_qubits(int dtype, const void* qb, void* state, const LaunchGeom& g, hipStream_t st);

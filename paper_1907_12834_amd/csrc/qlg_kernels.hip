@@ -18,6 +18,8 @@
 // The self-interaction U (qlg_math.hpp) is the arithmetic core: the path is
 // bound by the vector ALUs, not by HBM, and uses no matrix cores.
 
+#include <hip/hip_ext.h>
+
 #include "qlg_internal.hpp"
 #include "qlg_math.hpp"
 
@@ -32,24 +34,22 @@ __device__ __forceinline__ cx<T> shfl_from_prev(cx<T> v) {   // value of lane - 
   return cx<T>{__shfl_up(v.re, 1, kLanes), __shfl_up(v.im, 1, kLanes)};
 }
 
-// I'_{x,q} = S_q C S_q^T C with lanes along x; qb selects the moving qubit
-// (false: a, the paper's qubit 1; true: b, qubit 2).  qb is wave-uniform.
-template <typename T>
-__device__ __forceinline__ void iprime_lanes(cx<T> (&a)[5], cx<T> (&b)[5], bool qb) {
+// I'_{x,q} = S_q C S_q^T C with lanes along x.  Q = 1: qubit b (the paper's
+// qubit 2) moves; Q = 0: qubit a (qubit 1).
+template <typename T, int Q>
+__device__ __forceinline__ void iprime_lanes(cx<T> (&a)[5], cx<T> (&b)[5]) {
   collide2(a, b);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {   // S^T: q(x) <- q(x + 1)
-    const cx<T> v = shfl_from_next(sel(qb, b[m], a[m]));
-    a[m] = sel(qb, a[m], v);   // value selects keep a and b in registers
-    b[m] = sel(qb, v, b[m]);
+    if (Q) b[m] = shfl_from_next(b[m]);
+    else   a[m] = shfl_from_next(a[m]);
   }
   collide2(a, b);
   scale_quarter(a, b);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {   // S: q(x) <- q(x - 1)
-    const cx<T> v = shfl_from_prev(sel(qb, b[m], a[m]));
-    a[m] = sel(qb, a[m], v);
-    b[m] = sel(qb, v, b[m]);
+    if (Q) b[m] = shfl_from_prev(b[m]);
+    else   a[m] = shfl_from_prev(a[m]);
   }
 }
 
@@ -110,16 +110,24 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
   const Angles<T> an{plain ? A.ang_full.tg0 : A.ang.tg0, plain ? A.ang_full.tg1 : A.ang.tg1,
                      plain ? A.ang_full.tg25 : A.ang.tg25};
   cx<T> pold[5];
-  const int nsub = 4 * A.steps;
+  // one step: [U] I'_{x,b} [U] I'_{x,b} [U] I'_{x,a} [U] I'_{x,a}; the moving qubit is
+  // a compile-time parameter of each inner loop
 #pragma unroll 1
-  for (int k = 0; k < nsub; ++k) {
-    const int sub = k & 3;
-    if (A.overlap && k == nsub - 4) {
+  for (int st = 0; st < A.steps; ++st) {
+    if (A.overlap && st == A.steps - 1) {
 #pragma unroll
       for (int m = 0; m < 5; ++m) pold[m] = a[m] + b[m];
     }
-    if (!plain || sub == 0) potential(a, b, an);
-    iprime_lanes(a, b, sub < 2);
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j) {
+      if (!plain || j == 0) potential(a, b, an);
+      iprime_lanes<T, 1>(a, b);
+    }
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j) {
+      if (!plain) potential(a, b, an);
+      iprime_lanes<T, 0>(a, b);
+    }
   }
   const bool valid = lane >= H && lane < kLanes - H && x < L;
   if (valid) {
@@ -157,26 +165,38 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
 // output.  Each stage keeps two pending 5-vectors per lane:
 //   cn: the non-moving qubit of C(input) at row r - 1,
 //   mq: the moving qubit after the second collide at row r - 2.
-template <typename T>
-__device__ __forceinline__ void y_stage_core(cx<T> (&a)[5], cx<T> (&b)[5], cx<T> (&cn)[5], cx<T> (&mq)[5],
-                                             bool qb) {
+template <typename T, int Q>
+__device__ __forceinline__ void y_stage_core(cx<T> (&a)[5], cx<T> (&b)[5], cx<T> (&cn)[5], cx<T> (&mq)[5]) {
   collide2(a, b);                     // c(r)
   cx<T> ta[5], tb[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {       // t(r-1) = (c(r-1).nonq, c(r).q)   [S^T: q(y) <- q(y+1)]
-    const cx<T> keep = sel(qb, a[m], b[m]);
-    ta[m] = sel(qb, cn[m], a[m]);
-    tb[m] = sel(qb, b[m], cn[m]);
-    cn[m] = keep;
+    if (Q) { ta[m] = cn[m]; tb[m] = b[m]; cn[m] = a[m]; }
+    else   { ta[m] = a[m]; tb[m] = cn[m]; cn[m] = b[m]; }
   }
   collide2(ta, tb);                   // m(r-1)
   scale_quarter(ta, tb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {       // out(r-1) = (m(r-1).nonq, m(r-2).q)  [S: q(y) <- q(y-1)]
-    const cx<T> moved = sel(qb, tb[m], ta[m]);
-    a[m] = sel(qb, ta[m], mq[m]);
-    b[m] = sel(qb, mq[m], tb[m]);
-    mq[m] = moved;
+    if (Q) { a[m] = ta[m]; b[m] = mq[m]; mq[m] = tb[m]; }
+    else   { a[m] = mq[m]; b[m] = tb[m]; mq[m] = ta[m]; }
+  }
+}
+
+// One y stage on the streaming row, its pending rows kept in this lane's LDS slot.
+template <typename T, int Q>
+__device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>* slot) {
+  cx<T> cn[5], mq[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    cn[m] = slot[m * kLanes];
+    mq[m] = slot[(5 + m) * kLanes];
+  }
+  y_stage_core<T, Q>(a, b, cn, mq);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    slot[m * kLanes] = cn[m];
+    slot[(5 + m) * kLanes] = mq[m];
   }
 }
 
@@ -220,28 +240,29 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
       a[m] = src[m * d.stride];
       b[m] = src[(5 + m) * d.stride];
     }
-    // substeps 0..3: y stages (b, b, a, a); 4..7: x half (b, b, a, a).  Rows that
-    // leave the y pipeline before r = 8 are incomplete and skip the x half.
-    const int nsub = r < 8 ? 4 : 8;
+    // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y; slot k of this lane's LDS
+    // holds stage k's pending rows.  The plain split applies its single U at stage 0.
 #pragma unroll 1
-    for (int k = 0; k < nsub; ++k) {
-      if (!plain || k == 0) potential(a, b, an);
-      if (k < 4) {
-        cx<T>* slot = my + k * 10 * kLanes;
-        cx<T> cn[5], mq[5];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          cn[m] = slot[m * kLanes];
-          mq[m] = slot[(5 + m) * kLanes];
-        }
-        y_stage_core(a, b, cn, mq, k < 2);
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          slot[m * kLanes] = cn[m];
-          slot[(5 + m) * kLanes] = mq[m];
-        }
-      } else {
-        iprime_lanes(a, b, k < 6);
+    for (int j = 0; j < 2; ++j) {
+      if (!plain || j == 0) potential(a, b, an);
+      y_stage_lds<T, 1>(a, b, my + j * 10 * kLanes);
+    }
+#pragma unroll 1
+    for (int j = 2; j < 4; ++j) {
+      if (!plain) potential(a, b, an);
+      y_stage_lds<T, 0>(a, b, my + j * 10 * kLanes);
+    }
+    // x half for rows that have left the y pipeline complete (r >= 8)
+    if (r >= 8) {
+#pragma unroll 1
+      for (int j = 0; j < 2; ++j) {
+        if (!plain) potential(a, b, an);
+        iprime_lanes<T, 1>(a, b);
+      }
+#pragma unroll 1
+      for (int j = 0; j < 2; ++j) {
+        if (!plain) potential(a, b, an);
+        iprime_lanes<T, 0>(a, b);
       }
     }
     if (r < 8) continue;
@@ -498,37 +519,47 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
   return A;
 }
 
+// Launch `kernel`; with events, the dispatch packet stamps them at kernel start and end.
+template <typename K, typename A>
+static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1, A args) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, ev0, ev1, 0u, args);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args);
+}
+
 hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
   if (steps < 1 || 8 * steps >= kLanes) return hipErrorInvalidValue;
   const dim3 grid((g.ntiles + 3) / 4), block(256);
   // the plain split's single U uses theta = eps^2 = 4x the interleaved 1D angle
   if (dtype == 0)
-    hipLaunchKernelGGL(k_step1d<float>, grid, block, 0, st,
-                       step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+    launch_timed(k_step1d<float>, grid, block, 0, st, ev0, ev1,
+                 step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
   else
-    hipLaunchKernelGGL(k_step1d<double>, grid, block, 0, st,
-                       step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+    launch_timed(k_step1d<double>, grid, block, 0, st, ev0, ev1,
+                 step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
   return hipGetLastError();
 }
 
 hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
   if (tile_rows < 1) return hipErrorInvalidValue;
   const dim3 grid((g.ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
   // 2D interleaved angles are eps^2/8; the plain split's single U uses eps^2 = 8x
   if (dtype == 0) {
     const size_t lds = sizeof(cx<float>) * kStageSlots * kLanes * k2DWaves;
-    hipLaunchKernelGGL(k_step2d<float>, grid, block, lds, st,
-                       step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+    launch_timed(k_step2d<float>, grid, block, lds, st, ev0, ev1,
+                 step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
   } else {
     const size_t lds = sizeof(cx<double>) * kStageSlots * kLanes * k2DWaves;
-    hipLaunchKernelGGL(k_step2d<double>, grid, block, lds, st,
-                       step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+    launch_timed(k_step2d<double>, grid, block, lds, st, ev0, ev1,
+                 step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
   }
   return hipGetLastError();
 }
