@@ -39,12 +39,13 @@ OBS_EVERY = 100
 
 # HBM traffic of one k_step1d<float> launch of this workload (4 steps per pass), from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by a 256 MiB device copy
-# measured in the same runs (FETCH_SIZE read 131093 KiB for 262144 KiB copied: x2.000;
-# WRITE_SIZE 262144 KiB: x1.000).  Valid only for the kernel sources it was measured on.
+# measured in the same runs (FETCH_SIZE read 131092.9 KiB for 262144 KiB copied: x2.000;
+# WRITE_SIZE 262144 KiB: x1.000), mean over 111 launches of grid 32768.  Valid only for
+# the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "5026fe6614080adc", "steps_per_pass": 4,
-           "fetch_kib": 890.0, "fetch_scale": 262144.0 / 131093.3, "write_kib": 1280.4, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "d26eba18a9e5bb67", "steps_per_pass": 4,
+           "fetch_kib": 935.0, "fetch_scale": 262144.0 / 131092.9, "write_kib": 1280.4, "write_scale": 1.0}
 
 
 def parse():
@@ -55,7 +56,7 @@ def parse():
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--secondary", choices=["c64", "c128", "none"], default="c128",
                     help="also time the other storage precision of the same workload")
-    ap.add_argument("--cpu-steps", type=int, default=120,
+    ap.add_argument("--cpu-steps", type=int, default=500,
                     help="steps of the oracle sample for cpu_baseline (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=500,
                     help="steps of the batched-vs-one-at-a-time comparison (0 = skip)")
