@@ -97,10 +97,13 @@ typedef struct qlg_obs {
 
 /* Launch plan of the fused step; chosen by qlg_autotune or set by the caller. */
 typedef struct qlg_tuning {
-  int32_t steps_per_pass; /* 1D: steps fused per HBM pass (1..4); 2D: must be 1 */
+  int32_t steps_per_pass; /* 1D: steps fused per HBM pass (1..7; 4 S halo sites per side
+                             of each 64-site tile); 2D: must be 1 */
   int32_t tile_rows;      /* 2D: rows per streaming tile (8..256); 1D: ignored */
   int32_t use_graph;      /* 1: replay qlg_step's launches from a captured hipGraph */
-  int32_t reserved;
+  int32_t pair_waves;     /* 1D: 1 = the two qubit amplitudes of a tile on two wavefronts
+                             (twice the SIMDs for lattices too small to fill the chip);
+                             2D: must be 0 */
 } qlg_tuning;
 
 typedef struct qlg_ctx qlg_ctx;
@@ -133,12 +136,26 @@ qlg_status qlg_get_qubits(qlg_ctx* ctx, void* qubits_dev);
 /* Advance every instance by nsteps >= 0 QLG steps (Sec. VII), asynchronously. */
 qlg_status qlg_step(qlg_ctx* ctx, int64_t nsteps);
 
-/* Norms, populations, energy and (if the last qlg_step call ended with a
- * single-step pass) the overlap energy, per instance, into out_host[nbatch].
- * Synchronises the stream.  Returns QLG_ERR_NUMERIC (after filling out_host)
- * if any value is non-finite or |norm_q / norm_q(at set) - 1| exceeds 1e-4
- * (C64) or 1e-10 (C128). */
+/* Norms, populations, energy (Sec. II energy functional on the lattice) and,
+ * once a qlg_step call has run since the last set, the overlap energy of the
+ * last step (Sec. IV), per instance, into out_host[nbatch].  Synchronises the
+ * stream.  Returns QLG_ERR_NUMERIC (after filling out_host) if any value is
+ * non-finite or |norm_q / norm_q(at set) - 1| exceeds 1e-4 (C64) or 1e-10 (C128). */
 qlg_status qlg_observables(qlg_ctx* ctx, qlg_obs* out_host);
+
+/* Observables without a host round trip, for diagnostics every k steps of a
+ * long run.  qlg_record_observables enqueues the reductions of the current
+ * state into rec_dev (device memory owned by the caller, at least
+ * QLG_RECORD_DOUBLES * nbatch doubles, 8-byte aligned) and returns at once;
+ * the record holds the FP64 sums, the step count and the reference norm, so it
+ * can be decoded at any later time.  qlg_decode_records turns nrec consecutive
+ * records (rec_host[nrec][nbatch][QLG_RECORD_DOUBLES], host memory) into
+ * out_host[nrec][nbatch] with exactly the values and checks of qlg_observables
+ * (QLG_ERR_NUMERIC if any record fails them).  Both are host-side only apart
+ * from the kernels the first enqueues. */
+#define QLG_RECORD_DOUBLES 16
+qlg_status qlg_record_observables(qlg_ctx* ctx, double* rec_dev);
+qlg_status qlg_decode_records(qlg_ctx* ctx, const double* rec_host, int64_t nrec, qlg_obs* out_host);
 
 /* Plan control.  qlg_autotune times the candidate plans on the context's own
  * lattice without changing its state and keeps the fastest. */

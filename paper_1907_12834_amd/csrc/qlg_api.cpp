@@ -24,7 +24,7 @@ namespace {
 
 constexpr int64_t kMaxExtent = int64_t(1) << 30;
 constexpr int64_t kMaxSites = (int64_t(1) << 31) - 1;
-constexpr int kMaxSteps1D = 4;
+constexpr int kMaxSteps1D = 7;   // 4 * S halo sites per side must leave interior lanes
 constexpr int kMinTileRows = 8, kMaxTileRows = 256;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -98,7 +98,7 @@ Layout make_layout(const qlg_params* p) {
 }
 
 struct ScratchLayout {
-  size_t obs_part, obs_res, norm0, ov_part, ov_res, total;  // byte offsets
+  size_t obs_part, obs_res, norm0, ov_part, total;  // byte offsets
 };
 
 ScratchLayout scratch_layout(const Layout& L, int nbatch) {
@@ -106,10 +106,9 @@ ScratchLayout scratch_layout(const Layout& L, int nbatch) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
   s.obs_part = take(sizeof(double) * qlg::kNObs * (size_t)std::max(L.nchunks, 1));
-  s.obs_res = take(sizeof(double) * qlg::kNObs * nbatch);
-  s.norm0 = take(sizeof(double) * qlg::kNObs * nbatch);
+  s.obs_res = take(sizeof(double) * qlg::kRecord * nbatch);   // one observables record
+  s.norm0 = take(sizeof(double) * qlg::kRecord * nbatch);     // record of the state at set time
   s.ov_part = take(sizeof(double) * 2 * (size_t)std::max(L.max_tiles, 1));
-  s.ov_res = take(sizeof(double) * 2 * nbatch);
   s.total = o;
   return s;
 }
@@ -233,7 +232,8 @@ hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void
   double* ov = c->sc(c->S.ov_part);
   const bool plain = c->p.split == QLG_SPLIT_PLAIN;
   if (c->p.ndim == 1)
-    return qlg::launch_step1d(c->p.dtype, steps, plain, overlap, in, out, g, th * c->p.g0, th * c->p.g1,
+    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.pair_waves != 0, plain, overlap, in, out, g,
+                              th * c->p.g0, th * c->p.g1,
                               th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
   return qlg::launch_step2d(c->p.dtype, plain, overlap, c->tuning.tile_rows, in, out, g, th * c->p.g0,
                             th * c->p.g1, th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
@@ -382,13 +382,24 @@ void qlg_destroy(qlg_ctx* c) {
   delete c;
 }
 
+// Enqueue the observables record of the current state into rec (device).
+static qlg_status enqueue_record(qlg_ctx* c, double* rec, bool reference) {
+  const LaunchGeom g = c->geom();
+  hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), g, c->p.g0, c->p.g1, c->p.g2,
+                                         c->sc(c->S.obs_part), c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "observables kernel");
+  const double* ov = (!reference && c->has_overlap) ? c->sc(c->S.ov_part) : nullptr;
+  const double* ref = (!reference && c->norm0_valid) ? c->sc(c->S.norm0) : nullptr;
+  e = qlg::launch_record(g, c->sc(c->S.obs_part), ov, ref, rec, c->step_count, c->stream);
+  return e == hipSuccess ? QLG_OK : hip_check(c, e, "observables record kernel");
+}
+
 static qlg_status after_set(qlg_ctx* c) {
   c->step_count = 0;
   c->has_overlap = false;
-  // reference norm for the drift check, kept on the device
-  hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), c->geom(), c->p.g0, c->p.g1,
-                                         c->p.g2, c->sc(c->S.obs_part), c->sc(c->S.norm0), c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "observables kernel");
+  // reference record (qubit norm at set time) for the drift check, kept on the device
+  qlg_status s = enqueue_record(c, c->sc(c->S.norm0), true);
+  if (s) return s;
   c->norm0_valid = true;
   return QLG_OK;
 }
@@ -492,56 +503,72 @@ qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
   return QLG_OK;
 }
 
-qlg_status qlg_observables(qlg_ctx* c, qlg_obs* out) {
-  qlg_status s = check_ctx(c);
-  if (s) return s;
-  if (!out) return fail(c, QLG_ERR_ARG, "out is NULL");
-  const LaunchGeom g = c->geom();
-  hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), g, c->p.g0, c->p.g1, c->p.g2,
-                                         c->sc(c->S.obs_part), c->sc(c->S.obs_res), c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "observables kernel");
-  if (c->has_overlap) {
-    e = qlg::launch_overlap_reduce(g, c->sc(c->S.ov_part), c->sc(c->S.ov_res), c->stream);
-    if (e != hipSuccess) return hip_check(c, e, "overlap reduce kernel");
-  }
+// Host decoding of nrec records of nbatch instances; false if any is non-finite
+// or drifted.
+static bool decode_records(const qlg_ctx* c, const double* rec, int64_t nrec, qlg_obs* out) {
   const int nb = c->p.nbatch;
-  std::vector<double> res((size_t)nb * qlg::kNObs), n0((size_t)nb * qlg::kNObs), ov((size_t)nb * 2, 0.0);
-  e = hipMemcpyAsync(res.data(), c->sc(c->S.obs_res), res.size() * 8, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess && c->norm0_valid)
-    e = hipMemcpyAsync(n0.data(), c->sc(c->S.norm0), n0.size() * 8, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess && c->has_overlap)
-    e = hipMemcpyAsync(ov.data(), c->sc(c->S.ov_res), ov.size() * 8, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "copy observables");
   const double meas = std::pow(c->p.eps, c->p.ndim);
   const double tol = c->p.dtype == QLG_C64 ? 1e-4 : 1e-10;
   bool bad = false;
-  for (int i = 0; i < nb; ++i) {
-    const double* r = &res[(size_t)i * qlg::kNObs];
-    qlg_obs& o = out[i];
+  for (int64_t k = 0; k < nrec * nb; ++k) {
+    const double* r = rec + (size_t)k * qlg::kRecord;
+    qlg_obs& o = out[k];
     std::memset(&o, 0, sizeof o);
     o.norm_q = meas * r[0];
     o.norm_psi = meas * r[1];
     for (int m = 0; m < 5; ++m) o.pop[m] = meas * r[2 + m];
     o.energy = meas * (r[7] / (c->p.eps * c->p.eps) + r[8]);
-    o.step = c->step_count;
-    o.has_overlap = c->has_overlap ? 1 : 0;
-    if (c->has_overlap) {
-      o.overlap_re = meas * ov[2 * i];
-      o.overlap_im = meas * ov[2 * i + 1];
+    o.step = (int64_t)r[qlg::kNObs + 3];
+    const int flags = (int)r[qlg::kNObs + 4];
+    o.has_overlap = (flags & 1) ? 1 : 0;
+    if (o.has_overlap) {
+      o.overlap_re = meas * r[qlg::kNObs];
+      o.overlap_im = meas * r[qlg::kNObs + 1];
       const double nn = o.norm_psi;
       if (nn > 0) {   // i (nn - ov) / nn
         o.e_overlap_re = o.overlap_im / nn;
         o.e_overlap_im = (nn - o.overlap_re) / nn;
       }
     }
-    for (int k = 0; k < qlg::kNObs; ++k) bad |= !std::isfinite(r[k]);
-    if (c->norm0_valid && n0[(size_t)i * qlg::kNObs] > 0) {
-      const double drift = r[0] / n0[(size_t)i * qlg::kNObs] - 1.0;
+    for (int j = 0; j < qlg::kNObs; ++j) bad |= !std::isfinite(r[j]);
+    const double ref = r[qlg::kNObs + 2];
+    if ((flags & 2) && ref > 0) {
+      const double drift = r[0] / ref - 1.0;
       bad |= !(std::fabs(drift) <= tol);
     }
   }
-  if (bad) return fail(c, QLG_ERR_NUMERIC, "non-finite observable or qubit-norm drift above threshold");
+  return !bad;
+}
+
+qlg_status qlg_observables(qlg_ctx* c, qlg_obs* out) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!out) return fail(c, QLG_ERR_ARG, "out is NULL");
+  s = enqueue_record(c, c->sc(c->S.obs_res), false);
+  if (s) return s;
+  std::vector<double> rec((size_t)c->p.nbatch * qlg::kRecord);
+  hipError_t e = hipMemcpyAsync(rec.data(), c->sc(c->S.obs_res), rec.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "copy observables");
+  if (!decode_records(c, rec.data(), 1, out))
+    return fail(c, QLG_ERR_NUMERIC, "non-finite observable or qubit-norm drift above threshold");
+  return QLG_OK;
+}
+
+qlg_status qlg_record_observables(qlg_ctx* c, double* rec_dev) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!rec_dev) return fail(c, QLG_ERR_ARG, "rec_dev is NULL");
+  return enqueue_record(c, rec_dev, false);
+}
+
+qlg_status qlg_decode_records(qlg_ctx* c, const double* rec_host, int64_t nrec, qlg_obs* out_host) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (nrec < 0) return fail(c, QLG_ERR_ARG, "nrec must be >= 0");
+  if (nrec > 0 && (!rec_host || !out_host)) return fail(c, QLG_ERR_ARG, "rec_host or out_host is NULL");
+  if (!decode_records(c, rec_host, nrec, out_host))
+    return fail(c, QLG_ERR_NUMERIC, "non-finite observable or qubit-norm drift above threshold");
   return QLG_OK;
 }
 
@@ -551,10 +578,12 @@ qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
   if (!t) return fail(c, QLG_ERR_ARG, "tuning is NULL");
   qlg_tuning n = *t;
   if (c->p.ndim == 1) {
-    if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..4 in 1D");
+    if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..7 in 1D");
+    if (n.pair_waves != 0 && n.pair_waves != 1) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 or 1");
     n.tile_rows = 0;
   } else {
     if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D");
+    if (n.pair_waves != 0) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 in 2D");
     if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return fail(c, QLG_ERR_ARG, "tile_rows must be 8..256");
   }
   n.use_graph = n.use_graph ? 1 : 0;
@@ -573,9 +602,28 @@ qlg_status qlg_autotune(qlg_ctx* c) {
   if (s) return s;
   std::vector<qlg_tuning> cand;
   if (c->p.ndim == 1)
-    for (int S = 1; S <= kMaxSteps1D; ++S) cand.push_back(qlg_tuning{S, 0, c->tuning.use_graph, 0});
-  else
-    for (int r : {16, 32, 64, 128}) cand.push_back(qlg_tuning{1, r, c->tuning.use_graph, 0});
+    for (int pair = 0; pair <= 1; ++pair)
+      for (int S = 1; S <= (pair ? 4 : kMaxSteps1D); ++S) cand.push_back(qlg_tuning{S, 0, c->tuning.use_graph, pair});
+  else {
+    // powers of two, plus the smallest band heights whose tile count fits k waves per SIMD
+    // (k = 1..4): fewer halo rows without a tail of SIMDs that hold one wave more
+    std::vector<int> rows = {16, 32, 64, 128};
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    const int64_t nsimd = 4 * (int64_t)cus;
+    auto ntiles = [&](int r) {
+      int64_t t = 0;
+      for (const auto& d : c->L.inst) { int a, b; tiles_2d(d.nx, d.ny, r, &a, &b); t += (int64_t)a * b; }
+      return t;
+    };
+    for (int k = 1; k <= 4 && nsimd > 0; ++k) {
+      int r = kMinTileRows;
+      while (r < kMaxTileRows && ntiles(r) > k * nsimd) ++r;
+      if (ntiles(r) <= k * nsimd && std::find(rows.begin(), rows.end(), r) == rows.end()) rows.push_back(r);
+    }
+    for (int r : rows) cand.push_back(qlg_tuning{1, r, c->tuning.use_graph, 0});
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(c, QLG_ERR_DEVICE, "event create");
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(c, QLG_ERR_DEVICE, "event create"); }

@@ -23,6 +23,7 @@ struct InstDesc {
 
 constexpr int kChunk = 256;      // sites per chunk of the elementwise / reduction kernels
 constexpr int kNObs = 10;        // norm_q, norm_psi, pop[5], e_kin, e_pot, spare
+constexpr int kRecord = 16;      // doubles per instance in an observables record
 constexpr int kLanes = 64;       // wavefront width on gfx950
 constexpr int kHalo2D = 4;       // x halo of the 2D kernel (4 I' per axis per step)
 constexpr int kValid2D = kLanes - 2 * kHalo2D;
@@ -37,7 +38,8 @@ struct LaunchGeom {
 // Kernel launchers (qlg_kernels.hip).  All return the hipError_t of the launch.
 // dtype: 0 = complex64, 1 = complex128.  Angles are theta*g0, theta*g1, theta*g2/5.
 // ev0/ev1 (optional): events the dispatch packet itself stamps at kernel start/end.
-hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
+// pair: the k_step1d_pair variant (a and b of a tile on two wavefronts).
+hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
                          hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
@@ -47,10 +49,12 @@ hipError_t launch_set_psi(int dtype, const void* psi, void* state, const LaunchG
 hipError_t launch_get_psi(int dtype, const void* state, void* psi, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_set_qubits(int dtype, const void* qb, void* state, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_get_qubits(int dtype, const void* state, void* qb, const LaunchGeom& g, hipStream_t st);
-// Per-instance sums of the kNObs observables into res[nbatch][kNObs] (unscaled sums).
+// Per-chunk partial sums of the kNObs observables into part[nchunks][kNObs].
 hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
-                              double g1, double g2, double* part, double* res, hipStream_t st);
-// Per-instance sums of the per-tile overlap partials into res[nbatch][2].
-hipError_t launch_overlap_reduce(const LaunchGeom& g, const double* ovpart, double* res, hipStream_t st);
+                              double g1, double g2, double* part, hipStream_t st);
+// Per-instance record rec[nbatch][kRecord] from the chunk partials, the per-tile
+// overlap partials (ovpart may be null) and a reference record (ref may be null).
+hipError_t launch_record(const LaunchGeom& g, const double* part, const double* ovpart, const double* ref,
+                         double* rec, int64_t step, hipStream_t st);
 
 }  // namespace qlg

@@ -20,37 +20,63 @@
 
 #include <hip/hip_ext.h>
 
+#include <cmath>
+
 #include "qlg_internal.hpp"
 #include "qlg_math.hpp"
 
 namespace qlg {
 
-template <typename T>
-__device__ __forceinline__ cx<T> shfl_from_next(cx<T> v) {   // value of lane + 1
-  return cx<T>{__shfl_down(v.re, 1, kLanes), __shfl_down(v.im, 1, kLanes)};
+// Whole-wavefront moves by one lane through DPP (wave_shl:1, wave_shr:1, both
+// available on CDNA): a VALU operation that the compiler can fold into the
+// arithmetic that consumes it, instead of a round trip through the LDS
+// crossbar.  The end lane, always a halo lane here, reads 0.
+constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i + 1
+constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i - 1
+
+template <int Ctrl>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true));
+}
+template <int Ctrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, Ctrl, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), Ctrl, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 template <typename T>
-__device__ __forceinline__ cx<T> shfl_from_prev(cx<T> v) {   // value of lane - 1
-  return cx<T>{__shfl_up(v.re, 1, kLanes), __shfl_up(v.im, 1, kLanes)};
+__device__ __forceinline__ cx<T> from_next_lane(cx<T> v) {
+  return cx<T>{dpp_move<kDppWaveShl1>(v.re), dpp_move<kDppWaveShl1>(v.im)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> from_prev_lane(cx<T> v) {
+  return cx<T>{dpp_move<kDppWaveShr1>(v.re), dpp_move<kDppWaveShr1>(v.im)};
 }
 
-// I'_{x,q} = S_q C S_q^T C with lanes along x.  Q = 1: qubit b (the paper's
-// qubit 2) moves; Q = 0: qubit a (qubit 1).
+// 4 I'_{x,q} = S_q (2C) S_q^T (2C) with lanes along x (the factor 1/4 is left to
+// the caller).  Q = 1: qubit b (the paper's qubit 2) moves; Q = 0: qubit a (qubit 1).
 template <typename T, int Q>
-__device__ __forceinline__ void iprime_lanes(cx<T> (&a)[5], cx<T> (&b)[5]) {
+__device__ __forceinline__ void iprime4_lanes(cx<T> (&a)[5], cx<T> (&b)[5]) {
   collide2(a, b);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {   // S^T: q(x) <- q(x + 1)
-    if (Q) b[m] = shfl_from_next(b[m]);
-    else   a[m] = shfl_from_next(a[m]);
+    if (Q) b[m] = from_next_lane(b[m]);
+    else   a[m] = from_next_lane(a[m]);
   }
   collide2(a, b);
-  scale_quarter(a, b);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {   // S: q(x) <- q(x - 1)
-    if (Q) b[m] = shfl_from_prev(b[m]);
-    else   a[m] = shfl_from_prev(a[m]);
+    if (Q) b[m] = from_prev_lane(b[m]);
+    else   a[m] = from_prev_lane(a[m]);
   }
+}
+
+// Angles of interleaved substep j = 0..3 of a four-I' sequence, on a state that
+// carries the factor 4^j of the j I' before it (uniform selects, no indexing).
+template <typename T>
+__device__ __forceinline__ Angles<T> substep_angles(const Angles<T> (&t)[4], int j) {
+  return j == 0 ? t[0] : j == 1 ? t[1] : j == 2 ? t[2] : t[3];
 }
 
 __device__ __forceinline__ int64_t wrap64(int64_t x, int64_t n) {
@@ -73,8 +99,9 @@ struct StepArgs {
   const InstDesc* __restrict__ inst;
   const int32_t* __restrict__ tile2inst;
   double* __restrict__ ovpart;   // [ntiles][2] overlap partials (written when overlap != 0)
-  Angles<T> ang;                 // interleaved U^{1/(4d)}: theta = eps^2 / (4 d)
-  Angles<T> ang_full;            // plain split: theta = eps^2
+  Angles<T> ang[4];              // interleaved U^{1/(4d)}, theta = eps^2 / (4 d), for a state
+                                 // scaled by 4^j (substep j of a four-I' sequence)
+  Angles<T> ang_full;            // plain split: theta = eps^2, unscaled state
   int32_t ntiles;
   int32_t steps;                 // 1D: steps fused in this pass
   int32_t tile_rows;             // 2D: rows per streaming tile
@@ -107,11 +134,11 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
     b[m] = src[(5 + m) * d.stride];
   }
   const bool plain = A.plain != 0;
-  const Angles<T> an{plain ? A.ang_full.tg0 : A.ang.tg0, plain ? A.ang_full.tg1 : A.ang.tg1,
-                     plain ? A.ang_full.tg25 : A.ang.tg25};
   cx<T> pold[5];
   // one step: [U] I'_{x,b} [U] I'_{x,b} [U] I'_{x,a} [U] I'_{x,a}; the moving qubit is
-  // a compile-time parameter of each inner loop
+  // a compile-time parameter of each inner loop.  The four I' factors 1/4 are
+  // applied together at the end of the step (exact); U in between sees the state
+  // scaled by 4^j and compensates through its angles.
 #pragma unroll 1
   for (int st = 0; st < A.steps; ++st) {
     if (A.overlap && st == A.steps - 1) {
@@ -120,14 +147,15 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
     }
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain || j == 0) potential(a, b, an);
-      iprime_lanes<T, 1>(a, b);
+      if (!plain || j == 0) potential(a, b, plain ? A.ang_full : substep_angles(A.ang, j));
+      iprime4_lanes<T, 1>(a, b);
     }
 #pragma unroll 1
-    for (int j = 0; j < 2; ++j) {
-      if (!plain) potential(a, b, an);
-      iprime_lanes<T, 0>(a, b);
+    for (int j = 2; j < 4; ++j) {
+      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      iprime4_lanes<T, 0>(a, b);
     }
+    scale_by(a, b, T(1.0 / 256.0));
   }
   const bool valid = lane >= H && lane < kLanes - H && x < L;
   if (valid) {
@@ -158,6 +186,152 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// 1D fused step, qubit pair on two wavefronts
+// ---------------------------------------------------------------------------
+// Same tiles and schedule as k_step1d, but a tile's a (the paper's qubit 1) and
+// b (qubit 2) live on two wavefronts (even and odd wave of the workgroup; two
+// tiles per workgroup of four waves), so a lattice too small to fill the chip
+// runs on twice as many SIMDs with about 0.7x the per-lane work.  The partner
+// amplitudes come through LDS.
+//
+// Each substep U I'_{x,Q} is evaluated as C U S^T C then S: the collide
+// commutes with U (it mixes a and b with scalar weights, and W acts on the m
+// index of both alike) and leaves psi = a + b unchanged, so the first collide
+// and the coefficients of W share one exchange, and the second collide takes
+// the other.  In exact arithmetic the result is the step of k_step1d.
+//
+// own' of the unnormalised collide, on either wave: with s = own + other and
+// e = own - other, own' = (s_re + e_im, s_im - e_re).  For own = a this is 2a',
+// for own = b (e = -(a - b) exactly) it is 2b'.
+template <typename T>
+__device__ __forceinline__ void collide_own(cx<T> (&x)[5], const cx<T> (&y)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const T sr = x[m].re + y[m].re, si = x[m].im + y[m].im;
+    const T er = x[m].re - y[m].re, ei = x[m].im - y[m].im;
+    x[m] = cx<T>{sr + ei, si - er};
+  }
+}
+
+constexpr int kPairTiles = 2;                 // tiles per pair workgroup
+constexpr int kPairWaves = 2 * kPairTiles;    // wavefronts per pair workgroup
+
+// LDS exchange between the two wavefronts of a tile: double-buffered, one
+// workgroup barrier per exchange (the buffer written now was last read before
+// the previous barrier).  Wave v of the workgroup owns slot v; its partner is v ^ 1.
+template <typename T>
+struct PairXchg {
+  T (*buf)[kPairWaves][10][kLanes];
+  int q, v, lane, cur;
+  __device__ __forceinline__ void swap(const cx<T> (&own)[5], cx<T> (&other)[5]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      buf[cur][v][2 * m][lane] = own[m].re;
+      buf[cur][v][2 * m + 1][lane] = own[m].im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 5; ++m) other[m] = cx<T>{buf[cur][v ^ 1][2 * m][lane], buf[cur][v ^ 1][2 * m + 1][lane]};
+    cur ^= 1;
+  }
+};
+
+// One substep [U] I'_{x,Q} on this wave's qubit x (Q: qubit that streams).
+template <typename T, int Q>
+__device__ __forceinline__ void pair_substep(cx<T> (&x)[5], PairXchg<T>& X, bool with_u, const Angles<T>& ang) {
+  cx<T> y[5];
+  X.swap(x, y);
+  if (with_u) {
+    WCoef<T> W;
+    w_coefficients(x, y, ang, W);   // psi = x + y, the same sum on both waves
+    collide_own(x, y);
+    w_apply(x, W);
+  } else {
+    collide_own(x, y);
+  }
+  const bool moves = X.q == Q;      // uniform per wavefront
+  if (moves) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) x[m] = from_next_lane(x[m]);   // S^T
+  }
+  X.swap(x, y);
+  collide_own(x, y);
+  if (moves) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) x[m] = from_prev_lane(x[m]);   // S
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T> A) {
+  __shared__ T xbuf[2][kPairWaves][10][kLanes];
+  // Every wave of the workgroup takes part in every barrier: a workgroup whose
+  // second tile lies past the end recomputes the last tile and stores nothing.
+  const int v = threadIdx.x >> 6;
+  const int q = v & 1;
+  const int lane = threadIdx.x & (kLanes - 1);
+  const int wt = blockIdx.x * kPairTiles + (v >> 1);
+  const bool real = wt < A.ntiles;
+  const int w = real ? wt : A.ntiles - 1;
+  const InstDesc d = A.inst[A.tile2inst[w]];
+  const int H = 4 * A.steps;
+  const int TV = kLanes - 2 * H;
+  const int64_t L = d.nx;
+  const int64_t x0 = (int64_t)(w - d.tile_begin) * TV - H + lane;
+  const int64_t xw = wrap64(x0, L);
+  const cx<T>* src = A.in + d.off + (int64_t)(5 * q) * d.stride + xw;
+  cx<T> x[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) x[m] = src[m * d.stride];
+  PairXchg<T> X{xbuf, q, v, lane, 0};
+  const bool plain = A.plain != 0;
+  cx<T> pold[5];
+#pragma unroll 1
+  for (int st = 0; st < A.steps; ++st) {
+    if (A.overlap && st == A.steps - 1) {
+      cx<T> y[5];
+      X.swap(x, y);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) pold[m] = x[m] + y[m];
+    }
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j)
+      pair_substep<T, 1>(x, X, !plain || j == 0, plain ? A.ang_full : substep_angles(A.ang, j));
+#pragma unroll 1
+    for (int j = 2; j < 4; ++j) pair_substep<T, 0>(x, X, !plain, substep_angles(A.ang, j));
+#pragma unroll
+    for (int m = 0; m < 5; ++m) x[m] = T(1.0 / 256.0) * x[m];
+  }
+  const bool valid = real && lane >= H && lane < kLanes - H && x0 < L;
+  if (valid) {
+    cx<T>* dst = A.out + d.off + (int64_t)(5 * q) * d.stride + x0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) dst[m * d.stride] = x[m];
+  }
+  if (A.overlap) {
+    cx<T> y[5];
+    X.swap(x, y);
+    if (q == 0 && real) {
+      double ore = 0.0, oim = 0.0;
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const cx<T> c = cmulc(x[m] + y[m], pold[m]);   // conj(psi_t) psi_{t-1}
+          ore += (double)c.re;
+          oim += (double)c.im;
+        }
+      }
+      ore = wave_sum(ore);
+      oim = wave_sum(oim);
+      if (lane == 0) {
+        A.ovpart[2 * w] = ore;
+        A.ovpart[2 * w + 1] = oim;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 2D fused step: y half as a 4-stage register pipeline along rows, x half across lanes
 // ---------------------------------------------------------------------------
 // Stage k of the y half is [U] I'_{y,q}, q = b, b, a, a.  The streaming row
@@ -174,8 +348,7 @@ __device__ __forceinline__ void y_stage_core(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>
     if (Q) { ta[m] = cn[m]; tb[m] = b[m]; cn[m] = a[m]; }
     else   { ta[m] = a[m]; tb[m] = cn[m]; cn[m] = b[m]; }
   }
-  collide2(ta, tb);                   // m(r-1)
-  scale_quarter(ta, tb);
+  collide2(ta, tb);                   // m(r-1), times 4
 #pragma unroll
   for (int m = 0; m < 5; ++m) {       // out(r-1) = (m(r-1).nonq, m(r-2).q)  [S: q(y) <- q(y-1)]
     if (Q) { a[m] = ta[m]; b[m] = mq[m]; mq[m] = tb[m]; }
@@ -223,8 +396,6 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   const int y0 = ty * A.tile_rows;
   const bool xvalid = lane >= kHalo2D && lane < kLanes - kHalo2D && x < nx;
   const bool plain = A.plain != 0;
-  const Angles<T> an{plain ? A.ang_full.tg0 : A.ang.tg0, plain ? A.ang_full.tg1 : A.ang.tg1,
-                     plain ? A.ang_full.tg25 : A.ang.tg25};
 #pragma unroll
   for (int j = 0; j < kStageSlots; ++j) my[j * kLanes] = cx<T>{T(0), T(0)};
 
@@ -242,30 +413,33 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
     }
     // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y; slot k of this lane's LDS
     // holds stage k's pending rows.  The plain split applies its single U at stage 0.
+    // Stage k leaves its output times 4 (the factor 1/4 of its I' is deferred): all
+    // rows pass the same stages, so pending and streaming rows carry the same
+    // scale; one exact multiplication by 1/256 ends each half.
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain || j == 0) potential(a, b, an);
+      if (!plain || j == 0) potential(a, b, plain ? A.ang_full : substep_angles(A.ang, j));
       y_stage_lds<T, 1>(a, b, my + j * 10 * kLanes);
     }
 #pragma unroll 1
     for (int j = 2; j < 4; ++j) {
-      if (!plain) potential(a, b, an);
+      if (!plain) potential(a, b, substep_angles(A.ang, j));
       y_stage_lds<T, 0>(a, b, my + j * 10 * kLanes);
     }
-    // x half for rows that have left the y pipeline complete (r >= 8)
-    if (r >= 8) {
-#pragma unroll 1
-      for (int j = 0; j < 2; ++j) {
-        if (!plain) potential(a, b, an);
-        iprime_lanes<T, 1>(a, b);
-      }
-#pragma unroll 1
-      for (int j = 0; j < 2; ++j) {
-        if (!plain) potential(a, b, an);
-        iprime_lanes<T, 0>(a, b);
-      }
-    }
     if (r < 8) continue;
+    // x half for rows that have left the y pipeline complete (r >= 8)
+    scale_by(a, b, T(1.0 / 256.0));
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j) {
+      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      iprime4_lanes<T, 1>(a, b);
+    }
+#pragma unroll 1
+    for (int j = 2; j < 4; ++j) {
+      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      iprime4_lanes<T, 0>(a, b);
+    }
+    scale_by(a, b, T(1.0 / 256.0));
     const int yo = y0 - 8 + r;           // row leaving the pipeline
     if (xvalid && yo < ny) {
       const int64_t o = d.off + (int64_t)yo * nx + x;
@@ -458,9 +632,15 @@ __global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict_
   block_sum_store(v, part + (int64_t)blockIdx.x * kNObs);
 }
 
-// One block per instance: sum its chunk partials in a fixed order.
-__global__ __launch_bounds__(kChunk) void k_reduce_obs(LaunchGeom g, const double* __restrict__ part,
-                                                      double* __restrict__ res) {
+// One block per instance: its observables record, every sum in a fixed order.
+//   rec[i][0..9]  observable sums (kNObs), rec[i][10..11] overlap sums,
+//   rec[i][12]    reference qubit-norm sum, rec[i][13] step count,
+//   rec[i][14]    flags (1: overlap valid, 2: reference valid), rec[i][15] = 0.
+__global__ __launch_bounds__(kChunk) void k_reduce_record(LaunchGeom g, const double* __restrict__ part,
+                                                         const double* __restrict__ ovpart,
+                                                         const double* __restrict__ ref,
+                                                         double* __restrict__ rec, double step) {
+  __shared__ double sums[kNObs], ovs[kNObs];
   const InstDesc d = g.inst[blockIdx.x];
   double v[kNObs];
 #pragma unroll
@@ -470,25 +650,27 @@ __global__ __launch_bounds__(kChunk) void k_reduce_obs(LaunchGeom g, const doubl
 #pragma unroll
     for (int k = 0; k < kNObs; ++k) v[k] += p[k];
   }
-  block_sum_store(v, res + (int64_t)blockIdx.x * kNObs);
-}
-
-__global__ __launch_bounds__(kChunk) void k_reduce_ov(LaunchGeom g, const double* __restrict__ ovpart,
-                                                     double* __restrict__ res) {
-  const InstDesc d = g.inst[blockIdx.x];
-  double v[kNObs];
+  block_sum_store(v, sums);
+  __syncthreads();   // block_sum_store's own LDS is reused below
 #pragma unroll
   for (int k = 0; k < kNObs; ++k) v[k] = 0.0;
-  const int nt = d.ntx * d.nty;
-  for (int t = threadIdx.x; t < nt; t += kChunk) {
-    v[0] += ovpart[2 * (d.tile_begin + t)];
-    v[1] += ovpart[2 * (d.tile_begin + t) + 1];
+  if (ovpart) {
+    const int nt = d.ntx * d.nty;
+    for (int t = threadIdx.x; t < nt; t += kChunk) {
+      v[0] += ovpart[2 * (d.tile_begin + t)];
+      v[1] += ovpart[2 * (d.tile_begin + t) + 1];
+    }
   }
-  __shared__ double tmp[kNObs];
-  double* dst = tmp;
-  block_sum_store(v, dst);
+  block_sum_store(v, ovs);
   __syncthreads();
-  if (threadIdx.x < 2) res[2 * blockIdx.x + threadIdx.x] = tmp[threadIdx.x];
+  double* r = rec + (int64_t)blockIdx.x * kRecord;
+  const int k = threadIdx.x;
+  if (k < kNObs) r[k] = sums[k];
+  else if (k < kNObs + 2) r[k] = ovs[k - kNObs];
+  else if (k == kNObs + 2) r[k] = ref ? ref[(int64_t)blockIdx.x * kRecord] : 0.0;
+  else if (k == kNObs + 3) r[k] = step;
+  else if (k == kNObs + 4) r[k] = (ovpart ? 1.0 : 0.0) + (ref ? 2.0 : 0.0);
+  else if (k < kRecord) r[k] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -509,7 +691,13 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
   A.inst = g.inst;
   A.tile2inst = g.tile2inst;
   A.ovpart = ovpart;
-  A.ang = angles<T>(tg0, tg1, tg25);
+  for (int j = 0; j < 4; ++j) {   // state scaled by 4^j: theta n and theta F unchanged
+    const T f = T(std::ldexp(1.0, -4 * j));
+    A.ang[j] = angles<T>(tg0, tg1, tg25);
+    A.ang[j].tg0 *= f;
+    A.ang[j].tg25 *= f;
+    A.ang[j].fs = f;
+  }
   A.ang_full = angles<T>(full_factor * tg0, full_factor * tg1, full_factor * tg25);
   A.ntiles = g.ntiles;
   A.steps = steps;
@@ -529,13 +717,23 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
     hipLaunchKernelGGL(kernel, grid, block, lds, st, args);
 }
 
-hipError_t launch_step1d(int dtype, int steps, bool plain, bool overlap, const void* in, void* out,
+hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
   if (steps < 1 || 8 * steps >= kLanes) return hipErrorInvalidValue;
-  const dim3 grid((g.ntiles + 3) / 4), block(256);
   // the plain split's single U uses theta = eps^2 = 4x the interleaved 1D angle
+  if (pair) {
+    const dim3 grid((g.ntiles + kPairTiles - 1) / kPairTiles), block(kLanes * kPairWaves);
+    if (dtype == 0)
+      launch_timed(k_step1d_pair<float>, grid, block, 0, st, ev0, ev1,
+                   step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+    else
+      launch_timed(k_step1d_pair<double>, grid, block, 0, st, ev0, ev1,
+                   step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+    return hipGetLastError();
+  }
+  const dim3 grid((g.ntiles + 3) / 4), block(256);
   if (dtype == 0)
     launch_timed(k_step1d<float>, grid, block, 0, st, ev0, ev1,
                  step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
@@ -582,21 +780,20 @@ QLG_ELEMWISE(launch_set_qubits, k_set_qubits, const void*, void*)
 QLG_ELEMWISE(launch_get_qubits, k_get_qubits, const void*, void*)
 
 hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
-                              double g1, double g2, double* part, double* res, hipStream_t st) {
+                              double g1, double g2, double* part, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_observables<float>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<float>*)state,
                        g, ndim, g0, g1, g2, part);
   else
     hipLaunchKernelGGL(k_observables<double>, dim3(g.nchunks), dim3(kChunk), 0, st,
                        (const cx<double>*)state, g, ndim, g0, g1, g2, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_obs, dim3(g.nbatch), dim3(kChunk), 0, st, g, (const double*)part, res);
   return hipGetLastError();
 }
 
-hipError_t launch_overlap_reduce(const LaunchGeom& g, const double* ovpart, double* res, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_ov, dim3(g.nbatch), dim3(kChunk), 0, st, g, ovpart, res);
+hipError_t launch_record(const LaunchGeom& g, const double* part, const double* ovpart, const double* ref,
+                         double* rec, int64_t step, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_record, dim3(g.nbatch), dim3(kChunk), 0, st, g, part, ovpart, ref, rec,
+                     (double)step);
   return hipGetLastError();
 }
 

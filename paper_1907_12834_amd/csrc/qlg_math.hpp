@@ -107,13 +107,20 @@ QLG_HD double rcp_t(double x) { return 1.0 / x; }
 template <typename T>
 struct Angles {
   T tg0, tg1, tg25;
+  // U may be evaluated on the state scaled by an exact power of two s (the
+  // fused kernels defer the 1/4 of each I'): then tg0 and tg25 carry 1/s^2 and
+  // fs = 1/s^2 brings F back to its true scale, so that W, a function of
+  // theta n, theta F, the direction of F and (v v^H)/n only, is unchanged.
+  T fs = T(1);
 };
 
 // ---------------------------------------------------------------------------
 // Collide (sqrt SWAP on each (a_m, b_m) pair), without its factor 1/2:
 //   2 a' = (a + b) - i (a - b),   2 b' = (a + b) + i (a - b).
 // Two collides and one exact multiplication by 1/4 give C C exactly as the
-// scaled form would (scaling by powers of two commutes with rounding).
+// scaled form would (scaling by powers of two commutes with rounding); the
+// fused step kernels collect the four factors 1/4 of a step's I' into one
+// multiplication by 1/256 (scale_by) and evaluate U in between with Angles::fs.
 // ---------------------------------------------------------------------------
 template <typename T>
 QLG_HD void collide2(cx<T> (&a)[5], cx<T> (&b)[5]) {
@@ -127,12 +134,17 @@ QLG_HD void collide2(cx<T> (&a)[5], cx<T> (&b)[5]) {
 }
 
 template <typename T>
-QLG_HD void scale_quarter(cx<T> (&a)[5], cx<T> (&b)[5]) {
+QLG_HD void scale_by(cx<T> (&a)[5], cx<T> (&b)[5], T f) {
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    a[m] = T(0.25) * a[m];
-    b[m] = T(0.25) * b[m];
+    a[m] = f * a[m];
+    b[m] = f * b[m];
   }
+}
+
+template <typename T>
+QLG_HD void scale_quarter(cx<T> (&a)[5], cx<T> (&b)[5]) {
+  scale_by(a, b, T(0.25));
 }
 
 // ---------------------------------------------------------------------------
@@ -175,12 +187,12 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
     q[m] = W.p[m].re * W.p[m].re + W.p[m].im * W.p[m].im;
   }
   const T n = q[0] + q[1] + q[2] + q[3] + q[4];
-  const T Fz = T(2) * (q[0] - q[4]) + (q[1] - q[3]);
+  const T Fz = ang.fs * (T(2) * (q[0] - q[4]) + (q[1] - q[3]));
   // F_x + i F_y = psi^H f_+ psi = 2 p2* p1 + sqrt6 p1* p0 + sqrt6 p0* p-1 + 2 p-1* p-2
   const cx<T> f1 = cmulc(W.p[0], W.p[1]) + cmulc(W.p[3], W.p[4]);
   const cx<T> f2 = cmulc(W.p[1], W.p[2]) + cmulc(W.p[2], W.p[3]);
-  const T Fx = T(2) * f1.re + r6 * f2.re;
-  const T Fy = T(2) * f1.im + r6 * f2.im;
+  const T Fx = ang.fs * (T(2) * f1.re + r6 * f2.re);
+  const T Fy = ang.fs * (T(2) * f1.im + r6 * f2.im);
   const T Fp2 = Fx * Fx + Fy * Fy;
   const T Fn2 = Fp2 + Fz * Fz;
   // |F|, F_perp and their reciprocals; below `tiny` the direction is immaterial

@@ -21,11 +21,13 @@ STATUS_NAMES = {0: "QLG_OK", 1: "QLG_ERR_ARG", 2: "QLG_ERR_SHAPE", 3: "QLG_ERR_D
                 4: "QLG_ERR_DEVICE", 5: "QLG_ERR_OOM", 6: "QLG_ERR_STATE", 7: "QLG_ERR_NUMERIC"}
 C64, C128 = 0, 1
 INTERLEAVED, PLAIN = 0, 1
+RECORD_DOUBLES = 16   # QLG_RECORD_DOUBLES
 
 # every symbol declared in include/qlg.h
 EXPORTED = [
     "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
-    "qlg_get_qubits", "qlg_step", "qlg_observables", "qlg_set_tuning", "qlg_get_tuning",
+    "qlg_get_qubits", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
+    "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
     "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
     "qlg_last_error", "qlg_destroy",
@@ -58,7 +60,7 @@ class Obs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("steps_per_pass", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("pair_waves", ctypes.c_int32)]
 
 
 class QLGError(RuntimeError):
@@ -85,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_get_qubits": (i32, [vp, vp]),
         "qlg_step": (i32, [vp, i64]),
         "qlg_observables": (i32, [vp, P(Obs)]),
+        "qlg_record_observables": (i32, [vp, vp]),
+        "qlg_decode_records": (i32, [vp, vp, i64, P(Obs)]),
         "qlg_set_tuning": (i32, [vp, P(Tuning)]),
         "qlg_get_tuning": (i32, [vp, P(Tuning)]),
         "qlg_autotune": (i32, [vp]),
@@ -247,17 +251,56 @@ class Lattice:
             self._check(st, "qlg_observables")
         return [o.as_dict() for o in arr]
 
+    def new_records(self, nrec: int) -> torch.Tensor:
+        """Device buffer for `nrec` observables records of every instance."""
+        return torch.zeros((int(nrec), self.nbatch, RECORD_DOUBLES), dtype=torch.float64, device=self.device)
+
+    def record_observables(self, rec: torch.Tensor, k: int = 0):
+        """Enqueue the observables of the current state into record slot k of `rec` (no sync)."""
+        if not (rec.is_cuda and rec.dtype == torch.float64 and rec.is_contiguous()
+                and rec.dim() == 3 and rec.shape[1:] == (self.nbatch, RECORD_DOUBLES) and 0 <= k < rec.shape[0]):
+            raise ValueError("rec must be a contiguous float64 device tensor (nrec, nbatch, %d)" % RECORD_DOUBLES)
+        self._check(lib().qlg_record_observables(self.ctx, rec[k].data_ptr()), "qlg_record_observables")
+
+    def decode_records(self, rec, check: bool = True) -> List[List[dict]]:
+        """Records (device or host tensor (nrec, nbatch, 16)) -> per record, per instance dicts."""
+        if rec.is_cuda:
+            with torch.cuda.stream(self.stream):   # ordered after the kernels that wrote it
+                host = rec.detach().to("cpu", torch.float64).contiguous()
+        else:
+            host = rec.detach().to(torch.float64).contiguous()
+        nrec = host.shape[0]
+        arr = (Obs * (nrec * self.nbatch))()
+        st = lib().qlg_decode_records(self.ctx, host.data_ptr(), nrec, arr)
+        if check:
+            self._check(st, "qlg_decode_records")
+        return [[arr[r * self.nbatch + i].as_dict() for i in range(self.nbatch)] for r in range(nrec)]
+
+    def run(self, nsteps: int, every: int) -> List[List[dict]]:
+        """nsteps steps with the observables recorded after every `every` steps on the device;
+        one host synchronisation at the end."""
+        nrec = nsteps // every
+        rec = self.new_records(max(nrec, 1))
+        for k in range(nrec):
+            self.step(every)
+            self.record_observables(rec, k)
+        if nsteps - nrec * every:
+            self.step(nsteps - nrec * every)
+        return self.decode_records(rec[:nrec]) if nrec else []
+
     def tuning(self) -> dict:
         t = Tuning()
         self._check(lib().qlg_get_tuning(self.ctx, ctypes.byref(t)), "qlg_get_tuning")
-        return {"steps_per_pass": t.steps_per_pass, "tile_rows": t.tile_rows, "use_graph": t.use_graph}
+        return {"steps_per_pass": t.steps_per_pass, "tile_rows": t.tile_rows, "use_graph": t.use_graph,
+                "pair_waves": t.pair_waves}
 
     def set_tuning(self, steps_per_pass: Optional[int] = None, tile_rows: Optional[int] = None,
-                   use_graph: Optional[bool] = None):
+                   use_graph: Optional[bool] = None, pair_waves: Optional[bool] = None):
         cur = self.tuning()
         t = Tuning(steps_per_pass if steps_per_pass is not None else cur["steps_per_pass"],
                    tile_rows if tile_rows is not None else cur["tile_rows"],
-                   int(use_graph) if use_graph is not None else cur["use_graph"], 0)
+                   int(use_graph) if use_graph is not None else cur["use_graph"],
+                   int(pair_waves) if pair_waves is not None else cur["pair_waves"])
         self._check(lib().qlg_set_tuning(self.ctx, ctypes.byref(t)), "qlg_set_tuning")
 
     def autotune(self) -> dict:

@@ -1,0 +1,51 @@
+"""Write the oracle's state of the 1D two-soliton workload after its full length.
+
+The 1D two-soliton scattering workload (L = 16384, eps = 0.1, g = (1, -0.5, 0.5),
+interleaved split, seeded initial field from `qlg_inputs.c2_two_solitons`) is run
+for 20000 steps by the FP64 CPU oracle alone; psi = a + b after 2000 and after
+20000 steps is stored in `c2_oracle_psi.npz` (arrays `psi_2000`, `psi_20000`,
+complex128, shape (5, 16384)), together with the parameters used.
+
+Usage (from the repository root; about 20 minutes on 8 CPU threads):
+
+    python tests/golden/make_c2_reference.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import qlg_inputs as qi  # noqa: E402
+from oracle import qlg_oracle as O  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_psi.npz")
+SAVE_AT = (2000, 20000)
+
+
+def main():
+    w = qi.c2_two_solitons()
+    assert w.nsteps == SAVE_AT[-1]
+    p = torch.from_numpy(np.ascontiguousarray(w.psi[0])).to(torch.complex128)
+    a, b = O.encode(p)
+    saved = {}
+    t0 = time.time()
+    done = 0
+    with torch.no_grad():
+        for target in SAVE_AT:
+            while done < target:
+                k = min(500, target - done)
+                a, b = O.run(a, b, k, w.eps, w.g, 1, "interleaved")
+                done += k
+                print("step %d (%.0f s)" % (done, time.time() - t0), flush=True)
+            saved["psi_%d" % target] = (a + b).numpy()
+    np.savez_compressed(OUT, L=w.nx[0], eps=w.eps, g=np.array(w.g), steps=np.array(SAVE_AT), **saved)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()
