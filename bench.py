@@ -39,15 +39,19 @@ PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vect
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 
-# HBM traffic of one k_step1d<float> launch of this workload (4 steps per pass), from
-# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs scaled by a 256 MiB device copy
-# measured in the same runs (FETCH_SIZE read 131092.9 KiB for 262144 KiB copied: x2.000;
-# WRITE_SIZE 262144 KiB: x1.000), mean over 111 launches of grid 32768.  Valid only for
-# the kernel sources it was measured on.
+# HBM traffic of one launch of the fused 1D step on this workload (complex64), by kernel and
+# steps per pass, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
+# mean over the dispatches of that plan), each scaled by what the same counter reads for a
+# 256 MiB device copy in the same run (FETCH_SIZE: x2.000, WRITE_SIZE: x1.000).  Valid only
+# for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "d26eba18a9e5bb67", "steps_per_pass": 4,
-           "fetch_kib": 935.0, "fetch_scale": 262144.0 / 131092.9, "write_kib": 1280.4, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256_16": "b0ef51c2593e6a40", "fetch_scale": 262144.0 / 131092.6, "write_scale": 1.0,
+           "kib": {"k_step1d/S1": (857.8, 1280.0), "k_step1d/S2": (874.1, 1280.0), "k_step1d/S3": (895.8, 1280.0),
+                   "k_step1d/S4": (928.0, 1280.0), "k_step1d/S5": (1198.2, 1280.0), "k_step1d/S6": (1392.9, 1280.9),
+                   "k_step1d/S7": (2072.0, 1280.0), "k_step1d_pair/S1": (945.6, 1280.0),
+                   "k_step1d_pair/S2": (977.0, 1280.0), "k_step1d_pair/S3": (1019.9, 1280.0),
+                   "k_step1d_pair/S4": (1084.5, 1280.0)}}
 
 
 def parse():
@@ -55,6 +59,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="1d_two_soliton_scattering",
+                    help="the benchmark workload (default) or the 2D vortex-pair configuration")
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
     ap.add_argument("--secondary", choices=["c64", "c128", "none"], default="c128",
                     help="also time the other storage precision of the same workload")
@@ -79,15 +85,27 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def measure(dtype, steps, warmup):
+WORKLOADS = {
+    # name: (ndim, description)
+    "1d_two_soliton_scattering": (1, "1D L = 16384 two bright solitons, w = 48, k = -+0.05 pi"),
+    "2d_vortex_pair": (2, "2D 2048^2 uniform background with a Pade vortex pair 128 sites apart"),
+}
+
+
+def workload_input(name, steps):
+    import qlg_inputs as qi
+    return qi.c2_two_solitons(nsteps=steps) if name == "1d_two_soliton_scattering" else qi.c3_vortex_pair(nsteps=steps)
+
+
+def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering"):
     """Run the workload; return rate, wall time, per-launch kernel time and plan."""
     import torch
-    import qlg_inputs as qi
     from paper_1907_12834_amd.qlg import Lattice
 
-    w = qi.c2_two_solitons(nsteps=steps)
-    L = w.nx[0]
-    lat = Lattice(1, [L], g=w.g, eps=w.eps, dtype=dtype)
+    w = workload_input(workload, steps)
+    ndim = WORKLOADS[workload][0]
+    L = w.nx[0] * (w.ny[0] if ndim == 2 else 1)   # sites
+    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     tuning = lat.autotune()
     lat.set_tuning(use_graph=True)
@@ -217,28 +235,36 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    m = measure(args.dtype, args.steps, args.warmup)
+    m = measure(args.dtype, args.steps, args.warmup, args.workload)
     w, L = m["w"], m["L"]
+    ndim = WORKLOADS[args.workload][0]
     S = m["tuning"]["steps_per_pass"]
     kern_ms = m["kern_ms"]
     sites_per_launch = L * S
-    flops_launch = FLOPS_PER_SITE_STEP[1] * sites_per_launch
+    flops_launch = FLOPS_PER_SITE_STEP[ndim] * sites_per_launch
     achieved_tflops = flops_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L
     hbm_gbs = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    if ndim == 1:
+        kernel = "k_step1d_pair" if m["tuning"].get("pair_waves") else "k_step1d"
+        key = "%s/S%d" % (kernel, S)
+    else:
+        kernel = "k_step2d"
+        key = "%s/rows%d" % (kernel, m["tuning"]["tile_rows"])
     traffic = None
-    if (args.dtype == "c64" and S == TRAFFIC["steps_per_pass"]
-            and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]):
-        traffic = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    if args.dtype == "c64" and key in TRAFFIC["kib"] and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
+        fk, wk = TRAFFIC["kib"][key]
+        traffic = 1024.0 * (fk * TRAFFIC["fetch_scale"] + wk * TRAFFIC["write_scale"])
 
     secondary = None
     if args.secondary not in ("none", args.dtype):
-        m2 = measure(args.secondary, args.steps, min(args.warmup, 200))
+        m2 = measure(args.secondary, args.steps, min(args.warmup, 200), args.workload)
         secondary = {"storage": args.secondary, "value": m2["value"], "unit": "site-updates/s",
                      "kernel_ms_avg": m2["kern_ms"], "plan": m2["tuning"], "norm_drift": m2["drift"]}
     batched = batched_ratio(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = adjoint_ratio(args.adjoint_steps, 64) if args.adjoint_steps > 0 else None
-    cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
+    cpu = cpu_baseline(w, args.cpu_steps if ndim == 1 else max(1, args.cpu_steps // 500), ndim) \
+        if args.cpu_steps > 0 else None
 
     out = {
         "metric": "QLG site-updates/s + % HBM roofline; batched and fwd+adjoint vs plain step",
@@ -254,8 +280,8 @@ def main():
         "dtype": "f32" if args.dtype == "c64" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "1d_two_soliton_scattering",
-            "lattice": [L],
+            "workload": args.workload,
+            "lattice": [w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]],
             "storage": args.dtype,
             "split": "interleaved",
             "g": list(w.g),
@@ -271,10 +297,10 @@ def main():
             "frac": (achieved_tflops / PEAK_TFLOPS[args.dtype]) if achieved_tflops else None,
             "traffic": traffic,
             "traffic_unit": "bytes per launch",
-            "kernel": "k_step1d",
+            "kernel": kernel,
             "kernel_ms_avg": kern_ms,
             "launches_timed": m["launches"],
-            "flops_per_site_update": FLOPS_PER_SITE_STEP[1],
+            "flops_per_site_update": FLOPS_PER_SITE_STEP[ndim],
             "hbm_algorithmic_gbs": hbm_gbs,
             "hbm_frac": (hbm_gbs / PEAK_HBM_GBS) if hbm_gbs else None,
         },
@@ -287,7 +313,7 @@ def main():
     print(json.dumps(out))
 
 
-def cpu_baseline(w, nsteps):
+def cpu_baseline(w, nsteps, ndim=1):
     """The FP64 oracle, as it stands, on the first `nsteps` steps of the same workload."""
     import torch
     from oracle import qlg_oracle as O
@@ -295,10 +321,11 @@ def cpu_baseline(w, nsteps):
     t0 = time.perf_counter()
     O.run_psi(w.psi[0], nsteps, w.eps, w.g)
     dt = time.perf_counter() - t0
-    L = w.nx[0]
-    return {"value": L * nsteps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "same 1D L=%d workload, first %d steps (FP64 torch CPU, %d threads), %.1f s"
-                      % (L, nsteps, threads, dt)}
+    sites = w.nx[0] * (w.ny[0] if ndim == 2 else 1)
+    shape = "L=%d" % w.nx[0] if ndim == 1 else "%dx%d" % (w.ny[0], w.nx[0])
+    return {"value": sites * nsteps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "same %dD %s workload, first %d steps (FP64 torch CPU, %d threads), %.1f s"
+                      % (ndim, shape, nsteps, threads, dt)}
 
 
 if __name__ == "__main__":

@@ -136,6 +136,44 @@ def pade_density(r: np.ndarray, a1: float, a2: float, b1: float) -> np.ndarray:
     return (a2 * r2 * r2 + a1 * r2) / (a2 * r2 * r2 + b1 * r2 + 1.0)
 
 
+def pade_coefficients(geff: float) -> tuple:
+    """(a1, a2, b1) of the single-channel winding-1 Pade vortex on a unit background.
+
+    For psi = sqrt(pade(r)) e^{i theta} in a channel with effective coupling
+    geff (g0 + 4 g1 for m = +-2, g0 + g1 for m = +-1, g0 + g2/5 for m = 0), the
+    background density is 1, so E = geff, and the three lowest orders (r, r^3,
+    r^5) of the radial equation E f = -(f'' + f'/r - f/r^2) + geff f^3 vanish for
+    a1 = 11 geff / 32, b1 = geff / 3, a2 = a1 (b1 - E / 4) = 11 geff^2 / 384
+    (Sec. V; the root of Table III with a1 > 0).
+    """
+    g = float(geff)
+    return 11.0 * g / 32.0, 11.0 * g * g / 384.0, g / 3.0
+
+
+def pade_quadrupole_2d(n: int, eps: float, d: float, geff: float, m_index: int,
+                       core_scale: float = 1.0) -> np.ndarray:
+    """Four single-channel Pade vortices at (n/2 +- d, n/2 +- d) (sites), windings +1, -1, -1, +1,
+    in component m_index of an (5, n, n) field: the periodic calibration state of Sec. VI.
+    core_scale != 1 stretches every core by that factor (a non-eigenstate control)."""
+    a1, a2, b1 = pade_coefficients(geff)
+    f = np.ones((n, n), dtype=np.complex128)
+    c = n / 2.0
+    for sx, sy, wnd in ((-1, -1, 1), (1, -1, -1), (-1, 1, -1), (1, 1, 1)):
+        f = f * vortex_2d(n, n, c + sx * d, c + sy * d, wnd, eps / core_scale, a1, a2, b1)
+    psi = np.zeros((5, n, n), dtype=np.complex128)
+    psi[m_index] = f
+    return psi
+
+
+def dark_pair_1d(L: int, eps: float, coeffs: Sequence[float], K: float = 1.0, p: float = 0.0) -> np.ndarray:
+    """c_m K tanh(K(X - Lp/4)) tanh(K(3Lp/4 - X)) e^{i p X}, X = eps x, Lp = eps L: two dark
+    solitons in the periodic product form of Sec. IV (the amplitude c_m K appears once)."""
+    X = np.arange(L, dtype=np.float64) * eps
+    Lp = L * eps
+    f = K * np.tanh(K * (X - Lp / 4)) * np.tanh(K * (3 * Lp / 4 - X)) * np.exp(1j * p * X)
+    return np.asarray(coeffs, dtype=np.complex128).reshape(5, 1) * f[None, :]
+
+
 def vortex_2d(nx: int, ny: int, cx: float, cy: float, winding: int, eps: float,
               a1: float, a2: float, b1: float) -> np.ndarray:
     """sqrt(pade(r)) e^{i winding theta} on an (ny, nx) grid; r = eps * distance."""

@@ -411,6 +411,172 @@ def test_bright_soliton_overlap_energy():
         assert abs(e - (p * p - 1.0)) < 0.01 * max(1.0, abs(p * p - 1.0)), (p, e)
 
 
+def test_moving_bright_soliton_velocity():
+    """A kicked bright soliton moves with velocity 2p (Sec. III, eq. timedependentsoliton) and keeps
+    its shape."""
+    w, T = 16, 2.0
+    for p in (0.5, -0.8):
+        psi, eps = _bright(w, p=p)
+        L = psi.shape[1]
+        X = (np.arange(L) - L / 2) * eps
+        nsteps = int(round(T / eps ** 2))
+        A, B = O.run_psi(psi, nsteps, eps, G_BRIGHT)
+        d0 = (np.abs(psi) ** 2).sum(0)
+        d1 = (np.abs((A + B).numpy()) ** 2).sum(0)
+        shift = (X * d1).sum() / d1.sum() - (X * d0).sum() / d0.sum()
+        expect = 2 * p * nsteps * eps ** 2
+        assert abs(shift / expect - 1) < 0.01, (p, shift, expect)
+        moved = np.interp(X - expect, X, d0)
+        assert np.linalg.norm(d1 - moved) / np.linalg.norm(d0) < 0.03
+
+
+# ---------------------------------------------------------------------------
+# P7, P8: dark solitons (Table I with E = +2, psi = c K tanh(K x)) in the periodic
+# product form of Sec. IV; dispersion E = p^2 + 2 K^2 (eq. darkdispersion)
+# ---------------------------------------------------------------------------
+G_DARK = (1.0, 0.1, 0.7)   # repulsive in every channel: all Table I rows real at E = +2
+
+
+def _dark(w, p=0.0, row=16):
+    eps = 1.0 / w
+    c = qi.table1_coeffs(row, 2.0, *G_DARK, c1=0.5, c2=0.5).real
+    return qi.dark_pair_1d(40 * w, eps, c, K=1.0, p=p), eps
+
+
+@pytest.mark.parametrize("row", [6, 16])
+def test_dark_soliton_stationary_converges(row):
+    """Density of the two-kink state stays put; the error falls ~8x per doubling of resolution
+    (sum over twice the sites of an O(eps^2) error), and the plain split is worse than the
+    interleaved one (Sec. VII)."""
+    T, errs = 0.5, {}
+    for split in ("interleaved", "plain"):
+        for w in (8, 16):
+            psi, eps = _dark(w, row=row)
+            A, B = O.run_psi(psi, int(round(T / eps ** 2)), eps, G_DARK, split)
+            errs[split, w] = O.density_l2_error(t(psi), A + B)
+    assert errs["interleaved", 16] < errs["interleaved", 8] / 6, errs
+    assert errs["interleaved", 16] < 5e-4, errs
+    assert errs["plain", 8] > 1.5 * errs["interleaved", 8], errs
+
+
+def test_dark_soliton_overlap_energy():
+    """Re E_ov / eps^2 -> p^2 + 2 K^2 for resting and kicked dark solitons (p = 2 pi n / Lp keeps
+    the product state periodic)."""
+    w = 24
+    for p in (0.0, 2 * np.pi * 3 / 40.0):
+        psi, eps = _dark(w, p=p)
+        A, B = O.run_psi(psi, 40, eps, G_DARK)
+        prev = A + B
+        a1, b1 = O.step(A, B, eps, G_DARK, 1)
+        e = O.observables(a1, b1, eps, G_DARK, prev_psi=prev)["e_overlap"].real / eps ** 2
+        assert abs(e - (p * p + 2.0)) < 1e-3 * (p * p + 2.0), (p, e)
+
+
+# ---------------------------------------------------------------------------
+# P10: Pade vortices (Sec. V, Table III; calibration quadrupole of Sec. VI)
+# ---------------------------------------------------------------------------
+def _table3(m, E, g0, g1, g2):
+    """Table III closed forms as printed, for channel m, with the root that gives a1 > 0."""
+    if abs(m) == 2:
+        G = g0 + 4 * g1
+        gam = E * E * math.sqrt(361 * E * E - 8 * G * (4 * G + 13 * E))
+        a1 = max((19 * E ** 3 - 12 * G * E * E + s * gam) / (64 * G * (2 * E - G)) for s in (1, -1))
+        b1 = (16 * a1 * (G - 3 * E) + 5 * E * E) / (48 * (E - 4 * a1))
+    elif abs(m) == 1:
+        G = g0 + g1
+        gam = E * E * math.sqrt(361 * E * E - 8 * G * (4 * G + 13 * E))
+        a1 = max(-11 * E ** 4 / (76 * E ** 3 - 48 * G * E * E + s * 4 * gam) for s in (1, -1))
+        b1 = (16 * a1 * (G - 3 * E) + 5 * E * E) / (48 * (E - 4 * a1))
+    else:
+        G5 = 5 * g0 + g2
+        gam = E * E * math.sqrt(9025 * E * E - 8 * G5 * (20 * g0 + 4 * g2 + 65 * E))
+        a1 = max(5 * (95 * E ** 3 - 12 * G5 * E * E + s * gam) / (64 * G5 * (10 * E - G5)) for s in (1, -1))
+        b1 = (16 * a1 * (G5 - 15 * E) + 25 * E * E) / (240 * (E - 4 * a1))
+    return a1, a1 * (b1 - E / 4), b1
+
+
+GEFF = {2: lambda g: g[0] + 4 * g[1], 1: lambda g: g[0] + g[1], 0: lambda g: g[0] + g[2] / 5}
+
+
+@pytest.mark.parametrize("m", [2, 1, 0])
+@pytest.mark.parametrize("g", [(1.0, -0.1, 0.2), (1.3, 0.2, -0.5)])
+def test_pade_coefficients_match_table3(m, g):
+    """On a unit background (E = g_eff) the Pade coefficients equal Table III's closed forms."""
+    G = GEFF[m](g)
+    ours = qi.pade_coefficients(G)
+    assert np.allclose(ours, _table3(m, G, *g), rtol=1e-12, atol=0), (ours, _table3(m, G, *g))
+
+
+@pytest.mark.parametrize("G", [0.7, 1.04])
+def test_pade_profile_solves_radial_equation_to_r7(G):
+    """The radial residual E f + (f'' + f'/r - f/r^2) - G f^3 of f = sqrt(pade) vanishes through
+    r^5 (accurate to O(r^7), Sec. V): residual / r^7 stays bounded as r -> 0.  Derivatives by
+    high-order central differences, independent of the series used to find the coefficients."""
+    a1, a2, b1 = qi.pade_coefficients(G)
+    f = lambda r: np.sqrt(qi.pade_density(r, a1, a2, b1))   # noqa: E731
+    h = 1e-3
+    ratios = []
+    for r in (0.2, 0.1, 0.05):
+        d1 = (f(r - 2 * h) - 8 * f(r - h) + 8 * f(r + h) - f(r + 2 * h)) / (12 * h)
+        d2 = (-f(r - 2 * h) + 16 * f(r - h) - 30 * f(r) + 16 * f(r + h) - f(r + 2 * h)) / (12 * h * h)
+        res = G * f(r) + d2 + d1 / r - f(r) / r ** 2 - G * f(r) ** 3
+        ratios.append(abs(res) / r ** 7)
+    assert max(ratios) < 10 * G ** 4, ratios   # an O(r^3) or O(r^5) residual would blow up here
+    # a wrong coefficient leaves an O(r^3) residual
+    f = lambda r: np.sqrt(qi.pade_density(r, a1 * 1.05, a2, b1))   # noqa: E731
+    r = 0.05
+    d1 = (f(r - 2 * h) - 8 * f(r - h) + 8 * f(r + h) - f(r + 2 * h)) / (12 * h)
+    d2 = (-f(r - 2 * h) + 16 * f(r - h) - 30 * f(r) + 16 * f(r + h) - f(r + 2 * h)) / (12 * h * h)
+    assert abs(G * f(r) + d2 + d1 / r - f(r) / r ** 2 - G * f(r) ** 3) / r ** 7 > 1e3 * max(ratios)
+
+
+def _core_profile(nfield, cy, cx, R=14):
+    """Azimuthal average of the density in unit rings around the density minimum near (cy, cx)."""
+    win = nfield[cy - 6:cy + 7, cx - 6:cx + 7]
+    iy, ix = np.unravel_index(np.argmin(win), win.shape)
+    y0, x0 = cy - 6 + iy, cx - 6 + ix
+    yy, xx = np.mgrid[-R:R + 1, -R:R + 1]
+    rr = np.sqrt(yy ** 2 + xx ** 2)
+    vals = nfield[y0 - R:y0 + R + 1, x0 - R:x0 + R + 1]
+    return np.array([vals[(rr >= k) & (rr < k + 1)].mean() for k in range(R)])
+
+
+def _winding(field, cy, cx, rad):
+    """Phase winding of field along the square contour of half-size rad around (cy, cx)."""
+    pts = [(cy - rad, x) for x in range(cx - rad, cx + rad)] + [(y, cx + rad) for y in range(cy - rad, cy + rad)]
+    pts += [(cy + rad, x) for x in range(cx + rad, cx - rad, -1)] + [(y, cx - rad) for y in range(cy + rad, cy - rad, -1)]
+    ph = np.angle(np.array([field[q] for q in pts + pts[:1]]))
+    return float(np.sum(np.angle(np.exp(1j * np.diff(ph)))) / (2 * np.pi))
+
+
+@pytest.mark.parametrize("m_index", [2, 1])
+def test_pade_quadrupole_cores_stationary(m_index):
+    """Single-channel Pade quadrupole (m = 0 or m = +1) under the 2D step: each core keeps its radial
+    density profile (about 1 % change over unit time) where a free evolution or a core of the wrong
+    size changes it several times more; every winding number is conserved, and the other four
+    components stay exactly zero."""
+    g = (1.0, -0.3, 0.2)
+    G = GEFF[2 - m_index](g)
+    n, eps, d, T = 128, 0.25, 32, 1.0
+    nsteps = int(round(T / eps ** 2))
+    centres = [(n // 2 + sy * d, n // 2 + sx * d) for sx, sy in ((-1, -1), (1, -1), (-1, 1), (1, 1))]
+    change = {}
+    for label, gg, scale in (("pade", g, 1.0), ("free", (0.0, 0.0, 0.0), 1.0),
+                             ("core x1.5", g, 1.5), ("core x0.7", g, 0.7)):
+        psi = qi.pade_quadrupole_2d(n, eps, d, G, m_index, core_scale=scale)
+        A, B = O.run_psi(psi, nsteps, eps, gg)
+        out = (A + B).numpy()
+        n0, n1 = (np.abs(psi) ** 2).sum(0), (np.abs(out) ** 2).sum(0)
+        change[label] = np.mean([np.linalg.norm(_core_profile(n1, *c) - _core_profile(n0, *c)) /
+                                 np.linalg.norm(1 - _core_profile(n0, *c)) for c in centres])
+        if label == "pade":
+            assert [round(_winding(out[m_index], cy, cx, 8), 9) for cy, cx in centres] == [1.0, -1.0, -1.0, 1.0]
+            assert all(np.abs(out[k]).max() == 0.0 for k in range(5) if k != m_index)
+    assert change["pade"] < 0.03, change
+    for label in ("free", "core x1.5", "core x0.7"):
+        assert change["pade"] < 0.25 * change[label], change
+
+
 # ---------------------------------------------------------------------------
 # P9: reductions to scalar GP (pure m = 0: g0 + g2/5; pure m = +-2: g0 + 4 g1)
 # ---------------------------------------------------------------------------
