@@ -39,8 +39,8 @@ PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vect
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 
-# HBM traffic of one launch of the fused 1D step on this workload (complex64), by kernel and
-# steps per pass, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
+# HBM traffic of one launch of the fused step on the two workloads (complex64), by kernel and
+# plan (steps per pass in 1D, band height in 2D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
 # mean over the dispatches of that plan), each scaled by what the same counter reads for a
 # 256 MiB device copy in the same run (FETCH_SIZE: x2.000, WRITE_SIZE: x1.000).  Valid only
 # for the kernel sources it was measured on.
@@ -51,7 +51,10 @@ TRAFFIC = {"sources_sha256_16": "b0ef51c2593e6a40", "fetch_scale": 262144.0 / 13
                    "k_step1d/S4": (928.0, 1280.0), "k_step1d/S5": (1198.2, 1280.0), "k_step1d/S6": (1392.9, 1280.9),
                    "k_step1d/S7": (2072.0, 1280.0), "k_step1d_pair/S1": (945.6, 1280.0),
                    "k_step1d_pair/S2": (977.0, 1280.0), "k_step1d_pair/S3": (1019.9, 1280.0),
-                   "k_step1d_pair/S4": (1084.5, 1280.0)}}
+                   "k_step1d_pair/S4": (1084.5, 1280.0),
+                   # 2D vortex-pair workload, 2048^2 (bands of rows)
+                   "k_step2d/rows38": (264163.9, 328053.6), "k_step2d/rows16": (320248.3, 328754.6),
+                   "k_step2d/rows128": (219487.5, 327761.4)}}
 
 
 def parse():
