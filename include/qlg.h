@@ -182,7 +182,12 @@ qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_h
  * ------------------------------------------------------------------------- */
 
 /* Sizes for recording a forward run of nsteps with a checkpoint every
- * checkpoint_every steps (>= 1), and for the adjoint workspace. */
+ * checkpoint_every steps (>= 1), and for the adjoint workspace.  The workspace
+ * holds the input of every self-interaction of one checkpoint segment
+ * (checkpoint_every x 4 ndim state copies for the interleaved split,
+ * checkpoint_every copies for the plain split) plus two state copies, two
+ * complex128 cotangents and small reduction buffers: memory traded for
+ * recomputation, so checkpoint_every bounds it. */
 qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t checkpoint_every,
                              size_t* ckpt_bytes, size_t* work_bytes);
 

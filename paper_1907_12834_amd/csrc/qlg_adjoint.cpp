@@ -26,7 +26,8 @@ struct Sizes {
   size_t lam = 0;      // bytes of one padded complex128 cotangent
   int64_t nck = 0;     // checkpoints
   int nsub = 4;        // substeps per step
-  size_t off_steps = 0, off_zs = 0, off_lam = 0, off_part = 0, off_acc = 0, work = 0;
+  int nrec = 4;        // recorded self-interaction inputs per step (nsub, or 1 for the plain split)
+  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_acc = 0, work = 0;
 };
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
@@ -41,17 +42,17 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   s->lam = s->copy / eb * 16;
   s->nck = (nsteps + K - 1) / K;
   s->nsub = 4 * p->ndim;
-  int64_t sites = 0;
-  for (int i = 0; i < p->nbatch; ++i) sites += p->nx[i] * (p->ndim == 2 ? p->ny[i] : 1);
-  (void)sites;
+  s->nrec = p->split == QLG_SPLIT_PLAIN ? 1 : s->nsub;
   // chunk count bound: one chunk per 256 sites per instance
   int64_t nchunks = 0;
   for (int i = 0; i < p->nbatch; ++i) nchunks += (p->nx[i] * (p->ndim == 2 ? p->ny[i] : 1) + 255) / 256;
   size_t o = 0;
-  s->off_steps = o; o += up256((size_t)K * s->copy);
-  s->off_zs = o;    o += up256((size_t)s->nsub * s->copy);
+  // inputs of every self-interaction of one checkpoint segment: [K][nrec] state copies
+  s->off_zrec = o;  o += up256((size_t)K * (size_t)s->nrec * s->copy);
+  s->off_y = o;     o += up256(2 * s->copy);   // ping-pong of the forward chain
   s->off_lam = o;   o += up256(2 * s->lam);
-  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)std::max<int64_t>(nchunks, 1));
+  // dg partials of every substep of one step: [nsub][nchunks][3]
+  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)s->nsub * (size_t)std::max<int64_t>(nchunks, 1));
   s->off_acc = o;   o += up256(sizeof(double) * 4);
   s->work = o;
   return QLG_OK;
@@ -152,20 +153,21 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
 
   char* W = (char*)work_dev;
-  char* steps = W + s.off_steps;
-  char* zs = W + s.off_zs;                 // zs[0..nsub-2] = inputs of substeps 1..nsub-1; zs[nsub-1] = temp
+  char* zrec = W + s.off_zrec;             // zrec[j][r]: input of self-interaction r of step j of the segment
+  char* ybuf[2] = {W + s.off_y, W + s.off_y + s.copy};
   char* lam[2] = {W + s.off_lam, W + s.off_lam + s.lam};
   double* part = (double*)(W + s.off_part);
   double* acc = (double*)(W + s.off_acc);
   const qlg::LaunchGeom& g = v.geom;
   const hipStream_t str = v.stream;
-  const int nd = p.ndim, dt = p.dtype, nsub = s.nsub;
+  const int nd = p.ndim, dt = p.dtype, nsub = s.nsub, nrec = s.nrec;
+  const int nchunks = g.nchunks;
   const bool plain = p.split == QLG_SPLIT_PLAIN;
   const double theta = p.eps * p.eps / (4.0 * nd);
   const double theta_u = plain ? p.eps * p.eps : theta;
   auto axis_of = [&](int k) { return nd == 1 ? 0 : (k < 4 ? 1 : 0); };
   auto qb_of = [&](int k) { return (k % 4) < 2 ? 1 : 0; };
-  auto zbuf = [&](int i) { return zs + (size_t)i * s.copy; };
+  auto zbuf = [&](int64_t j, int r) { return zrec + ((size_t)j * nrec + r) * s.copy; };
 
   hipError_t e = qlg::launch_zero(acc, 4, str);
   if (e == hipSuccess) e = qlg::launch_lam_layout(true, lambda_dev, lam[0], g, str);
@@ -175,38 +177,43 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t t0 = seg * K;
     const int n_in = (int)std::min<int64_t>(K, nsteps - t0);
-    const char* ck = (const char*)ckpt_dev + (size_t)seg * s.copy;
-    auto state_at = [&](int j) -> const void* { return j == 0 ? (const void*)ck : steps + (size_t)j * s.copy; };
-    for (int j = 1; j < n_in; ++j) {
-      e = qlg::ctx_launch_step(ctx, state_at(j - 1), steps + (size_t)j * s.copy);
-      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+    // Forward chain from the checkpoint: substep k of step j is "I'_{k-1} then U_k"
+    // (the I' of the previous substep, none for the first one), recording every U input.
+    const void* src = (const char*)ckpt_dev + (size_t)seg * s.copy;
+    int yb = 0;
+    for (int j = 0; j < n_in; ++j) {
+      for (int k = 0; k < nsub; ++k) {
+        const int kp = k == 0 ? nsub - 1 : k - 1;
+        const bool first = j == 0 && k == 0;
+        const bool has_u = !plain || k == 0;
+        if (j == n_in - 1 && k > (plain ? 0 : nsub - 1)) break;   // later links feed nothing recorded
+        e = qlg::launch_chain(dt, src, ybuf[yb], has_u ? zbuf(j, plain ? 0 : k) : nullptr, g,
+                              first ? -1 : axis_of(kp), qb_of(kp), has_u, theta_u * p.g0, theta_u * p.g1,
+                              theta_u * p.g2 / 5.0, str);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+        src = ybuf[yb];
+        yb ^= 1;
+      }
     }
     for (int j = n_in - 1; j >= 0; --j) {
-      const void* z = state_at(j);
-      // inputs of the self-interaction substeps 1..nsub-1 (interleaved split only)
-      if (!plain) {
-        const void* in = z;
-        for (int k = 0; k + 1 < nsub; ++k) {
-          e = qlg::launch_sub_potential(dt, in, zbuf(nsub - 1), g, theta * p.g0, theta * p.g1, theta * p.g2 / 5.0,
-                                        str);
-          if (e == hipSuccess) e = qlg::launch_sub_iprime(dt, zbuf(nsub - 1), zbuf(k), g, axis_of(k), qb_of(k), str);
-          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep recompute");
-          in = zbuf(k);
-        }
-      }
       for (int k = nsub - 1; k >= 0; --k) {
-        e = qlg::launch_sub_iprime_adj(lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), str);
-        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint kinetic kernel");
-        lc = 1 - lc;
-        if (!plain) {
-          const void* zk = k == 0 ? z : (const void*)zbuf(k - 1);
-          e = qlg::launch_sub_vjp(dt, zk, lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
-          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
+        if (plain) {
+          e = qlg::launch_sub_iprime_adj(lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), str);
+          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint kinetic kernel");
+        } else {
+          // kinetic pull-back and self-interaction VJP of substep k in one kernel
+          e = qlg::launch_sub_adj(dt, zbuf(j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
+                                  p.g1, p.g2, part + (size_t)3 * k * nchunks, str);
+          if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep kernel");
         }
+        lc = 1 - lc;
       }
       if (plain) {
-        e = qlg::launch_sub_vjp(dt, z, lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
+        e = qlg::launch_sub_vjp(dt, zbuf(j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
+      } else {
+        e = qlg::launch_dg_accumulate(part, nsub * nchunks, acc, str);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint parameter-gradient reduction");
       }
     }
   }

@@ -15,14 +15,12 @@ struct CtxView {
   int cur;
   LaunchGeom geom;
   double* part;             // scratch: >= nchunks * 10 doubles
-  double* res;              // scratch: >= nbatch * 10 doubles
+  double* res;              // scratch: >= nbatch * 16 doubles
 };
 
 CtxView ctx_view(qlg_ctx* c);
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg);
 qlg_status ctx_step(qlg_ctx* c, int64_t nsteps);
-// one fused step from `in` to `out` (padded layout), no overlap recording
-hipError_t ctx_launch_step(qlg_ctx* c, const void* in, void* out);
 qlg_status ctx_hip(qlg_ctx* c, hipError_t e, const char* what);
 bool ctx_broken(const qlg_ctx* c);
 

@@ -4,8 +4,10 @@
 // linear and unitary, so their pull-back is the exact inverse I'^H = C^H S C^H S^T
 // applied to the cotangent (no stored state).  The self-interaction is
 // nonlinear: its pull-back (qlg_vjp.hpp, FP64) needs the substep's input
-// state, which is recomputed from the step's input with the per-substep
-// kernels below (same per-site arithmetic as the fused forward kernels).
+// state, which a chain of per-substep kernels regenerates from the segment's
+// checkpoint (the per-site formulas of the fused forward kernels; the compiler
+// may contract them into FMAs differently, so the regenerated FP32 states can
+// differ from the forward's in the last bit).
 //
 // All kernels are one thread per site over 256-site chunks of each instance.
 
@@ -81,26 +83,13 @@ __device__ __forceinline__ void collide2_adj(cx<double> (&a)[5], cx<double> (&b)
 
 }  // namespace
 
-// U(theta) on every site, out of place.
+// (I' in)(x) for I'_{axis,q} = S_q C S_q^T C, from `in` at x-1, x, x+1, with the fused
+// kernels' operation order: c = C(in) at x-1, x, x+1;  t(y) = (c.nonq(y), c.q(y+1));
+// m(y) = C t(y) (two unscaled collides and an exact 1/4);  out.nonq(x) = m(x).nonq,
+// out.q(x) = m(x-1).q.
 template <typename T>
-__global__ __launch_bounds__(kChunk) void k_sub_potential(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                         LaunchGeom g, Angles<T> ang) {
-  const Site r = site_here(g);
-  if (!r.ok) return;
-  cx<T> a[5], b[5];
-  load_site(in, r.d, r.s, a, b);
-  potential(a, b, ang);
-  store_site(out, r.d, r.s, a, b);
-}
-
-// I'_{axis,q} = S_q C S_q^T C, out of place, with the fused kernels' operation order:
-//   c = C(in) at x-1, x, x+1;  t(y) = (c.nonq(y), c.q(y+1));  m(y) = C t(y) (two unscaled
-//   collides and an exact 1/4);  out.nonq(x) = m(x).nonq,  out.q(x) = m(x-1).q.
-template <typename T>
-__global__ __launch_bounds__(kChunk) void k_sub_iprime(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                      LaunchGeom g, int axis, int qb) {
-  const Site r = site_here(g);
-  if (!r.ok) return;
+__device__ __forceinline__ void iprime_site(const cx<T>* __restrict__ in, const Site& r, int axis, int qb,
+                                            cx<T> (&oa)[5], cx<T> (&ob)[5]) {
   const int sm = neighbour(r, axis, -1), sp = neighbour(r, axis, +1);
   cx<T> a0[5], b0[5], a1[5], b1[5], a2[5], b2[5];   // x-1, x, x+1
   load_site(in, r.d, sm, a0, b0);
@@ -122,22 +111,36 @@ __global__ __launch_bounds__(kChunk) void k_sub_iprime(const cx<T>* __restrict__
   scale_quarter(ta, tb);
   collide2(ua, ub);
   scale_quarter(ua, ub);
-  cx<T> oa[5], ob[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     oa[m] = sel(qb != 0, ta[m], ua[m]);   // moving qubit from m(x-1), the other from m(x)
     ob[m] = sel(qb != 0, ub[m], tb[m]);
   }
-  store_site(out, r.d, r.s, oa, ob);
 }
 
-// lambda <- I'^H lambda = C^H S_q C^H S_q^T lambda (FP64), out of place:
-//   w(y) = C^H(lambda.nonq(y), lambda.q(y+1));  out(x) = C^H(w(x).nonq, w(x-1).q).
-__global__ __launch_bounds__(kChunk) void k_sub_iprime_adj(const cx<double>* __restrict__ in,
-                                                          cx<double>* __restrict__ out, LaunchGeom g, int axis,
-                                                          int qb) {
+// One link of the recorded forward chain that regenerates a checkpoint segment:
+//   z = I'_{axis,q}(in) at this site (z = in when axis < 0),  rec <- z (when rec is set),
+//   out <- U(z) (out <- z when !with_u).
+// Successive links walk the substeps "U_k then I'_k" of consecutive steps as
+// "I'_{k-1} then U_k", so every input z of a self-interaction is written once.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_chain(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                 cx<T>* __restrict__ rec, LaunchGeom g, int axis, int qb,
+                                                 int with_u, Angles<T> ang) {
   const Site r = site_here(g);
   if (!r.ok) return;
+  cx<T> a[5], b[5];
+  if (axis >= 0) iprime_site(in, r, axis, qb, a, b);
+  else load_site(in, r.d, r.s, a, b);
+  if (rec) store_site(rec, r.d, r.s, a, b);
+  if (with_u) potential(a, b, ang);
+  store_site(out, r.d, r.s, a, b);
+}
+
+// (I'^H lambda)(x) = (C^H S_q C^H S_q^T lambda)(x) (FP64) from lambda at x-1, x, x+1:
+//   w(y) = C^H(lambda.nonq(y), lambda.q(y+1));  out(x) = C^H(w(x).nonq, w(x-1).q).
+__device__ __forceinline__ void iprime_adj_site(const cx<double>* __restrict__ in, const Site& r, int axis, int qb,
+                                                cx<double> (&oa)[5], cx<double> (&ob)[5]) {
   const int sm = neighbour(r, axis, -1), sp = neighbour(r, axis, +1);
   cx<double> a0[5], b0[5], a1[5], b1[5], a2[5], b2[5];
   load_site(in, r.d, sm, a0, b0);
@@ -153,7 +156,6 @@ __global__ __launch_bounds__(kChunk) void k_sub_iprime_adj(const cx<double>* __r
   }
   collide2_adj(wa, wb);
   collide2_adj(va, vb);
-  cx<double> oa[5], ob[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     oa[m] = sel(qb != 0, wa[m], va[m]);
@@ -165,6 +167,16 @@ __global__ __launch_bounds__(kChunk) void k_sub_iprime_adj(const cx<double>* __r
     oa[m] = 0.25 * oa[m];
     ob[m] = 0.25 * ob[m];
   }
+}
+
+// lambda <- I'^H lambda, out of place.
+__global__ __launch_bounds__(kChunk) void k_sub_iprime_adj(const cx<double>* __restrict__ in,
+                                                          cx<double>* __restrict__ out, LaunchGeom g, int axis,
+                                                          int qb) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+  cx<double> oa[5], ob[5];
+  iprime_adj_site(in, r, axis, qb, oa, ob);
   store_site(out, r.d, r.s, oa, ob);
 }
 
@@ -202,6 +214,28 @@ __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z,
     load_site(lam, r.d, r.s, la, lb);
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg);
     store_site(lam, r.d, r.s, la, lb);
+  }
+  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
+}
+
+// One adjoint substep of the interleaved split, fused: lambda_out = (dU)^H I'^H lambda_in,
+// the kinetic pull-back recomputed per site from lambda_in at x-1, x, x+1 along `axis`,
+// then the FP64 self-interaction VJP at the substep input z; dg partials per chunk.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
+                                                   const cx<double>* __restrict__ lin,
+                                                   cx<double>* __restrict__ lout, LaunchGeom g, int axis, int qb,
+                                                   double theta, double g0, double g1, double g2,
+                                                   double* __restrict__ part) {
+  const Site r = site_here(g);
+  double dg[3] = {0.0, 0.0, 0.0};
+  if (r.ok) {
+    cx<double> la[5], lb[5];
+    iprime_adj_site(lin, r, axis, qb, la, lb);
+    cx<double> a[5], b[5];
+    load_site(z, r.d, r.s, a, b);
+    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg);
+    store_site(lout, r.d, r.s, la, lb);
   }
   block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
 }
@@ -360,23 +394,15 @@ __global__ __launch_bounds__(kChunk) void k_fid_grad(const cx<T>* __restrict__ t
 // ---------------------------------------------------------------------------
 #define QLG_GRID dim3(g.nchunks), dim3(kChunk), 0, st
 
-hipError_t launch_sub_potential(int dtype, const void* in, void* out, const LaunchGeom& g, double tg0, double tg1,
-                                double tg25, hipStream_t st) {
+hipError_t launch_chain(int dtype, const void* in, void* out, void* rec, const LaunchGeom& g, int axis, int qb,
+                        bool with_u, double tg0, double tg1, double tg25, hipStream_t st) {
+  if (g.nchunks == 0) return hipSuccess;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_sub_potential<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, g,
-                       Angles<float>{(float)tg0, (float)tg1, (float)tg25});
+    hipLaunchKernelGGL(k_chain<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, (cx<float>*)rec, g, axis,
+                       qb, with_u ? 1 : 0, Angles<float>{(float)tg0, (float)tg1, (float)tg25});
   else
-    hipLaunchKernelGGL(k_sub_potential<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, g,
-                       Angles<double>{tg0, tg1, tg25});
-  return hipGetLastError();
-}
-
-hipError_t launch_sub_iprime(int dtype, const void* in, void* out, const LaunchGeom& g, int axis, int qb,
-                             hipStream_t st) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_sub_iprime<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, g, axis, qb);
-  else
-    hipLaunchKernelGGL(k_sub_iprime<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, g, axis, qb);
+    hipLaunchKernelGGL(k_chain<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, (cx<double>*)rec, g,
+                       axis, qb, with_u ? 1 : 0, Angles<double>{tg0, tg1, tg25});
   return hipGetLastError();
 }
 
@@ -396,6 +422,23 @@ hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom&
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, (const double*)part, g.nchunks, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* lam_out, const LaunchGeom& g, int axis,
+                          int qb, double theta, double g0, double g1, double g2, double* part, hipStream_t st) {
+  if (g.nchunks == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sub_adj<float>, QLG_GRID, (const cx<float>*)z, (const cx<double>*)lam_in,
+                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, part);
+  else
+    hipLaunchKernelGGL(k_sub_adj<double>, QLG_GRID, (const cx<double>*)z, (const cx<double>*)lam_in,
+                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, part, nparts, acc);
   return hipGetLastError();
 }
 

@@ -706,6 +706,5 @@ CtxView ctx_view(qlg_ctx* c) {
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg) { return fail(c, s, msg); }
 qlg_status ctx_step(qlg_ctx* c, int64_t nsteps) { return qlg_step(c, nsteps); }
 bool ctx_broken(const qlg_ctx* c) { return c->broken; }
-hipError_t ctx_launch_step(qlg_ctx* c, const void* in, void* out) { return launch_pass(c, 1, false, in, out); }
 qlg_status ctx_hip(qlg_ctx* c, hipError_t e, const char* what) { return hip_check(c, e, what); }
 }  // namespace qlg

@@ -41,8 +41,22 @@ struct UFrame {
   cx<double> E[5];     // e^{-i (phi0 + m phi)}, m = 2..-2
   cx<double> u;        // e^{i alpha}
   double ca, sa, cb, sb;
-  double D[5][5];      // d^2(beta) [m'][m]
+  // d^2(beta) entries d_{m'm} for m' >= |m|; the rest by d_{m'm} = (-1)^{m-m'} d_{mm'} = d_{-m,-m'}
+  double d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;
 };
+
+// Full d^2(beta) matrix [m'][m] (rows/columns m = 2..-2) from the nine stored entries,
+// built where it is used so that it need not stay live in registers.
+struct DMat {
+  double m[5][5];
+};
+QLG_HD DMat dmat(const UFrame& f) {
+  return DMat{{{f.d22, f.d21, f.d20, f.d2m1, f.d2m2},
+               {-f.d21, f.d11, f.d10, f.d1m1, f.d2m1},
+               {f.d20, -f.d10, f.d00, f.d10, f.d20},
+               {-f.d2m1, f.d1m1, -f.d10, f.d11, f.d21},
+               {f.d2m2, -f.d2m1, f.d20, -f.d21, f.d22}}};
+}
 
 QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double theta, double g0,
                     double g1, double g2, UFrame& f) {
@@ -88,27 +102,25 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
   }
   f.u = cx<double>{f.ca, f.sa};
   const double cb = f.cb, sb = f.sb;
-  const double d22 = 0.25 * opc * opc, d21 = -0.5 * sb * opc, d20 = r38 * sb * sb, d2m1 = -0.5 * sb * omc,
-               d2m2 = 0.25 * omc * omc, d11 = 0.5 * opc * (2 * cb - 1), d10 = -r32 * sb * cb,
-               d1m1 = 0.5 * omc * (2 * cb + 1), d00 = 0.5 * (3 * cb * cb - 1);
-  const double Dm[5][5] = {
-      {d22, d21, d20, d2m1, d2m2},
-      {-d21, d11, d10, d1m1, d2m1},
-      {d20, -d10, d00, d10, d20},
-      {-d2m1, d1m1, -d10, d11, d21},
-      {d2m2, -d2m1, d20, -d21, d22},
-  };
-  for (int i = 0; i < 5; ++i)
-    for (int j = 0; j < 5; ++j) f.D[i][j] = Dm[i][j];
+  f.d22 = 0.25 * opc * opc;
+  f.d21 = -0.5 * sb * opc;
+  f.d20 = r38 * sb * sb;
+  f.d2m1 = -0.5 * sb * omc;
+  f.d2m2 = 0.25 * omc * omc;
+  f.d11 = 0.5 * opc * (2 * cb - 1);
+  f.d10 = -r32 * sb * cb;
+  f.d1m1 = 0.5 * omc * (2 * cb + 1);
+  f.d00 = 0.5 * (3 * cb * cb - 1);
 }
 
 // Q^H x = d^T Phi^* x (Phi^* multiplies component m by u^m)
 QLG_HD void to_frame(const UFrame& f, const cx<double> (&x)[5], cx<double> (&out)[5]) {
   const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
   const cx<double> w[5] = {x[0] * u2, x[1] * u, x[2], x[3] * uc, x[4] * u2c};
+  const DMat D = dmat(f);
   for (int k = 0; k < 5; ++k) {
-    cx<double> acc = f.D[0][k] * w[0];
-    for (int m = 1; m < 5; ++m) acc = rfma(f.D[m][k], w[m], acc);
+    cx<double> acc = D.m[0][k] * w[0];
+    for (int m = 1; m < 5; ++m) acc = rfma(D.m[m][k], w[m], acc);
     out[k] = acc;
   }
 }
@@ -117,9 +129,10 @@ QLG_HD void to_frame(const UFrame& f, const cx<double> (&x)[5], cx<double> (&out
 QLG_HD void from_frame(const UFrame& f, const cx<double> (&z)[5], cx<double> (&out)[5]) {
   const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
   cx<double> t[5];
+  const DMat D = dmat(f);
   for (int m = 0; m < 5; ++m) {
-    cx<double> acc = f.D[m][0] * z[0];
-    for (int k = 1; k < 5; ++k) acc = rfma(f.D[m][k], z[k], acc);
+    cx<double> acc = D.m[m][0] * z[0];
+    for (int k = 1; k < 5; ++k) acc = rfma(D.m[m][k], z[k], acc);
     t[m] = acc;
   }
   out[0] = t[0] * u2c;
@@ -188,15 +201,15 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
   const double kappa = theta * g2 / 5.0;
   const cx<double> dcn = dc_dn(kappa, f.n);
   const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * cx<double>{cos(kappa * f.n), -sin(kappa * f.n)};
-  // one 5-vector x with output cotangent ly; lx receives P^H lambda_{y1}
-  auto one = [&](const cx<double>(&x)[5], const cx<double>(&ly)[5], cx<double>(&lx)[5]) {
+  // one 5-vector x; l holds the output cotangent on entry and P^H lambda_{y1} on exit
+  auto one = [&](const cx<double>(&x)[5], cx<double>(&l)[5]) {
     cx<double> s{0.0, 0.0};
     for (int m = 0; m < 5; ++m) s = s + cmulc(v[m], x[m]);    // v^H x
     cx<double> y1[5];
     for (int m = 0; m < 5; ++m) y1[m] = x[m] + (f.cs * s) * v[m];
     cx<double> Y[5], Lam[5];
     to_frame(f, y1, Y);
-    to_frame(f, ly, Lam);
+    to_frame(f, l, Lam);
     double acc0 = 0.0, acc1 = 0.0;
     for (int i = 0; i < 5; ++i) {
       const cx<double> t = f.E[i] * cmulc(Lam[i], Y[i]);    // conj(Lam) E Y
@@ -221,7 +234,7 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     // singlet factor
     cx<double> lv{0.0, 0.0};
     for (int m = 0; m < 5; ++m) lv = lv + cmulc(l1[m], v[m]);   // l^H v
-    for (int m = 0; m < 5; ++m) lx[m] = l1[m] + (conj(f.cs) * conj(lv)) * v[m];
+    for (int m = 0; m < 5; ++m) l[m] = l1[m] + (conj(f.cs) * conj(lv)) * v[m];
     cx<double> xs[5], Sx[5], lc[5], Sl[5];
     for (int m = 0; m < 5; ++m) { xs[m] = conj(x[m]); lc[m] = conj(l1[m]); }
     apply_S(xs, Sx);
@@ -230,9 +243,8 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     dn += (dcn * s * lv).re;
     dg[2] += (dcg * s * lv).re;
   };
-  cx<double> pa[5], pb[5];
-  one(a, la, pa);
-  one(b, lb, pb);
+  one(a, la);
+  one(b, lb);
   // G in the frame: G_mu = Re(-i tau sum T_jk (f_mu)_jk)
   for (int i = 0; i < 5; ++i) dGz += (2 - i) * Tdiag[i].im;   // Re(-i z) = Im(z)
   dGz *= tau;
@@ -262,8 +274,8 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     lpsi[i] = lpsi[i] + t;
   }
   for (int m = 0; m < 5; ++m) {
-    la[m] = pa[m] + lpsi[m];
-    lb[m] = pb[m] + lpsi[m];
+    la[m] = la[m] + lpsi[m];
+    lb[m] = lb[m] + lpsi[m];
   }
 }
 
