@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 FLOPS_U = 894          # one application of U (coefficients 190 + 2 x 352 per 5-vector)
 FLOPS_IPRIME = 85      # one I' (two collides 2 x 40 + its share of the exact 1/256 per step, 5)
 FLOPS_PER_SITE_STEP = {1: 4 * (FLOPS_U + FLOPS_IPRIME), 2: 8 * (FLOPS_U + FLOPS_IPRIME)}
+# plain split: one U (theta = eps^2) and the 4 d I' of a step
+FLOPS_PER_SITE_STEP_PLAIN = {1: FLOPS_U + 4 * FLOPS_IPRIME, 2: FLOPS_U + 8 * FLOPS_IPRIME}
 # HBM bytes per site per pass: read + write of 10 complex amplitudes
 BYTES_PER_SITE_PASS = {"c64": 2 * 10 * 8, "c128": 2 * 10 * 16}
 # MI355X published peaks
@@ -65,6 +67,8 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="1d_two_soliton_scattering",
                     help="the benchmark workload (default) or the 2D vortex-pair configuration")
     ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--split", choices=["interleaved", "plain"], default="interleaved",
+                    help="operator splitting of the step (the benchmark uses the interleaved one)")
     ap.add_argument("--secondary", choices=["c64", "c128", "none"], default="c128",
                     help="also time the other storage precision of the same workload")
     ap.add_argument("--cpu-steps", type=int, default=500,
@@ -100,7 +104,7 @@ def workload_input(name, steps):
     return qi.c2_two_solitons(nsteps=steps) if name == "1d_two_soliton_scattering" else qi.c3_vortex_pair(nsteps=steps)
 
 
-def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering"):
+def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="interleaved"):
     """Run the workload; return rate, wall time, per-launch kernel time and plan."""
     import torch
     from paper_1907_12834_amd.qlg import Lattice
@@ -108,7 +112,7 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering"):
     w = workload_input(workload, steps)
     ndim = WORKLOADS[workload][0]
     L = w.nx[0] * (w.ny[0] if ndim == 2 else 1)   # sites
-    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype)
+    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype, split=split)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     tuning = lat.autotune()
     lat.set_tuning(use_graph=True)
@@ -238,16 +242,20 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    m = measure(args.dtype, args.steps, args.warmup, args.workload)
+    m = measure(args.dtype, args.steps, args.warmup, args.workload, args.split)
     w, L = m["w"], m["L"]
     ndim = WORKLOADS[args.workload][0]
     S = m["tuning"]["steps_per_pass"]
     kern_ms = m["kern_ms"]
     sites_per_launch = L * S
-    flops_launch = FLOPS_PER_SITE_STEP[ndim] * sites_per_launch
+    flops_site = (FLOPS_PER_SITE_STEP if args.split == "interleaved" else FLOPS_PER_SITE_STEP_PLAIN)[ndim]
+    flops_launch = flops_site * sites_per_launch
     achieved_tflops = flops_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L
     hbm_gbs = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    # the roofline that bounds this launch: flops per algorithmic byte against the ridge point
+    intensity = flops_launch / bytes_launch
+    bound = "alu" if intensity >= PEAK_TFLOPS[args.dtype] * 1e12 / (PEAK_HBM_GBS * 1e9) else "hbm"
     if ndim == 1:
         kernel = "k_step1d_pair" if m["tuning"].get("pair_waves") else "k_step1d"
         key = "%s/S%d" % (kernel, S)
@@ -261,7 +269,7 @@ def main():
 
     secondary = None
     if args.secondary not in ("none", args.dtype):
-        m2 = measure(args.secondary, args.steps, min(args.warmup, 200), args.workload)
+        m2 = measure(args.secondary, args.steps, min(args.warmup, 200), args.workload, args.split)
         secondary = {"storage": args.secondary, "value": m2["value"], "unit": "site-updates/s",
                      "kernel_ms_avg": m2["kern_ms"], "plan": m2["tuning"], "norm_drift": m2["drift"]}
     batched = batched_ratio(args.batched_steps) if args.batched_steps > 0 else None
@@ -286,24 +294,26 @@ def main():
             "workload": args.workload,
             "lattice": [w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]],
             "storage": args.dtype,
-            "split": "interleaved",
+            "split": args.split,
             "g": list(w.g),
             "eps": w.eps,
             "observables_every": OBS_EVERY,
             "plan": m["tuning"],
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_TFLOPS[args.dtype],
-            "unit": "TFLOP/s",
-            "frac": (achieved_tflops / PEAK_TFLOPS[args.dtype]) if achieved_tflops else None,
+            "bound": bound,
+            "achieved": achieved_tflops if bound == "alu" else hbm_gbs,
+            "peak": PEAK_TFLOPS[args.dtype] if bound == "alu" else PEAK_HBM_GBS,
+            "unit": "TFLOP/s" if bound == "alu" else "GB/s",
+            "frac": ((achieved_tflops / PEAK_TFLOPS[args.dtype]) if bound == "alu" else hbm_gbs / PEAK_HBM_GBS)
+            if kern_ms > 0 else None,
+            "flop_per_byte": intensity,
             "traffic": traffic,
             "traffic_unit": "bytes per launch",
             "kernel": kernel,
             "kernel_ms_avg": kern_ms,
             "launches_timed": m["launches"],
-            "flops_per_site_update": FLOPS_PER_SITE_STEP[ndim],
+            "flops_per_site_update": flops_site,
             "hbm_algorithmic_gbs": hbm_gbs,
             "hbm_frac": (hbm_gbs / PEAK_HBM_GBS) if hbm_gbs else None,
         },

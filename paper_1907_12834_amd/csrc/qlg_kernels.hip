@@ -373,6 +373,16 @@ __device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>*
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its
+// own L2.  Give each XCD a contiguous range of logical workgroups, so that tiles
+// that share halo rows and columns (consecutive tiles) read them through one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_contiguous_block(int b, int nblocks) {
+  const int x = b % kXcds, l = b / kXcds;
+  const int per = nblocks / kXcds, extra = nblocks % kXcds;
+  return x * per + (x < extra ? x : extra) + l;
+}
+
 // LDS words per wavefront for the y pipeline: 4 stages x (cn[5], mq[5]) x 64 lanes.
 constexpr int kStageSlots = 4 * 10;
 constexpr int k2DWaves = 2;   // wavefronts per workgroup of the 2D kernel
@@ -383,7 +393,7 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   // slots it wrote itself, so no barrier is needed anywhere in the kernel.
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int wv = threadIdx.x >> 6;
-  const int w = blockIdx.x * k2DWaves + wv;
+  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * k2DWaves + wv;
   if (w >= A.ntiles) return;
   const int lane = threadIdx.x & (kLanes - 1);
   cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStageSlots * kLanes) + lane;
@@ -401,15 +411,33 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
 
   double ore = 0.0, oim = 0.0;
   const int nrows = A.tile_rows + 8;
-#pragma unroll 1
-  for (int r = 0; r < nrows; ++r) {
+  // complex64 rows are loaded one iteration ahead, so that a row's HBM latency overlaps
+  // the arithmetic of the row before it (complex128 has no registers to spare for it:
+  // the extra row would halve its occupancy)
+  constexpr bool kAhead = sizeof(T) == 4;
+  auto load_row = [&](int r, cx<T>(&a)[5], cx<T>(&b)[5]) {
     const int yw = (int)wrap64(y0 - 4 + r, ny);
     const cx<T>* src = A.in + d.off + (int64_t)yw * nx + xw;
-    cx<T> a[5], b[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       a[m] = src[m * d.stride];
       b[m] = src[(5 + m) * d.stride];
+    }
+  };
+  cx<T> na[5], nb[5];
+  if (kAhead) load_row(0, na, nb);
+#pragma unroll 1
+  for (int r = 0; r < nrows; ++r) {
+    cx<T> a[5], b[5];
+    if (kAhead) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        a[m] = na[m];
+        b[m] = nb[m];
+      }
+      if (r + 1 < nrows) load_row(r + 1, na, nb);
+    } else {
+      load_row(r, a, b);
     }
     // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y; slot k of this lane's LDS
     // holds stage k's pending rows.  The plain split applies its single U at stage 0.
