@@ -109,6 +109,16 @@ struct StepArgs {
   int32_t overlap;               // 1: record <psi_t|psi_{t-1}> of the last step
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its
+// own L2.  Give each XCD a contiguous range of logical workgroups, so that tiles
+// that share halo rows and columns (consecutive tiles) read them through one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_contiguous_block(int b, int nblocks) {
+  const int x = b % kXcds, l = b / kXcds;
+  const int per = nblocks / kXcds, extra = nblocks % kXcds;
+  return x * per + (x < extra ? x : extra) + l;
+}
+
 // ---------------------------------------------------------------------------
 // 1D fused step: `steps` steps per pass, 4*steps halo sites on each side
 // ---------------------------------------------------------------------------
@@ -117,7 +127,7 @@ struct StepArgs {
 // split applies one U with theta = eps^2 before the first I' only.
 template <typename T>
 __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (w >= A.ntiles) return;   // whole wavefronts only; no block-level synchronisation below
   const int lane = threadIdx.x & (kLanes - 1);
   const InstDesc d = A.inst[A.tile2inst[w]];
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T>
   const int v = threadIdx.x >> 6;
   const int q = v & 1;
   const int lane = threadIdx.x & (kLanes - 1);
-  const int wt = blockIdx.x * kPairTiles + (v >> 1);
+  const int wt = xcd_contiguous_block(blockIdx.x, gridDim.x) * kPairTiles + (v >> 1);
   const bool real = wt < A.ntiles;
   const int w = real ? wt : A.ntiles - 1;
   const InstDesc d = A.inst[A.tile2inst[w]];
@@ -371,16 +381,6 @@ __device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>*
     slot[m * kLanes] = cn[m];
     slot[(5 + m) * kLanes] = mq[m];
   }
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its
-// own L2.  Give each XCD a contiguous range of logical workgroups, so that tiles
-// that share halo rows and columns (consecutive tiles) read them through one L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_contiguous_block(int b, int nblocks) {
-  const int x = b % kXcds, l = b / kXcds;
-  const int per = nblocks / kXcds, extra = nblocks % kXcds;
-  return x * per + (x < extra ? x : extra) + l;
 }
 
 // LDS words per wavefront for the y pipeline: 4 stages x (cn[5], mq[5]) x 64 lanes.
