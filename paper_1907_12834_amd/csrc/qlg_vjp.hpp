@@ -192,12 +192,19 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     apply_S(pc, v);                          // v = S psi*
   }
   double dn = 0.0;                           // dL/dn
-  double dFx = 0.0, dFy = 0.0, dGz = 0.0;    // G in the frame
-  cx<double> Tdiag[5] = {}, Tup[4] = {}, Tdn[4] = {};
+  // G in the frame, G_mu = Re(-i tau sum_jk conj(M'_jk) Delta_jk (f_mu)_jk), accumulated over a
+  // and b: only the diagonal (f_z) and the first off-diagonals (f_x, f_y) of M' enter
+  double dFx = 0.0, dFy = 0.0, dGz = 0.0;
   cx<double> lpsi[5] = {};
   const double cfac[4] = {2.0, Consts::r6, Consts::r6, 2.0};
   const cx<double> e0{cos(f.phi0), -sin(f.phi0)};
   const double sc = sinc_d(0.5 * f.phi);
+  // divided differences between neighbouring m: Delta = e^{-i phi0} e^{-i phi (m_i + m_{i+1})/2} sinc(phi/2)
+  cx<double> dlt[4];
+  for (int i = 0; i < 4; ++i) {
+    const double msum = (2 - i) + (1 - i);
+    dlt[i] = sc * (e0 * cx<double>{cos(0.5 * f.phi * msum), -sin(0.5 * f.phi * msum)});
+  }
   const double kappa = theta * g2 / 5.0;
   const cx<double> dcn = dc_dn(kappa, f.n);
   const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * cx<double>{cos(kappa * f.n), -sin(kappa * f.n)};
@@ -205,56 +212,52 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
   auto one = [&](const cx<double>(&x)[5], cx<double>(&l)[5]) {
     cx<double> s{0.0, 0.0};
     for (int m = 0; m < 5; ++m) s = s + cmulc(v[m], x[m]);    // v^H x
-    cx<double> y1[5];
-    for (int m = 0; m < 5; ++m) y1[m] = x[m] + (f.cs * s) * v[m];
     cx<double> Y[5], Lam[5];
-    to_frame(f, y1, Y);
+    {
+      cx<double> y1[5];
+      for (int m = 0; m < 5; ++m) y1[m] = x[m] + (f.cs * s) * v[m];
+      to_frame(f, y1, Y);
+    }
     to_frame(f, l, Lam);
     double acc0 = 0.0, acc1 = 0.0;
     for (int i = 0; i < 5; ++i) {
-      const cx<double> t = f.E[i] * cmulc(Lam[i], Y[i]);    // conj(Lam) E Y
-      acc0 += t.im;
-      acc1 += (2 - i) * t.im;
-      Tdiag[i] = Tdiag[i] + t;
+      const double t = (f.E[i] * cmulc(Lam[i], Y[i])).im;     // Im(conj(Lam) E Y)
+      acc0 += t;
+      acc1 += (2 - i) * t;
     }
     dn += theta * g0 * acc0;
     dg[0] += theta * f.n * acc0;
     dg[1] += theta * f.Fn * acc1;
-    // off-diagonal divided differences: pairs (i, i+1), m_i = 2 - i
+    dGz += acc1;                                               // Re(-i z) = Im(z)
     for (int i = 0; i < 4; ++i) {
-      const double msum = (2 - i) + (1 - i);
-      const cx<double> dlt = sc * (e0 * cx<double>{cos(0.5 * f.phi * msum), -sin(0.5 * f.phi * msum)});
-      Tup[i] = Tup[i] + dlt * cmulc(Lam[i], Y[i + 1]);       // conj(M'_{i,i+1}) Delta
-      Tdn[i] = Tdn[i] + dlt * cmulc(Lam[i + 1], Y[i]);       // conj(M'_{i+1,i}) Delta
+      const cx<double> tu = dlt[i] * cmulc(Lam[i], Y[i + 1]);   // conj(M'_{i,i+1}) Delta
+      const cx<double> td = dlt[i] * cmulc(Lam[i + 1], Y[i]);   // conj(M'_{i+1,i}) Delta
+      const double ch = 0.5 * cfac[i];
+      // f_x: (i,i+1) and (i+1,i) entries ch;  f_y: (i,i+1) = -i ch, (i+1,i) = +i ch
+      dFx += ch * (tu.im + td.im);
+      dFy += ch * (td.re - tu.re);
     }
-    // cotangent of y1: Q conj(E) Lam
-    cx<double> z[5], l1[5];
-    for (int i = 0; i < 5; ++i) z[i] = conj(f.E[i]) * Lam[i];
-    from_frame(f, z, l1);
+    // cotangent of y1: Q conj(E) Lam (reusing Y for it)
+    for (int i = 0; i < 5; ++i) Lam[i] = conj(f.E[i]) * Lam[i];
+    from_frame(f, Lam, Y);
     // singlet factor
     cx<double> lv{0.0, 0.0};
-    for (int m = 0; m < 5; ++m) lv = lv + cmulc(l1[m], v[m]);   // l^H v
-    for (int m = 0; m < 5; ++m) l[m] = l1[m] + (conj(f.cs) * conj(lv)) * v[m];
-    cx<double> xs[5], Sx[5], lc[5], Sl[5];
-    for (int m = 0; m < 5; ++m) { xs[m] = conj(x[m]); lc[m] = conj(l1[m]); }
-    apply_S(xs, Sx);
-    apply_S(lc, Sl);
-    for (int m = 0; m < 5; ++m) lpsi[m] = lpsi[m] + (conj(f.cs) * conj(lv)) * Sx[m] + (f.cs * s) * Sl[m];
+    for (int m = 0; m < 5; ++m) lv = lv + cmulc(Y[m], v[m]);   // l^H v
+    const cx<double> k1 = conj(f.cs) * conj(lv), k2 = f.cs * s;
+    for (int m = 0; m < 5; ++m) {
+      l[m] = Y[m] + k1 * v[m];
+      // (S z)_m = (-1)^m z_{-m}: index i <-> 4 - i, sign - for m = +-1
+      const double sg = (m == 1 || m == 3) ? -1.0 : 1.0;
+      lpsi[m] = lpsi[m] + sg * (k1 * conj(x[4 - m]) + k2 * conj(Y[4 - m]));
+    }
     dn += (dcn * s * lv).re;
     dg[2] += (dcg * s * lv).re;
   };
   one(a, la);
   one(b, lb);
-  // G in the frame: G_mu = Re(-i tau sum T_jk (f_mu)_jk)
-  for (int i = 0; i < 5; ++i) dGz += (2 - i) * Tdiag[i].im;   // Re(-i z) = Im(z)
   dGz *= tau;
-  for (int i = 0; i < 4; ++i) {
-    const double ch = 0.5 * cfac[i];
-    // f_x: (i,i+1) and (i+1,i) entries ch;  f_y: (i,i+1) = -i ch, (i+1,i) = +i ch
-    dFx += tau * ch * (Tup[i].im + Tdn[i].im);
-    // Re(-i tau (-i ch Tup + i ch Tdn)) = tau ch Re(-Tup + Tdn)
-    dFy += tau * ch * (-Tup[i].re + Tdn[i].re);
-  }
+  dFx *= tau;
+  dFy *= tau;
   // lab frame: dL/dF = R3 G,  R3 = R_z(alpha) R_y(beta)
   const double ca = f.ca, sa = f.sa, cb = f.cb, sb = f.sb;
   const double LFx = ca * cb * dFx - sa * dFy + ca * sb * dGz;
