@@ -48,15 +48,15 @@ OBS_EVERY = 100
 # for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "b0ef51c2593e6a40", "fetch_scale": 262144.0 / 131092.6, "write_scale": 1.0,
-           "kib": {"k_step1d/S1": (857.8, 1280.0), "k_step1d/S2": (874.1, 1280.0), "k_step1d/S3": (895.8, 1280.0),
-                   "k_step1d/S4": (928.0, 1280.0), "k_step1d/S5": (1198.2, 1280.0), "k_step1d/S6": (1392.9, 1280.9),
-                   "k_step1d/S7": (2072.0, 1280.0), "k_step1d_pair/S1": (945.6, 1280.0),
-                   "k_step1d_pair/S2": (977.0, 1280.0), "k_step1d_pair/S3": (1019.9, 1280.0),
-                   "k_step1d_pair/S4": (1084.5, 1280.0),
+TRAFFIC = {"sources_sha256_16": "dcf3472a8b618536", "fetch_scale": 262144.0 / 131088.5, "write_scale": 1.0,
+           "kib": {"k_step1d/S4": (778.5, 1280.0), "k_step1d/S5": (789.3, 1280.0), "k_step1d/S6": (820.1, 1280.9),
+                   "k_step1d/S7": (791.6, 1280.0), "k_step1d_pair/S1": (767.7, 1280.0),
+                   "k_step1d_pair/S2": (768.4, 1280.0), "k_step1d_pair/S3": (767.9, 1280.0),
+                   "k_step1d_pair/S4": (767.0, 1280.0),
                    # 2D vortex-pair workload, 2048^2 (bands of rows)
-                   "k_step2d/rows38": (264163.9, 328053.6), "k_step2d/rows16": (320248.3, 328754.6),
-                   "k_step2d/rows128": (219487.5, 327761.4)}}
+                   "k_step2d/rows38": (234475.5, 328540.3), "k_step2d/rows76": (214238.4, 328207.7),
+                   "k_step2d/rows19": (260433.1, 329046.7), "k_step2d/rows16": (273323.4, 330070.9),
+                   "k_step2d/rows128": (182755.1, 327965.2)}}
 
 
 def parse():
