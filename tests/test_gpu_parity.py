@@ -280,27 +280,29 @@ def test_2d_random_qubits(dtype, split, shape, rows):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_c3_vortex_pair_reduced(dtype):
-    """2D vortex-pair workload on 128^2 (the 2048^2 construction, separation 64), 60 steps."""
+    """2D vortex-pair workload on 256^2 (the 2048^2 construction: separation 128, eps = 0.1,
+    seeded Pade cores), 200 steps in the autotuned plan, the whole lattice vs the oracle."""
     rng = np.random.default_rng(2019)
-    psi = qi.vortex_pair_2d(128, 128, 64.0, 0.1, rng)
-    g, eps, nsteps = (1.0, -0.3, 0.2), 0.1, 60
-    lat = lattice(2, [128], [128], g=g, eps=eps, dtype=dtype)
+    psi = qi.vortex_pair_2d(256, 256, 128.0, 0.1, rng)
+    g, eps, nsteps = (1.0, -0.3, 0.2), 0.1, 200
+    lat = lattice(2, [256], [256], g=g, eps=eps, dtype=dtype)
+    lat.autotune()
     lat.set_psi([torch.from_numpy(psi)])
     o0 = lat.observables()[0]
     lat.step(nsteps)
     got = lat.get_psi()[0].cpu().numpy()
-    a, b = oracle_psi(psi, nsteps, eps, g, key="c3-128")
+    a, b = oracle_psi(psi, nsteps, eps, g, key="c3-256")
     err = rel_l2(got, a + b)
     drift = abs(lat.observables()[0]["norm_q"] / o0["norm_q"] - 1)
-    print("C3-128 %s rel-L2 %.3e drift %.3e" % (dtype, err, drift))
+    print("C3-256 %s plan %s rel-L2 %.3e drift %.3e" % (dtype, lat.tuning(), err, drift))
     assert err <= TOL[dtype]
     assert drift <= (1e-12 if dtype == "c128" else 1e-5)
 
 
 def test_c3_full_size_light_cone_samples():
-    """2048^2 complex64 in the autotuned configuration, 12 steps, light-cone windows vs the oracle."""
+    """2048^2 complex64 in the autotuned configuration, 20 steps, light-cone windows vs the oracle."""
     w = qi.c3_vortex_pair()
-    nsteps = 12
+    nsteps = 20
     lat = lattice(2, [2048], [2048], g=w.g, eps=w.eps, dtype="c64")
     lat.autotune()
     lat.set_psi([torch.from_numpy(w.psi[0])])
@@ -321,7 +323,7 @@ def test_batched_equals_individual_and_oracle(dtype, plan):
     """Batched and one-at-a-time runs under the same plan (steps per pass, kernel variant) are
     bit-identical; the two kernel variants round in different orders, so the plan is pinned."""
     S, pair = plan
-    w = qi.c4_batched(nbatch=8, nsteps=60)
+    w = qi.c4_batched(nbatch=8, nsteps=1000)
     lat = lattice(1, w.nx, g=w.g, eps=w.eps, dtype=dtype)
     lat.set_tuning(steps_per_pass=S, pair_waves=pair)
     lat.set_psi([torch.from_numpy(p) for p in w.psi])
@@ -335,7 +337,7 @@ def test_batched_equals_individual_and_oracle(dtype, plan):
         alone = one.get_psi()[0].cpu().numpy()
         assert np.array_equal(alone, got[i]), i    # same kernels, same arithmetic: bit-identical
     i = int(np.argmin(w.nx))
-    a, b = oracle_psi(w.psi[i], w.nsteps, w.eps, w.g)
+    a, b = oracle_psi(w.psi[i], w.nsteps, w.eps, w.g, key="c4-smallest")
     assert rel_l2(got[i], a + b) <= TOL[dtype]
 
 
