@@ -17,7 +17,10 @@ the paper (Taylor, Smith, Yepez, arXiv:1907.12834):
   1D, n = 8 in 2D): Sec. VII "Operator interleaving";
 * scaling x -> a x, t -> a^2 t: Sec. VII "Scaling";
 * overlap energy E = i(<psi_t|psi_t> - <psi_t|psi_{t-1}>)/<psi_t|psi_t>: Sec. IV,
-  eq. (disecrete_energy).
+  eq. (disecrete_energy);
+* per-site F_par, F_perp, |A00| (Sec. III, eq. cmap) and the lattice vorticity
+  of one component from central differences of its phase, with plaquette
+  winding numbers (Sec. VI, "Calculating quantum vorticity on a lattice").
 
 The paper defers C, S and U to earlier work, so the definitions below are
 readings (each listed in the design doc with its evidence):
@@ -280,3 +283,40 @@ def density_l2_error(psi_exact: torch.Tensor, psi_sim: torch.Tensor) -> float:
     n1 = (psi_exact.abs() ** 2).sum(0)
     n2 = (psi_sim.abs() ** 2).sum(0)
     return float(((n1 - n2) ** 2).sum())
+
+
+# ---------------------------------------------------------------------------
+# Diagnostic fields (Sec. III eq. cmap) and lattice vorticity (Sec. VI)
+# ---------------------------------------------------------------------------
+def fields(psi: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """Per-site n, F_par = F_z, F_perp = sqrt(F_x^2 + F_y^2) and |A00| = |sigma| / sqrt(5),
+    sigma = psi^T S psi = 2 psi_2 psi_-2 - 2 psi_1 psi_-1 + psi_0^2 (the general forms: the
+    printed component formulas hold for real psi only)."""
+    n, F, _ = invariants(psi)
+    sigma = 2 * psi[0] * psi[4] - 2 * psi[1] * psi[3] + psi[2] * psi[2]
+    return {"n": n, "f_par": F[2], "f_perp": torch.sqrt(F[0] ** 2 + F[1] ** 2),
+            "a00": sigma.abs() / math.sqrt(5.0)}
+
+
+def _wrap(d: np.ndarray) -> np.ndarray:
+    """Phase difference reduced to (-pi, pi]."""
+    return d - 2 * np.pi * np.ceil((d - np.pi) / (2 * np.pi))
+
+
+def vorticity(psi_m: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Vorticity of one component on a periodic (Ny, Nx) lattice, Sec. VI: S = arg psi_m (0 where
+    psi_m = 0); v_x = (S(x+1) - S(x-1)) / 2 and v_y likewise, each difference wrapped to (-pi, pi];
+    omega = (v_y(x+1, y) - v_y(x-1, y) - v_x(x, y+1) + v_x(x, y-1)) / 2, the central-difference curl
+    (the printed stencil swaps v_x and v_y in two terms).  Also the winding number of every
+    plaquette (x, y) -> (x+1, y) -> (x+1, y+1) -> (x, y+1): the sum of its four wrapped phase
+    differences over 2 pi, an integer, indexed by its corner (x, y)."""
+    psi_m = np.asarray(psi_m, dtype=np.complex128)
+    S = np.where(psi_m == 0, 0.0, np.angle(psi_m))
+    sx = lambda f, k: np.roll(f, -k, axis=1)   # noqa: E731  f(x + k)
+    sy = lambda f, k: np.roll(f, -k, axis=0)   # noqa: E731  f(y + k)
+    vx = _wrap(sx(S, 1) - sx(S, -1)) / 2
+    vy = _wrap(sy(S, 1) - sy(S, -1)) / 2
+    omega = (sx(vy, 1) - sx(vy, -1) - sy(vx, 1) + sy(vx, -1)) / 2
+    s10, s11, s01 = sx(S, 1), sx(sy(S, 1), 1), sy(S, 1)
+    circ = _wrap(s10 - S) + _wrap(s11 - s10) + _wrap(s01 - s11) + _wrap(S - s01)
+    return omega, np.rint(circ / (2 * np.pi)).astype(np.int32)

@@ -652,3 +652,112 @@ def test_energy_gradient_is_hloc():
     hl = np.stack([np_hloc(psi[:, x], g) for x in range(psi.shape[1])], axis=1)
     want = eps * (-lap + hl)
     assert np.abs(grad - want).max() < 1e-10 * np.abs(want).max()
+
+
+# ---------------------------------------------------------------------------
+# P11: per-site fields (Sec. III eq. cmap) and lattice vorticity (Sec. VI)
+# ---------------------------------------------------------------------------
+def test_fields_table2_golden():
+    """fields() reproduces Table II's F_par, F_perp and |A00| for the Table I states."""
+    with open(os.path.join(GOLDEN, "table2_characteristics.json")) as fh:
+        gold = json.load(fh)
+    E = 2.0
+    g0, g1, g2 = TABLE_G
+    env = dict(E=E, g0=g0, g1=g1, g2=g2, sqrt=math.sqrt)
+    for row, exprs in gold["rows"].items():
+        c = qi.table1_coeffs(int(row), E, *TABLE_G, **FAMILY.get(int(row), {}))
+        fl = O.fields(t(np.tile(c[:, None], (1, 3))))
+        got = [abs(float(fl["f_par"][1])), float(fl["f_perp"][1]), float(fl["a00"][1])]
+        want = [eval(e, {}, env) for e in exprs]  # noqa: S307 - fixed fixture strings
+        assert np.allclose(got, want, atol=1e-12), (row, got, want)
+        assert abs(float(fl["n"][1]) - np.vdot(c, c).real) < 1e-12
+
+
+def test_fields_spin_rotations():
+    """Spin rotations: a rotated |m=2> has F_par = 2 cos b, F_perp = 2 |sin b|; n and |A00| are
+    invariant under any rotation (|A00| is the singlet amplitude), F_par and F_perp under rotations
+    about z, and |F| under all.  A wrong sign or a dropped pairing in sigma breaks the invariance."""
+    fx, fy, fz = np_spin2()
+    rng = np.random.default_rng(11)
+    psi = rng.normal(size=(5, 6)) + 1j * rng.normal(size=(5, 6))
+    base = O.fields(t(psi))
+    for beta in (0.3, 1.1, 2.5):
+        Ry = sl.expm(-1j * beta * fy)
+        Rz = sl.expm(-1j * 0.7 * beta * fz)
+        top = O.fields(t(Ry @ np.eye(5)[:, :1]))
+        assert abs(float(top["f_par"][0]) - 2 * math.cos(beta)) < 1e-12
+        assert abs(float(top["f_perp"][0]) - 2 * abs(math.sin(beta))) < 1e-12
+        assert abs(float(top["a00"][0]) - 0.0) < 1e-12
+        for R, same in ((Ry, ("n", "a00")), (Rz, ("n", "a00", "f_par", "f_perp"))):
+            rot = O.fields(t(R @ psi))
+            for k in same:
+                assert torch.allclose(rot[k], base[k], atol=1e-12, rtol=1e-12), (beta, k)
+            F2 = lambda f: f["f_par"] ** 2 + f["f_perp"] ** 2   # noqa: E731
+            assert torch.allclose(F2(rot), F2(base), rtol=1e-12)
+    # the polar m = 0 state and the m = +-2 "cyclic" pair: |A00| = 1/sqrt(5) at unit density
+    assert abs(float(O.fields(t(np.eye(5)[:, 2:3]))["a00"][0]) - 1 / math.sqrt(5)) < 1e-15
+    assert abs(float(O.fields(t((np.eye(5)[:, 0] + np.eye(5)[:, 4])[:, None] / math.sqrt(2)))["a00"][0])
+               - 1 / math.sqrt(5)) < 1e-15
+
+
+def _vortex_field(ny, nx, cores, kx=0.0, ky=0.0):
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    out = np.exp(1j * (kx * x + ky * y))
+    for cy, cx, w in cores:
+        out = out * np.exp(1j * w * np.arctan2(y - cy, x - cx))
+    return out
+
+
+def test_vorticity_plaquette_windings():
+    """Winding +1 / -1 on exactly the plaquettes that enclose a +1 / -1 core, 0 elsewhere in the
+    interior, also on top of a uniform flow.  (The test field, a product of atan2 phases, is not
+    periodic, so the seam plaquettes carry windings of their own.)  Over the whole periodic lattice
+    the windings sum to zero: every wrapped edge difference enters two plaquettes with opposite
+    signs."""
+    cores = [(20.5, 14.5, 1), (20.5, 45.5, -1), (44.5, 30.5, 1), (44.5, 50.5, -1)]
+    for kx, ky in ((0.0, 0.0), (2 * np.pi * 3 / 64, -2 * np.pi / 64)):
+        _, wind = O.vorticity(_vortex_field(64, 64, cores, kx, ky))
+        inner = wind[:-1, :-1]
+        nz = {(int(a), int(b)): int(inner[a, b]) for a, b in zip(*np.nonzero(inner))}
+        want = {(int(cy), int(cx)): w for cy, cx, w in cores}
+        assert wind.dtype == np.int32
+        assert nz == want, nz
+        assert int(wind.sum()) == 0
+
+
+def test_vorticity_uniform_flow_and_circulation():
+    """omega vanishes for a uniform flow (a plane wave, any wrap of the phase); summed over a box
+    around one core it equals the circulation 2 pi w (discrete Stokes), and away from the cores it
+    decays like the continuum curl of grad(arg), which is zero."""
+    y, x = np.mgrid[0:48, 0:64].astype(float)
+    om, wind = O.vorticity(np.exp(1j * (2 * np.pi * 5 / 64 * x - 2 * np.pi * 7 / 48 * y)))
+    assert np.abs(om).max() < 1e-14 and not wind.any()
+    cores = [(32.5, 20.5, 1), (32.5, 44.5, -1)]
+    om, _ = O.vorticity(_vortex_field(64, 64, cores))
+    for cy, cx, w in cores:
+        box = om[int(cy) - 10:int(cy) + 12, int(cx) - 10:int(cx) + 12]
+        assert abs(box.sum() - 2 * np.pi * w) < 1e-9, box.sum()
+    far = np.ones_like(om, bool)
+    for cy, cx, _ in cores:
+        far[int(cy) - 4:int(cy) + 6, int(cx) - 4:int(cx) + 6] = False
+    assert np.abs(om[far]).max() < 0.05 * np.abs(om).max()
+
+
+def test_vorticity_zero_component_and_signed_zeros():
+    """A component that is identically zero (also as -0.0) has phase 0: omega = 0, no windings."""
+    z = np.zeros((8, 8), complex)
+    z.real[::2] = -0.0
+    z.imag[:, ::3] = -0.0
+    om, wind = O.vorticity(z)
+    assert not om.any() and not wind.any()
+
+
+def test_vorticity_small_lattices():
+    """On a 1 x N or 2 x N periodic lattice the stencils wrap onto the site itself (np.roll reading)."""
+    rng = np.random.default_rng(3)
+    for shape in ((1, 7), (2, 5), (3, 3)):
+        psi = np.exp(1j * rng.uniform(-np.pi, np.pi, size=shape))
+        om, wind = O.vorticity(psi)
+        assert om.shape == shape and np.isfinite(om).all()
+        # the total winding of a periodic lattice is zero
+        assert int(wind.sum()) == 0
