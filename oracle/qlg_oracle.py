@@ -299,8 +299,8 @@ def fields(psi: torch.Tensor) -> Dict[str, torch.Tensor]:
 
 
 def _wrap(d: np.ndarray) -> np.ndarray:
-    """Phase difference reduced to (-pi, pi]."""
-    return d - 2 * np.pi * np.ceil((d - np.pi) / (2 * np.pi))
+    """A difference of two phases in [-pi, pi] (so d in [-2 pi, 2 pi]) reduced to (-pi, pi]."""
+    return np.where(d > np.pi, d - 2 * np.pi, np.where(d <= -np.pi, d + 2 * np.pi, d))
 
 
 def vorticity(psi_m: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
