@@ -77,6 +77,9 @@ def parse():
                     help="steps of the batched-vs-one-at-a-time comparison (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward+adjoint vs forward comparison (0 = skip)")
+    ap.add_argument("--diag-reps", type=int, default=50,
+                    help="launches of the per-site field and vorticity kernels timed on the workload's "
+                         "lattice (0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device (a plain copy kernel of known "
                          "size that rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE runs use to scale their counters)")
@@ -154,6 +157,47 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     lat.set_timing(False)
     return {"w": w, "L": L, "value": L * steps / wall, "wall": wall, "kern_ms": kern_ms, "launches": launches,
             "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0}
+
+
+def diagnostics(workload, dtype, reps):
+    """Per-site fields (Sec. III) and, in 2D, the vorticity of m = +2 (Sec. VI) on the workload's
+    lattice after 20 steps: average time per launch over `reps` back-to-back launches, from HIP
+    events on the library's stream, against the algorithmic HBM bytes of each kernel."""
+    import torch
+    from paper_1907_12834_amd.qlg import Lattice, lib
+
+    w = workload_input(workload, 20)
+    ndim = WORKLOADS[workload][0]
+    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype)
+    lat.set_psi([torch.from_numpy(w.psi[0])])
+    lat.step(20)
+    n = lat.sites
+    outs = [torch.empty(n, dtype=torch.float64, device=lat.device) for _ in range(4)]
+    wind = torch.empty(n, dtype=torch.int32, device=lat.device)
+    elem = 8 if dtype == "c64" else 16
+    L = lib()
+    # bytes per site: the 10 qubit amplitudes read and 4 doubles written; a_m, b_m read
+    # and one double and one int32 written
+    calls = {"k_fields": (lambda: L.qlg_fields(lat.ctx, *[t.data_ptr() for t in outs]), 10 * elem + 32)}
+    if ndim == 2:
+        calls["k_vorticity"] = (lambda: L.qlg_vorticity(lat.ctx, 0, outs[0].data_ptr(), wind.data_ptr()),
+                                2 * elem + 12)
+    res = {"lattice_sites": n, "storage": dtype}
+    for name, (fn, bsite) in calls.items():
+        for _ in range(5):
+            assert fn() == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = bsite * n / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "bytes_per_site": bsite, "achieved_gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+    lat.close()
+    return res
 
 
 def batched_ratio(steps):
@@ -274,6 +318,7 @@ def main():
                      "kernel_ms_avg": m2["kern_ms"], "plan": m2["tuning"], "norm_drift": m2["drift"]}
     batched = batched_ratio(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = adjoint_ratio(args.adjoint_steps, 64) if args.adjoint_steps > 0 else None
+    diag = diagnostics(args.workload, args.dtype, args.diag_reps) if args.diag_reps > 0 else None
     cpu = cpu_baseline(w, args.cpu_steps if ndim == 1 else max(1, args.cpu_steps // 500), ndim) \
         if args.cpu_steps > 0 else None
 
@@ -321,6 +366,7 @@ def main():
         "secondary": secondary,
         "batched": batched,
         "adjoint": adjoint,
+        "diagnostics": diag,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

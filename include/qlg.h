@@ -133,6 +133,35 @@ qlg_status qlg_get_psi(qlg_ctx* ctx, void* psi_dev);
 qlg_status qlg_set_qubits(qlg_ctx* ctx, const void* qubits_dev);
 qlg_status qlg_get_qubits(qlg_ctx* ctx, void* qubits_dev);
 
+/* Per-site diagnostic fields of the current state (Sec. III, eq. (cmap)), in
+ * FP64, each in the canonical scalar layout: the instances back to back, each
+ * [ny][nx] row-major (x fastest), nbatch * sites doubles in all:
+ *   n_dev:      density n = sum_m |psi_m|^2;
+ *   f_par_dev:  F_par = F_z = sum_m m |psi_m|^2;
+ *   f_perp_dev: F_perp = sqrt(F_x^2 + F_y^2);
+ *   a00_dev:    |A00| = |2 psi_2 psi_-2 - 2 psi_1 psi_-1 + psi_0^2| / sqrt(5),
+ *               the singlet-pair amplitude.
+ * psi = a + b is formed in the context's dtype (the value qlg_get_psi returns)
+ * and then promoted to FP64.  Device buffers owned by the caller, 8-byte
+ * aligned; a NULL output is not written, but not all four may be NULL
+ * (QLG_ERR_ARG).  Asynchronous on the context's stream. */
+qlg_status qlg_fields(qlg_ctx* ctx, double* n_dev, double* f_par_dev, double* f_perp_dev, double* a00_dev);
+
+/* Lattice vorticity of hyperfine component m_index (0..4 for m = 2..-2) of a
+ * 2D state (Sec. VI, "Calculating quantum vorticity on a lattice"), periodic:
+ * the phase S = arg psi_m (0 where psi_m is exactly zero) gives velocities by
+ * central differences, v_x(x, y) = w(S(x+1, y) - S(x-1, y)) / 2 and v_y
+ * likewise, each difference w(.) reduced to (-pi, pi]; then
+ *   omega_dev[x, y] = (v_y(x+1, y) - v_y(x-1, y) - v_x(x, y+1) + v_x(x, y-1)) / 2
+ * (FP64), and winding_dev[x, y] (int32) is the winding number of the plaquette
+ * (x, y) -> (x+1, y) -> (x+1, y+1) -> (x, y+1): the sum of its four wrapped
+ * phase differences over 2 pi: +1 where the phase of psi_m rises by 2 pi
+ * counter-clockwise (x right, y up) around the plaquette.
+ * Both use the canonical scalar layout of qlg_fields; either may be NULL, not
+ * both (QLG_ERR_ARG).  QLG_ERR_SHAPE for a 1D context, QLG_ERR_ARG for
+ * m_index outside 0..4.  Asynchronous on the context's stream. */
+qlg_status qlg_vorticity(qlg_ctx* ctx, int32_t m_index, double* omega_dev, int32_t* winding_dev);
+
 /* Advance every instance by nsteps >= 0 QLG steps (Sec. VII), asynchronously. */
 qlg_status qlg_step(qlg_ctx* ctx, int64_t nsteps);
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqlg.so")
 
-SOURCES = ["qlg_kernels.hip", "qlg_adjoint_kernels.hip", "qlg_api.cpp", "qlg_adjoint.cpp"]
+SOURCES = ["qlg_kernels.hip", "qlg_adjoint_kernels.hip", "qlg_diag_kernels.hip", "qlg_api.cpp",
+           "qlg_adjoint.cpp"]
 ARCH = os.environ.get("QLG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

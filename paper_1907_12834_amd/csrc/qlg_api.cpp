@@ -16,6 +16,7 @@
 
 #include "qlg_internal.hpp"
 #include "qlg_adjoint.hpp"
+#include "qlg_diag.hpp"
 
 using qlg::InstDesc;
 using qlg::LaunchGeom;
@@ -435,6 +436,28 @@ qlg_status qlg_get_qubits(qlg_ctx* c, void* qb) {
   if (!qb) return fail(c, QLG_ERR_ARG, "qubits is NULL");
   return hip_check(c, qlg::launch_get_qubits(c->p.dtype, c->copy(c->cur), qb, c->geom(), c->stream),
                    "get_qubits kernel");
+}
+
+qlg_status qlg_fields(qlg_ctx* c, double* n, double* f_par, double* f_perp, double* a00) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!n && !f_par && !f_perp && !a00) return fail(c, QLG_ERR_ARG, "every field output is NULL");
+  return hip_check(c, qlg::launch_fields(c->p.dtype, c->copy(c->cur), c->geom(), n, f_par, f_perp, a00, c->stream),
+                   "fields kernel");
+}
+
+qlg_status qlg_vorticity(qlg_ctx* c, int32_t m_index, double* omega, int32_t* winding) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (c->p.ndim != 2) return fail(c, QLG_ERR_SHAPE, "vorticity needs a 2D lattice");
+  if (m_index < 0 || m_index > 4) return fail(c, QLG_ERR_ARG, "m_index must be in 0..4");
+  if (!omega && !winding) return fail(c, QLG_ERR_ARG, "omega and winding are both NULL");
+  for (const qlg::InstDesc& d : c->L.inst) {
+    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->copy(c->cur), d, m_index, omega, winding, c->stream),
+                  "vorticity kernel");
+    if (s) return s;
+  }
+  return QLG_OK;
 }
 
 qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {

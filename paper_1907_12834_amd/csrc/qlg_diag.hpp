@@ -1,0 +1,21 @@
+// Launchers of the per-site diagnostic kernels (qlg_diag_kernels.hip).
+// Internal to the library; the public entry points are qlg_fields and
+// qlg_vorticity in include/qlg.h.
+#pragma once
+
+#include "qlg_internal.hpp"
+
+namespace qlg {
+
+// n, F_par, F_perp, |A00| of every site (FP64, canonical scalar layout
+// [instance][y][x]); a NULL output is skipped.  dtype: 0 = complex64, 1 = complex128.
+hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, double* n, double* f_par,
+                         double* f_perp, double* a00, hipStream_t st);
+
+// Vorticity (FP64) and plaquette winding numbers (int32) of component m of one
+// 2D instance, written at the instance's place in the canonical scalar layout;
+// a NULL output is skipped.
+hipError_t launch_vorticity(int dtype, const void* state, const InstDesc& d, int m, double* omega,
+                            int32_t* winding, hipStream_t st);
+
+}  // namespace qlg

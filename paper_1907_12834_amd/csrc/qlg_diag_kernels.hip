@@ -1,0 +1,186 @@
+// Per-site diagnostics of a QLG state: the spin-density fields of Sec. III
+// eq. (cmap) and the lattice vorticity of one hyperfine component (Sec. VI,
+// "Calculating quantum vorticity on a lattice").
+//
+// Both read psi = a + b formed in the state's own precision (the value
+// qlg_get_psi returns) and work in FP64 from there.
+#include "qlg_diag.hpp"
+#include "qlg_math.hpp"
+
+namespace qlg {
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+constexpr double kTwoPi = 2.0 * kPi;
+
+// ---------------------------------------------------------------------------
+// Fields: n, F_par = F_z, F_perp = |F_+|, |A00| = |sigma| / sqrt(5)
+// ---------------------------------------------------------------------------
+// One thread per site, 256-site chunks of one instance per workgroup (the
+// chunk table of the elementwise kernels).  With F_+ = sum_m
+// sqrt(6 - m(m+1)) psi*_{m+1} psi_m, F_x = Re F_+ and F_y = Im F_+, so
+// F_perp = sqrt(F_x^2 + F_y^2) = |F_+|; sigma = 2 psi_2 psi_-2 - 2 psi_1 psi_-1
+// + psi_0^2 is the singlet pair amplitude psi^T S psi.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_fields(const cx<T>* __restrict__ st, LaunchGeom g,
+                                                  double* __restrict__ n_out, double* __restrict__ fpar_out,
+                                                  double* __restrict__ fperp_out, double* __restrict__ a00_out) {
+  const InstDesc d = g.inst[g.chunk2inst[blockIdx.x]];
+  const int s = (blockIdx.x - d.chunk_begin) * kChunk + threadIdx.x;
+  if (s >= d.sites) return;
+  cx<double> p[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> v = st[d.off + m * d.stride + s] + st[d.off + (5 + m) * d.stride + s];
+    p[m] = cx<double>{(double)v.re, (double)v.im};
+  }
+  double q[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) q[m] = p[m].re * p[m].re + p[m].im * p[m].im;
+  const int64_t o = d.psi_off / 5 + s;  // the canonical scalar layout [instance][y][x]
+  if (n_out) n_out[o] = q[0] + q[1] + q[2] + q[3] + q[4];
+  if (fpar_out) fpar_out[o] = 2.0 * (q[0] - q[4]) + (q[1] - q[3]);
+  if (fperp_out) {
+    const double r6 = 2.449489742783178;  // sqrt(6)
+    cx<double> fp = 2.0 * cmulc(p[0], p[1]);
+    fp = rfma(r6, cmulc(p[1], p[2]), fp);
+    fp = rfma(r6, cmulc(p[2], p[3]), fp);
+    fp = rfma(2.0, cmulc(p[3], p[4]), fp);
+    fperp_out[o] = sqrt(fp.re * fp.re + fp.im * fp.im);
+  }
+  if (a00_out) {
+    cx<double> sg = p[2] * p[2];
+    sg = rfma(2.0, p[0] * p[4], sg);
+    sg = rfma(-2.0, p[1] * p[3], sg);
+    a00_out[o] = sqrt(sg.re * sg.re + sg.im * sg.im) * 0.4472135954999579;  // 1/sqrt(5)
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vorticity and plaquette windings of component m (2D, periodic)
+// ---------------------------------------------------------------------------
+// Phase S = arg psi_m (0 where psi_m is exactly zero).  Velocities are the
+// central differences v_x = wrap(S(x+1) - S(x-1)) / 2, v_y likewise, each
+// difference reduced to (-pi, pi]; omega is their central-difference curl
+//   omega = (v_y(x+1, y) - v_y(x-1, y) - v_x(x, y+1) + v_x(x, y-1)) / 2,
+// which needs S only at the four diagonal neighbours.  The winding number of
+// the plaquette with corner (x, y) is the sum of the wrapped differences
+// around (x, y) -> (x+1, y) -> (x+1, y+1) -> (x, y+1), over 2 pi.
+//
+// A workgroup of 256 threads owns a 64 x 32 tile of outputs.  It loads psi_m
+// of the tile and a one-site periodic halo, 66 x 34 sites (1.10 per output),
+// issuing every load of a thread before the first atan2, then stores the
+// phases in LDS; every thread then reads its neighbours from there.
+// Floating-point contraction is off so that each difference, product and sum
+// rounds once, in the order written.
+constexpr int kVortW = 64, kVortH = 32, kVortThreads = 256;
+constexpr int kVortLW = kVortW + 2, kVortLH = kVortH + 2;
+constexpr int kVortLoads = (kVortLW * kVortLH + kVortThreads - 1) / kVortThreads;
+
+__device__ __forceinline__ double phase_of(double re, double im) {
+  return (re == 0.0 && im == 0.0) ? 0.0 : atan2(im, re);
+}
+
+// d is a difference of two phases in [-pi, pi]: one add or subtract of 2 pi
+// brings it to (-pi, pi]
+__device__ __forceinline__ double wrap_pi(double dlt) {
+  return dlt > kPi ? dlt - kTwoPi : (dlt <= -kPi ? dlt + kTwoPi : dlt);
+}
+
+// coordinate c in [-1, n + 65) brought to [0, n); tiles wider than the
+// lattice (n < 66) wrap more than once
+__device__ __forceinline__ uint32_t wrap_coord(int64_t c, int32_t n) {
+  if (c < 0) c += n;
+  uint32_t u = (uint32_t)c;
+  if (u >= (uint32_t)n) u = u - (uint32_t)n < (uint32_t)n ? u - (uint32_t)n : u % (uint32_t)n;
+  return u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restrict__ st, InstDesc d, int m,
+                                                           int64_t block0, double* __restrict__ omega_out,
+                                                           int32_t* __restrict__ wind_out) {
+#pragma clang fp contract(off)
+  __shared__ double S[kVortLH][kVortLW];
+  const int64_t ntx = (d.nx + kVortW - 1) / kVortW, blk = block0 + blockIdx.x;
+  const int64_t x0 = (blk % ntx) * kVortW, y0 = (blk / ntx) * kVortH;
+  const cx<T>* pa = st + d.off + (int64_t)m * d.stride;
+  const cx<T>* pb = st + d.off + (int64_t)(5 + m) * d.stride;
+  cx<T> v[kVortLoads];
+#pragma unroll
+  for (int r = 0; r < kVortLoads; ++r) {
+    const int i = threadIdx.x + r * kVortThreads;
+    if (i < kVortLH * kVortLW) {
+      const int ly = i / kVortLW, lx = i - ly * kVortLW;
+      const int64_t s = (int64_t)wrap_coord(y0 - 1 + ly, d.ny) * d.nx + wrap_coord(x0 - 1 + lx, d.nx);
+      v[r] = pa[s] + pb[s];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kVortLoads; ++r) {
+    const int i = threadIdx.x + r * kVortThreads;
+    if (i < kVortLH * kVortLW) (&S[0][0])[i] = phase_of((double)v[r].re, (double)v[r].im);
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kVortW;
+  const int64_t x = x0 + lx;
+  if (x >= d.nx) return;
+  const int64_t base = d.psi_off / 5;
+  for (int k = threadIdx.x / kVortW; k < kVortH; k += kVortThreads / kVortW) {
+    const int64_t y = y0 + k;
+    if (y >= d.ny) break;
+    const int j = k + 1, i = lx + 1;
+    const int64_t o = base + y * d.nx + x;
+    if (omega_out) {
+      const double vy_p = wrap_pi(S[j + 1][i + 1] - S[j - 1][i + 1]) / 2.0;
+      const double vy_m = wrap_pi(S[j + 1][i - 1] - S[j - 1][i - 1]) / 2.0;
+      const double vx_p = wrap_pi(S[j + 1][i + 1] - S[j + 1][i - 1]) / 2.0;
+      const double vx_m = wrap_pi(S[j - 1][i + 1] - S[j - 1][i - 1]) / 2.0;
+      omega_out[o] = (((vy_p - vy_m) - vx_p) + vx_m) / 2.0;
+    }
+    if (wind_out) {
+      const double s00 = S[j][i], s10 = S[j][i + 1], s11 = S[j + 1][i + 1], s01 = S[j + 1][i];
+      const double circ = ((wrap_pi(s10 - s00) + wrap_pi(s11 - s10)) + wrap_pi(s01 - s11)) + wrap_pi(s00 - s01);
+      wind_out[o] = (int32_t)rint(circ / kTwoPi);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, double* n, double* f_par,
+                         double* f_perp, double* a00, hipStream_t st) {
+  if (g.nchunks == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fields<float>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<float>*)state, g, n,
+                       f_par, f_perp, a00);
+  else
+    hipLaunchKernelGGL(k_fields<double>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<double>*)state, g,
+                       n, f_par, f_perp, a00);
+  return hipGetLastError();
+}
+
+static int64_t vorticity_blocks(const InstDesc& d) {
+  return (int64_t)((d.nx + kVortW - 1) / kVortW) * ((d.ny + kVortH - 1) / kVortH);
+}
+
+hipError_t launch_vorticity(int dtype, const void* state, const InstDesc& d, int m, double* omega,
+                            int32_t* winding, hipStream_t st) {
+  // pieces of at most 2^22 workgroups keep every launch far below 2^32 work-items
+  constexpr int64_t kPiece = int64_t(1) << 22;
+  const int64_t nb = vorticity_blocks(d);
+  for (int64_t b0 = 0; b0 < nb; b0 += kPiece) {
+    const unsigned n = (unsigned)(nb - b0 < kPiece ? nb - b0 : kPiece);
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_vorticity<float>, dim3(n), dim3(kVortThreads), 0, st, (const cx<float>*)state, d, m,
+                         b0, omega, winding);
+    else
+      hipLaunchKernelGGL(k_vorticity<double>, dim3(n), dim3(kVortThreads), 0, st, (const cx<double>*)state, d,
+                         m, b0, omega, winding);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace qlg

@@ -26,7 +26,7 @@ RECORD_DOUBLES = 16   # QLG_RECORD_DOUBLES
 # every symbol declared in include/qlg.h
 EXPORTED = [
     "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
-    "qlg_get_qubits", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
+    "qlg_get_qubits", "qlg_fields", "qlg_vorticity", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
     "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_get_psi": (i32, [vp, vp]),
         "qlg_set_qubits": (i32, [vp, vp]),
         "qlg_get_qubits": (i32, [vp, vp]),
+        "qlg_fields": (i32, [vp, vp, vp, vp, vp]),
+        "qlg_vorticity": (i32, [vp, i32, vp, vp]),
         "qlg_step": (i32, [vp, i64]),
         "qlg_observables": (i32, [vp, P(Obs)]),
         "qlg_record_observables": (i32, [vp, vp]),
@@ -240,6 +242,39 @@ class Lattice:
         flat = torch.empty(10 * self.sites, dtype=self.torch_dtype, device=self.device)
         self._check(lib().qlg_get_qubits(self.ctx, flat.data_ptr()), "qlg_get_qubits")
         return self._unflat(flat, 10)
+
+    def _unflat_scalar(self, flat: torch.Tensor) -> List[torch.Tensor]:
+        out, o = [], 0
+        for i in range(self.nbatch):
+            n = self.nx[i] * self.ny[i]
+            out.append(flat[o:o + n].reshape(self._shape(i)[1:]))
+            o += n
+        return out
+
+    def fields(self, which: Sequence[str] = ("n", "f_par", "f_perp", "a00")) -> List[dict]:
+        """Per instance, the FP64 fields n, F_par, F_perp, |A00| (Sec. III eq. cmap) named in `which`."""
+        names = ("n", "f_par", "f_perp", "a00")
+        bad = [w for w in which if w not in names]
+        if bad or not which:
+            raise ValueError("fields must be a non-empty subset of %s" % (names,))
+        bufs = {w: torch.empty(self.sites, dtype=torch.float64, device=self.device) for w in which}
+        ptrs = [bufs[w].data_ptr() if w in bufs else None for w in names]
+        self._check(lib().qlg_fields(self.ctx, *ptrs), "qlg_fields")
+        per = {w: self._unflat_scalar(b) for w, b in bufs.items()}
+        return [{w: per[w][i] for w in which} for i in range(self.nbatch)]
+
+    def vorticity(self, m_index: int, omega: bool = True, winding: bool = True) -> List[dict]:
+        """Per instance {"omega": FP64 (ny, nx), "winding": int32 (ny, nx)} of component m_index (Sec. VI)."""
+        om = torch.empty(self.sites, dtype=torch.float64, device=self.device) if omega else None
+        wd = torch.empty(self.sites, dtype=torch.int32, device=self.device) if winding else None
+        self._check(lib().qlg_vorticity(self.ctx, int(m_index), om.data_ptr() if om is not None else None,
+                                        wd.data_ptr() if wd is not None else None), "qlg_vorticity")
+        out = [dict() for _ in range(self.nbatch)]
+        for key, buf in (("omega", om), ("winding", wd)):
+            if buf is not None:
+                for i, v in enumerate(self._unflat_scalar(buf)):
+                    out[i][key] = v
+        return out
 
     def step(self, nsteps: int = 1):
         self._check(lib().qlg_step(self.ctx, int(nsteps)), "qlg_step")
