@@ -18,6 +18,9 @@ the paper (Taylor, Smith, Yepez, arXiv:1907.12834):
 * scaling x -> a x, t -> a^2 t: Sec. VII "Scaling";
 * overlap energy E = i(<psi_t|psi_t> - <psi_t|psi_{t-1}>)/<psi_t|psi_t>: Sec. IV,
   eq. (disecrete_energy);
+* the optional psi-independent term (V(x) + mu) psi_m of Sec. II "Additional
+  terms" (external trap, chemical potential), a per-site phase inside U, and its
+  energy eps^d sum (V + mu) n;
 * per-site F_par, F_perp, |A00| (Sec. III, eq. cmap) and the lattice vorticity
   of one component from central differences of its phase, with plaquette
   winding numbers (Sec. VI, "Calculating quantum vorticity on a lattice").
@@ -167,8 +170,12 @@ def expm(M: torch.Tensor, max_terms: int = 18) -> torch.Tensor:
     return T
 
 
-def potential(a: torch.Tensor, b: torch.Tensor, theta: float, g: Sequence[float]):
-    """Apply W = e^{-i th g0 n} exp(-i th g1 F.f) P_A to a and b (same frozen W)."""
+def potential(a: torch.Tensor, b: torch.Tensor, theta: float, g: Sequence[float], ext=None):
+    """Apply W = e^{-i th (g0 n + ext)} exp(-i th g1 F.f) P_A to a and b (same frozen W).
+
+    ext (optional) is the m-independent term of the equation of motion that does not
+    depend on psi (Sec. II "Additional terms"): an external potential V(x) plus a
+    chemical potential mu, a real array of the spatial shape or a scalar."""
     g0, g1, g2 = g
     psi = a + b
     n, F, v = invariants(psi)
@@ -180,7 +187,8 @@ def potential(a: torch.Tensor, b: torch.Tensor, theta: float, g: Sequence[float]
     # spin factor R = exp(-i th g1 F.f), one 5x5 matrix exponential per site
     H = (F[0].reshape(-1, 1, 1) * FX + F[1].reshape(-1, 1, 1) * FY + F[2].reshape(-1, 1, 1) * FZ)
     R = expm(-1j * theta * g1 * H)                               # (sites, 5, 5)
-    dens = torch.exp(-1j * theta * g0 * n).reshape(-1)
+    phase = g0 * n if ext is None else g0 * n + torch.as_tensor(ext, dtype=RDT)
+    dens = torch.exp(-1j * theta * phase).reshape(-1)
 
     out = []
     for x in (a, b):
@@ -206,15 +214,25 @@ def kinetic_sequence(ndim: int):
     return [(ax, q[0]) for ax in axes for q in one]
 
 
-def step(a, b, eps: float, g, ndim: int, split: str = "interleaved"):
+def external(V=None, mu: float = 0.0):
+    """The psi-independent diagonal term V(x) + mu (None when both are absent)."""
+    if V is None:
+        return None if mu == 0.0 else mu
+    return torch.as_tensor(np.asarray(V, dtype=np.float64)) + mu
+
+
+def step(a, b, eps: float, g, ndim: int, split: str = "interleaved", V=None, mu: float = 0.0):
+    """One step; V (spatial shape, real) and mu add the term (V(x) + mu) psi_m to the
+    equation of motion, so U gains the phase e^{-i theta (V + mu)} per site."""
     seq = kinetic_sequence(ndim)
+    ext = external(V, mu)
     if split == "interleaved":
         theta = eps * eps / len(seq)
         for ax, q in seq:
-            a, b = potential(a, b, theta, g)
+            a, b = potential(a, b, theta, g, ext)
             a, b = iprime(a, b, ax, q)
     elif split == "plain":
-        a, b = potential(a, b, eps * eps, g)
+        a, b = potential(a, b, eps * eps, g, ext)
         for ax, q in seq:
             a, b = iprime(a, b, ax, q)
     else:
@@ -222,26 +240,26 @@ def step(a, b, eps: float, g, ndim: int, split: str = "interleaved"):
     return a, b
 
 
-def run(a, b, nsteps: int, eps: float, g, ndim: int, split: str = "interleaved"):
+def run(a, b, nsteps: int, eps: float, g, ndim: int, split: str = "interleaved", V=None, mu: float = 0.0):
     for _ in range(nsteps):
-        a, b = step(a, b, eps, g, ndim, split)
+        a, b = step(a, b, eps, g, ndim, split, V, mu)
     return a, b
 
 
-def run_psi(psi: np.ndarray, nsteps: int, eps: float, g, split: str = "interleaved"):
+def run_psi(psi: np.ndarray, nsteps: int, eps: float, g, split: str = "interleaved", V=None, mu: float = 0.0):
     """Convenience: encode a numpy psi (5, ...) field, run, return (a, b) tensors."""
     p = torch.from_numpy(np.ascontiguousarray(psi)).to(CDT)
     a, b = encode(p)
     ndim = p.dim() - 1
     with torch.no_grad():
-        return run(a, b, nsteps, eps, g, ndim, split)
+        return run(a, b, nsteps, eps, g, ndim, split, V, mu)
 
 
 # ---------------------------------------------------------------------------
 # Observables (Sec. IV overlap energy; continuum energy of eq. hamspin2)
 # ---------------------------------------------------------------------------
-def energy(psi: torch.Tensor, eps: float, g) -> torch.Tensor:
-    """E = eps^d sum_x [ sum_axis |psi(x+e) - psi(x)|^2 / eps^2
+def energy(psi: torch.Tensor, eps: float, g, V=None, mu: float = 0.0) -> torch.Tensor:
+    """E = eps^d sum_x [ sum_axis |psi(x+e) - psi(x)|^2 / eps^2 + (V + mu) n
                          + (g0 n^2 + g1 |F|^2 + g2 |sigma|^2 / 5) / 2 ].
 
     The kinetic term is the forward-difference form of psi^H (-lap) psi with
@@ -257,10 +275,14 @@ def energy(psi: torch.Tensor, eps: float, g) -> torch.Tensor:
     sigma = (v.conj() * psi).sum(0)
     f2 = F[0] ** 2 + F[1] ** 2 + F[2] ** 2
     pot = 0.5 * (g0 * n * n + g1 * f2 + g2 * sigma.abs() ** 2 / 5).sum()
+    ext = external(V, mu)
+    if ext is not None:
+        pot = pot + (ext * n).sum()
     return (eps ** d) * (kin + pot)
 
 
-def observables(a, b, eps: float, g, prev_psi: Optional[torch.Tensor] = None) -> Dict[str, float]:
+def observables(a, b, eps: float, g, prev_psi: Optional[torch.Tensor] = None, V=None,
+                mu: float = 0.0) -> Dict[str, float]:
     d = a.dim() - 1
     meas = eps ** d
     psi = a + b
@@ -268,7 +290,7 @@ def observables(a, b, eps: float, g, prev_psi: Optional[torch.Tensor] = None) ->
         "norm_q": float(meas * ((a.abs() ** 2).sum() + (b.abs() ** 2).sum())),
         "norm_psi": float(meas * (psi.abs() ** 2).sum()),
         "pop": [float(meas * (psi[i].abs() ** 2).sum()) for i in range(5)],
-        "energy": float(energy(psi, eps, g)),
+        "energy": float(energy(psi, eps, g, V, mu)),
     }
     if prev_psi is not None:
         nn = (psi.abs() ** 2).sum()

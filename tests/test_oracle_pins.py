@@ -761,3 +761,99 @@ def test_vorticity_small_lattices():
         assert om.shape == shape and np.isfinite(om).all()
         # the total winding of a periodic lattice is zero
         assert int(wind.sum()) == 0
+
+
+# ---------------------------------------------------------------------------
+# P12: external potential and chemical potential (Sec. II "Additional terms"; Sec. IV dispersion)
+# ---------------------------------------------------------------------------
+def _trap_1d(eps, omega=1.0, half_width=10.0):
+    """Lattice X = eps (i - L/2) and the harmonic trap V = omega^2 X^2 / 4 (m = 1/2: V = m omega^2 X^2 / 2)."""
+    L = int(round(2 * half_width / eps))
+    X = eps * (np.arange(L) - L / 2)
+    return X, omega ** 2 * X ** 2 / 4
+
+
+def _spinor(profile, seed=5):
+    rng = np.random.default_rng(seed)
+    c = rng.normal(size=5) + 1j * rng.normal(size=5)
+    return c.reshape((5,) + (1,) * profile.ndim) * profile[None]
+
+
+def test_harmonic_trap_ground_state_energy():
+    """Free spinor in a harmonic trap: the ground state exp(-omega X^2/4) in every component has
+    E = omega/2 (overlap energy of one step, which converges fast) and the lattice energy per
+    particle tends to omega/2 at second order.  A wrong factor or sign of V, or V applied with the
+    wrong theta, moves E by O(1)."""
+    errs = []
+    for eps in (0.2, 0.1):
+        X, V = _trap_1d(eps)
+        psi = _spinor(np.exp(-X ** 2 / 4))
+        a, b = O.encode(t(psi))
+        a1, b1 = O.step(a, b, eps, (0.0, 0.0, 0.0), 1, V=V)
+        ob = O.observables(a1, b1, eps, (0.0, 0.0, 0.0), prev_psi=a + b, V=V)
+        assert abs(ob["e_overlap"].real / eps ** 2 - 0.5) < 1e-4, (eps, ob["e_overlap"])
+        errs.append(abs(ob["energy"] / ob["norm_psi"] - 0.5))
+    assert errs[1] < 1e-3 and 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_harmonic_trap_oscillation():
+    """A displaced ground state oscillates as <X>(t) = X0 cos(omega t) (exact in the continuum for a
+    quadratic potential); the lattice error falls faster than 4x per halving of eps."""
+    X0, errs = 2.0, []
+    for eps in (0.2, 0.1):
+        X, V = _trap_1d(eps)
+        psi = _spinor(np.exp(-(X - X0) ** 2 / 4))
+        n_half = int(round(np.pi / eps ** 2))
+        out = psi
+        for nst in (n_half // 2, n_half - n_half // 2):     # quarter and half period
+            A, B = O.run_psi(out, nst, eps, (0.0, 0.0, 0.0), V=V)
+            out = (A + B).numpy()
+        n = (np.abs(out) ** 2).sum(0)
+        xm = float((n * X).sum() / n.sum())
+        errs.append(abs(xm - X0 * np.cos(n_half * eps ** 2)))
+    assert errs[1] < 5e-4 and errs[0] / errs[1] > 4.0, errs
+
+
+def test_harmonic_trap_2d_anisotropic():
+    """2D trap V = (wx^2 X^2 + wy^2 Y^2)/4: the product ground state has E = (wx + wy)/2 (here 1.5),
+    reached at second order in eps, so the potential enters both axes' substeps with the right theta."""
+    wx, wy, errs = 1.0, 2.0, []
+    for eps in (0.2, 0.1):
+        n = int(round(16 / eps))
+        X = eps * (np.arange(n) - n / 2)
+        Y = X[:, None]
+        V = (wx ** 2 * X[None, :] ** 2 + wy ** 2 * Y ** 2) / 4
+        psi = _spinor(np.exp(-wx * X[None, :] ** 2 / 4 - wy * Y ** 2 / 4))
+        a, b = O.encode(t(psi))
+        a1, b1 = O.step(a, b, eps, (0.0, 0.0, 0.0), 2, V=V)
+        ob = O.observables(a1, b1, eps, (0.0, 0.0, 0.0), prev_psi=a + b, V=V)
+        errs.append(abs(ob["e_overlap"].real / eps ** 2 - (wx + wy) / 2))
+    assert errs[1] < 2e-3 and 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+@pytest.mark.parametrize("split", ["interleaved", "plain"])
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_chemical_potential_is_a_global_phase(split, ndim):
+    """mu psi_m in the equation of motion multiplies the state by e^{-i mu t}: after n steps the
+    run with mu equals the run without it times e^{-i mu eps^2 n}, also with interactions and a trap."""
+    shape = (24,) if ndim == 1 else (12, 10)
+    psi = qi.random_field(shape, seed=9, scale=0.5)
+    V = np.random.default_rng(2).uniform(0, 3, size=shape)
+    g, eps, mu, nst = (1.1, -0.6, 0.8), 0.3, 1.7, 6
+    A0, B0 = O.run_psi(psi, nst, eps, g, split, V=V)
+    A1, B1 = O.run_psi(psi, nst, eps, g, split, V=V, mu=mu)
+    ph = np.exp(-1j * mu * eps ** 2 * nst)
+    assert torch.allclose(A1, A0 * ph, atol=1e-12) and torch.allclose(B1, B0 * ph, atol=1e-12)
+
+
+def test_bright_soliton_dispersion_with_chemical_potential():
+    """Sec. IV: with a chemical potential the bright-soliton dispersion is E = mu + p^2 - k^2."""
+    w, mu = 24, 0.7
+    for p in (0.0, 0.5):
+        psi, eps = _bright(w, p=p)
+        A, B = O.run_psi(psi, 40, eps, G_BRIGHT, mu=mu)
+        prev = A + B
+        a1, b1 = O.step(A, B, eps, G_BRIGHT, 1, mu=mu)
+        obs = O.observables(a1, b1, eps, G_BRIGHT, prev_psi=prev, mu=mu)
+        e = obs["e_overlap"].real / eps ** 2
+        assert abs(e - (mu + p * p - 1.0)) < 0.01 * max(1.0, abs(mu + p * p - 1.0)), (p, e)
