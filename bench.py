@@ -48,15 +48,17 @@ OBS_EVERY = 100
 # for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "dcf3472a8b618536", "fetch_scale": 262144.0 / 131088.5, "write_scale": 1.0,
-           "kib": {"k_step1d/S4": (778.5, 1280.0), "k_step1d/S5": (789.3, 1280.0), "k_step1d/S6": (820.1, 1280.9),
-                   "k_step1d/S7": (791.6, 1280.0), "k_step1d_pair/S1": (767.7, 1280.0),
-                   "k_step1d_pair/S2": (768.4, 1280.0), "k_step1d_pair/S3": (767.9, 1280.0),
-                   "k_step1d_pair/S4": (767.0, 1280.0),
+TRAFFIC = {"sources_sha256_16": "7937ff896441d2cc", "fetch_scale": 262144.0 / 131088.6, "write_scale": 1.0,
+           "kib": {"k_step1d/S1": (783.6, 1280.0), "k_step1d/S2": (784.4, 1280.0), "k_step1d/S3": (783.9, 1280.0),
+                   "k_step1d/S4": (783.0, 1280.0), "k_step1d/S5": (793.8, 1280.0), "k_step1d/S6": (833.5, 1281.0),
+                   "k_step1d/S7": (796.1, 1280.0), "k_step1d_pair/S1": (762.7, 1280.0),
+                   "k_step1d_pair/S2": (763.4, 1280.0), "k_step1d_pair/S3": (762.9, 1280.0),
+                   "k_step1d_pair/S4": (762.0, 1280.0),
                    # 2D vortex-pair workload, 2048^2 (bands of rows)
-                   "k_step2d/rows38": (234475.5, 328540.3), "k_step2d/rows76": (214238.4, 328207.7),
-                   "k_step2d/rows19": (260433.1, 329046.7), "k_step2d/rows16": (273323.4, 330070.9),
-                   "k_step2d/rows128": (182755.1, 327965.2)}}
+                   "k_step2d/rows38": (234817.7, 328501.9), "k_step2d/rows76": (214313.9, 328202.3),
+                   "k_step2d/rows64": (220021.2, 328337.3), "k_step2d/rows32": (231682.5, 328670.1),
+                   "k_step2d/rows25": (238789.6, 329221.1), "k_step2d/rows19": (260713.5, 329018.8),
+                   "k_step2d/rows16": (273047.8, 330039.3), "k_step2d/rows128": (182792.4, 327976.4)}}
 
 
 def parse():
@@ -77,6 +79,8 @@ def parse():
                     help="steps of the batched-vs-one-at-a-time comparison (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward+adjoint vs forward comparison (0 = skip)")
+    ap.add_argument("--trap-steps", type=int, default=4000,
+                    help="steps of the same workload with a harmonic trap and chemical potential (0 = skip)")
     ap.add_argument("--diag-reps", type=int, default=50,
                     help="launches of the per-site field and vorticity kernels timed on the workload's "
                          "lattice (0 = skip)")
@@ -107,8 +111,20 @@ def workload_input(name, steps):
     return qi.c2_two_solitons(nsteps=steps) if name == "1d_two_soliton_scattering" else qi.c3_vortex_pair(nsteps=steps)
 
 
-def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="interleaved"):
-    """Run the workload; return rate, wall time, per-launch kernel time and plan."""
+def trap_potential(w, ndim):
+    """A weak harmonic trap V = omega^2 r^2 / 4 centred on the lattice (m = 1/2), with omega chosen
+    so that V reaches 1/2 at the edge midpoints, plus mu = 0.5."""
+    import numpy as np
+    half = [0.5 * w.eps * n for n in ([w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]])]
+    omega = math.sqrt(2.0) / max(half)
+    axes = [w.eps * (np.arange(n) - n / 2) for n in ([w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]])]
+    r2 = axes[0] ** 2 if ndim == 1 else axes[0][:, None] ** 2 + axes[1][None, :] ** 2
+    return omega ** 2 * r2 / 4, 0.5
+
+
+def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="interleaved", trap=False):
+    """Run the workload (with a harmonic trap and mu if `trap`); return rate, wall time,
+    per-launch kernel time and plan."""
     import torch
     from paper_1907_12834_amd.qlg import Lattice
 
@@ -116,6 +132,8 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     ndim = WORKLOADS[workload][0]
     L = w.nx[0] * (w.ny[0] if ndim == 2 else 1)   # sites
     lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype, split=split)
+    if trap:
+        lat.set_potential(*trap_potential(w, ndim))
     lat.set_psi([torch.from_numpy(w.psi[0])])
     tuning = lat.autotune()
     lat.set_tuning(use_graph=True)
@@ -319,6 +337,14 @@ def main():
     batched = batched_ratio(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = adjoint_ratio(args.adjoint_steps, 64) if args.adjoint_steps > 0 else None
     diag = diagnostics(args.workload, args.dtype, args.diag_reps) if args.diag_reps > 0 else None
+    potential = None
+    if args.trap_steps > 0:
+        mt = measure(args.dtype, args.trap_steps, min(args.warmup, 200), args.workload, args.split, trap=True)
+        potential = {"what": "the same workload in a harmonic trap V = omega^2 r^2/4 (V = 1/2 at the edge "
+                             "midpoints) with mu = 0.5", "steps": args.trap_steps, "value": mt["value"],
+                     "unit": "site-updates/s", "kernel_ms_avg": mt["kern_ms"], "plan": mt["tuning"],
+                     "kernel_time_vs_no_potential": (mt["kern_ms"] / kern_ms) if kern_ms > 0 else None,
+                     "norm_drift": mt["drift"]}
     cpu = cpu_baseline(w, args.cpu_steps if ndim == 1 else max(1, args.cpu_steps // 500), ndim) \
         if args.cpu_steps > 0 else None
 
@@ -367,6 +393,7 @@ def main():
         "batched": batched,
         "adjoint": adjoint,
         "diagnostics": diag,
+        "potential": potential,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

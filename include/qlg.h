@@ -133,6 +133,20 @@ qlg_status qlg_get_psi(qlg_ctx* ctx, void* psi_dev);
 qlg_status qlg_set_qubits(qlg_ctx* ctx, const void* qubits_dev);
 qlg_status qlg_get_qubits(qlg_ctx* ctx, void* qubits_dev);
 
+/* External and chemical potential (Sec. II, "Additional terms"): the equation of
+ * motion of every component gains (V(x) + mu) psi_m, so each self-interaction U
+ * gains the per-site phase exp(-i theta (V(x) + mu)) and the energy of qlg_obs
+ * gains eps^d sum (V + mu) n.  V_dev: device memory owned by the caller, FP64,
+ * 8-byte aligned, in the canonical scalar layout of qlg_fields (nbatch * sites
+ * doubles), or NULL for no potential; the library keeps the pointer, and every
+ * later qlg_step and observables call reads it, so it must stay allocated until
+ * the potential is replaced or the context destroyed (its values may change
+ * between calls).  mu: finite, else QLG_ERR_ARG.  qlg_set_potential(ctx, NULL, 0)
+ * returns to the plain equation.  While a potential is set the adjoint entry
+ * points (qlg_forward_record, qlg_objective_grad, qlg_adjoint_step) return
+ * QLG_ERR_STATE.  Host-side only; drops the captured step graphs. */
+qlg_status qlg_set_potential(qlg_ctx* ctx, const double* V_dev, double mu);
+
 /* Per-site diagnostic fields of the current state (Sec. III, eq. (cmap)), in
  * FP64, each in the canonical scalar layout: the instances back to back, each
  * [ny][nx] row-major (x fastest), nbatch * sites doubles in all:

@@ -76,6 +76,8 @@ qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t c
 qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t K, void* ckpt_dev, size_t ckpt_bytes) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  if (qlg::ctx_view(ctx).has_ext)
+    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   qlg::CtxView v = qlg::ctx_view(ctx);
   Sizes s;
   qlg_status st = sizes_for(v.p, nsteps, K, &s);
@@ -98,6 +100,8 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
                               double* value_host, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  if (qlg::ctx_view(ctx).has_ext)
+    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   if (!lambda_dev || !value_host) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or value pointer is NULL");
   if (kind != 0 && kind != 1) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "kind must be 0 (energy) or 1 (fidelity)");
   if (kind == 1 && !target_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "fidelity needs a target");
@@ -140,6 +144,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
                             void* work_dev, size_t work_bytes, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  if (qlg::ctx_view(ctx).has_ext)
+    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   const qlg::CtxView v = qlg::ctx_view(ctx);
   const qlg_params& p = *v.p;
   Sizes s;

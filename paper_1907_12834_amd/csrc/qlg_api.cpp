@@ -138,6 +138,7 @@ struct qlg_ctx {
   int32_t* d_chunk2inst = nullptr;
   int32_t ntiles = 0;
   qlg_tuning tuning{1, 32, 0, 0};
+  qlg::ExtPot ext;               // external potential (caller's device array) and mu
   bool tuned = false;
   // bookkeeping
   int64_t step_count = 0;
@@ -232,12 +233,13 @@ hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void
   const LaunchGeom g = c->geom();
   double* ov = c->sc(c->S.ov_part);
   const bool plain = c->p.split == QLG_SPLIT_PLAIN;
+  qlg::ExtPot ext = c->ext;
+  ext.theta = th;
   if (c->p.ndim == 1)
     return qlg::launch_step1d(c->p.dtype, steps, c->tuning.pair_waves != 0, plain, overlap, in, out, g,
-                              th * c->p.g0, th * c->p.g1,
-                              th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
+                              th * c->p.g0, th * c->p.g1, th * c->p.g2 / 5.0, ext, ov, c->stream, ev0, ev1);
   return qlg::launch_step2d(c->p.dtype, plain, overlap, c->tuning.tile_rows, in, out, g, th * c->p.g0,
-                            th * c->p.g1, th * c->p.g2 / 5.0, ov, c->stream, ev0, ev1);
+                            th * c->p.g1, th * c->p.g2 / 5.0, ext, ov, c->stream, ev0, ev1);
 }
 
 // Enqueue nsteps as passes of steps_per_pass (1D) or single steps (2D), ping-ponging
@@ -387,7 +389,7 @@ void qlg_destroy(qlg_ctx* c) {
 static qlg_status enqueue_record(qlg_ctx* c, double* rec, bool reference) {
   const LaunchGeom g = c->geom();
   hipError_t e = qlg::launch_observables(c->p.dtype, c->p.ndim, c->copy(c->cur), g, c->p.g0, c->p.g1, c->p.g2,
-                                         c->sc(c->S.obs_part), c->stream);
+                                         c->ext, c->sc(c->S.obs_part), c->stream);
   if (e != hipSuccess) return hip_check(c, e, "observables kernel");
   const double* ov = (!reference && c->has_overlap) ? c->sc(c->S.ov_part) : nullptr;
   const double* ref = (!reference && c->norm0_valid) ? c->sc(c->S.norm0) : nullptr;
@@ -436,6 +438,17 @@ qlg_status qlg_get_qubits(qlg_ctx* c, void* qb) {
   if (!qb) return fail(c, QLG_ERR_ARG, "qubits is NULL");
   return hip_check(c, qlg::launch_get_qubits(c->p.dtype, c->copy(c->cur), qb, c->geom(), c->stream),
                    "get_qubits kernel");
+}
+
+qlg_status qlg_set_potential(qlg_ctx* c, const double* V, double mu) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (!std::isfinite(mu)) return fail(c, QLG_ERR_ARG, "mu must be finite");
+  if (V && (reinterpret_cast<uintptr_t>(V) & 7u)) return fail(c, QLG_ERR_ARG, "V must be 8-byte aligned");
+  c->ext.V = V;
+  c->ext.mu = mu;
+  drop_graphs(c);   // captured launches carry the previous kernel and arguments
+  return QLG_OK;
 }
 
 qlg_status qlg_fields(qlg_ctx* c, double* n, double* f_par, double* f_perp, double* a00) {
@@ -724,6 +737,7 @@ CtxView ctx_view(qlg_ctx* c) {
   v.geom = c->geom();
   v.part = c->sc(c->S.obs_part);
   v.res = c->sc(c->S.obs_res);
+  v.has_ext = c->ext.on();
   return v;
 }
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg) { return fail(c, s, msg); }

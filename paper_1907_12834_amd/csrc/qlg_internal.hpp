@@ -35,23 +35,35 @@ struct LaunchGeom {
   int32_t ntiles, nchunks, nbatch;
 };
 
+// The psi-independent diagonal term (V(x) + mu) psi_m of the equation of motion
+// (Sec. II, "Additional terms"): V per site in the canonical scalar layout (FP64,
+// [instance][y][x]; nullptr: none) and a uniform mu.  theta is the interleaved
+// angle eps^2 / (4 d); the plain split uses eps^2.
+struct ExtPot {
+  const double* V = nullptr;
+  double mu = 0.0;
+  double theta = 0.0;
+  bool on() const { return V != nullptr || mu != 0.0; }
+};
+
 // Kernel launchers (qlg_kernels.hip).  All return the hipError_t of the launch.
 // dtype: 0 = complex64, 1 = complex128.  Angles are theta*g0, theta*g1, theta*g2/5.
 // ev0/ev1 (optional): events the dispatch packet itself stamps at kernel start/end.
 // pair: the k_step1d_pair variant (a and b of a tile on two wavefronts).
 hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
+                         double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
+                         double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_set_psi(int dtype, const void* psi, void* state, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_get_psi(int dtype, const void* state, void* psi, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_set_qubits(int dtype, const void* qb, void* state, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_get_qubits(int dtype, const void* state, void* qb, const LaunchGeom& g, hipStream_t st);
-// Per-chunk partial sums of the kNObs observables into part[nchunks][kNObs].
+// Per-chunk partial sums of the kNObs observables into part[nchunks][kNObs]; the
+// potential energy density includes (V + mu) n.
 hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
-                              double g1, double g2, double* part, hipStream_t st);
+                              double g1, double g2, const ExtPot& ext, double* part, hipStream_t st);
 // Per-instance record rec[nbatch][kRecord] from the chunk partials, the per-tile
 // overlap partials (ovpart may be null) and a reference record (ref may be null).
 hipError_t launch_record(const LaunchGeom& g, const double* part, const double* ovpart, const double* ref,

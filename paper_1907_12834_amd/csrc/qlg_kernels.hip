@@ -102,12 +102,21 @@ struct StepArgs {
   Angles<T> ang[4];              // interleaved U^{1/(4d)}, theta = eps^2 / (4 d), for a state
                                  // scaled by 4^j (substep j of a four-I' sequence)
   Angles<T> ang_full;            // plain split: theta = eps^2, unscaled state
+  const double* __restrict__ pot;  // V(x), canonical scalar layout (nullptr: none); kExt kernels only
+  double mu;                     // chemical potential; kExt kernels only
+  T th_ext;                      // theta of the (V + mu) phase: eps^2/(4d), or eps^2 for the plain split
   int32_t ntiles;
   int32_t steps;                 // 1D: steps fused in this pass
   int32_t tile_rows;             // 2D: rows per streaming tile
   int32_t plain;                 // 1: plain split, 0: interleaved
   int32_t overlap;               // 1: record <psi_t|psi_{t-1}> of the last step
 };
+
+// theta (V + mu) at site s of instance d: the per-site angle of the (V + mu) phase
+template <typename T>
+__device__ __forceinline__ T ext_angle(const StepArgs<T>& A, const InstDesc& d, int64_t s) {
+  return A.th_ext * T((A.pot ? A.pot[d.psi_off / 5 + s] : 0.0) + A.mu);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its
 // own L2.  Give each XCD a contiguous range of logical workgroups, so that tiles
@@ -125,7 +134,7 @@ __device__ __forceinline__ int xcd_contiguous_block(int b, int nblocks) {
 // Substep k = 0..3 of a 1D step is [U] I'_{x,q} with q = b, b, a, a (Sec. VII:
 // psi(t+tau) = I'_1 U I'_1 U I'_2 U I'_2 U psi(t), rightmost first); the plain
 // split applies one U with theta = eps^2 before the first I' only.
-template <typename T>
+template <typename T, bool kExt>
 __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
   const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (w >= A.ntiles) return;   // whole wavefronts only; no block-level synchronisation below
@@ -143,6 +152,9 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
     a[m] = src[m * d.stride];
     b[m] = src[(5 + m) * d.stride];
   }
+  // each lane keeps its site for the whole pass: one (V + mu) angle per lane
+  T ext = T(0);
+  if constexpr (kExt) ext = ext_angle(A, d, xw);
   const bool plain = A.plain != 0;
   cx<T> pold[5];
   // one step: [U] I'_{x,b} [U] I'_{x,b} [U] I'_{x,a} [U] I'_{x,a}; the moving qubit is
@@ -157,12 +169,12 @@ __global__ __launch_bounds__(256) void k_step1d(StepArgs<T> A) {
     }
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain || j == 0) potential(a, b, plain ? A.ang_full : substep_angles(A.ang, j));
+      if (!plain || j == 0) potential<T, kExt>(a, b, plain ? A.ang_full : substep_angles(A.ang, j), ext);
       iprime4_lanes<T, 1>(a, b);
     }
 #pragma unroll 1
     for (int j = 2; j < 4; ++j) {
-      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), ext);
       iprime4_lanes<T, 0>(a, b);
     }
     scale_by(a, b, T(1.0 / 256.0));
@@ -247,13 +259,14 @@ struct PairXchg {
 };
 
 // One substep [U] I'_{x,Q} on this wave's qubit x (Q: qubit that streams).
-template <typename T, int Q>
-__device__ __forceinline__ void pair_substep(cx<T> (&x)[5], PairXchg<T>& X, bool with_u, const Angles<T>& ang) {
+template <typename T, int Q, bool kExt>
+__device__ __forceinline__ void pair_substep(cx<T> (&x)[5], PairXchg<T>& X, bool with_u, const Angles<T>& ang,
+                                             T ext) {
   cx<T> y[5];
   X.swap(x, y);
   if (with_u) {
     WCoef<T> W;
-    w_coefficients(x, y, ang, W);   // psi = x + y, the same sum on both waves
+    w_coefficients<T, kExt>(x, y, ang, W, ext);   // psi = x + y, the same sum on both waves
     collide_own(x, y);
     w_apply(x, W);
   } else {
@@ -272,7 +285,7 @@ __device__ __forceinline__ void pair_substep(cx<T> (&x)[5], PairXchg<T>& X, bool
   }
 }
 
-template <typename T>
+template <typename T, bool kExt>
 __global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T> A) {
   __shared__ T xbuf[2][kPairWaves][10][kLanes];
   // Every wave of the workgroup takes part in every barrier: a workgroup whose
@@ -294,6 +307,8 @@ __global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T>
 #pragma unroll
   for (int m = 0; m < 5; ++m) x[m] = src[m * d.stride];
   PairXchg<T> X{xbuf, q, v, lane, 0};
+  T ext = T(0);
+  if constexpr (kExt) ext = ext_angle(A, d, xw);
   const bool plain = A.plain != 0;
   cx<T> pold[5];
 #pragma unroll 1
@@ -306,9 +321,9 @@ __global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T>
     }
 #pragma unroll 1
     for (int j = 0; j < 2; ++j)
-      pair_substep<T, 1>(x, X, !plain || j == 0, plain ? A.ang_full : substep_angles(A.ang, j));
+      pair_substep<T, 1, kExt>(x, X, !plain || j == 0, plain ? A.ang_full : substep_angles(A.ang, j), ext);
 #pragma unroll 1
-    for (int j = 2; j < 4; ++j) pair_substep<T, 0>(x, X, !plain, substep_angles(A.ang, j));
+    for (int j = 2; j < 4; ++j) pair_substep<T, 0, kExt>(x, X, !plain, substep_angles(A.ang, j), ext);
 #pragma unroll
     for (int m = 0; m < 5; ++m) x[m] = T(1.0 / 256.0) * x[m];
   }
@@ -387,7 +402,7 @@ __device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>*
 constexpr int kStageSlots = 4 * 10;
 constexpr int k2DWaves = 2;   // wavefronts per workgroup of the 2D kernel
 
-template <typename T>
+template <typename T, bool kExt>
 __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   // Per-lane pipeline buffers live in LDS; every lane reads back only the
   // slots it wrote itself, so no barrier is needed anywhere in the kernel.
@@ -415,7 +430,8 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   // the arithmetic of the row before it (complex128 has no registers to spare for it:
   // the extra row would halve its occupancy)
   constexpr bool kAhead = sizeof(T) == 4;
-  auto load_row = [&](int r, cx<T>(&a)[5], cx<T>(&b)[5]) {
+  // with kExt, e is the (V + mu) angle of the row's site in this lane
+  auto load_row = [&](int r, cx<T>(&a)[5], cx<T>(&b)[5], T& e) {
     const int yw = (int)wrap64(y0 - 4 + r, ny);
     const cx<T>* src = A.in + d.off + (int64_t)yw * nx + xw;
 #pragma unroll
@@ -423,21 +439,35 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
       a[m] = src[m * d.stride];
       b[m] = src[(5 + m) * d.stride];
     }
+    if constexpr (kExt) e = ext_angle(A, d, (int64_t)yw * nx + xw);
   };
+  // (V + mu) angles of the rows at the four y stages and of the row leaving for the
+  // x half: stage j works on the row loaded j iterations ago, the x half on the row
+  // loaded four iterations ago
+  T e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0), e4 = T(0), ne = T(0);
   cx<T> na[5], nb[5];
-  if (kAhead) load_row(0, na, nb);
+  if (kAhead) load_row(0, na, nb, ne);
 #pragma unroll 1
   for (int r = 0; r < nrows; ++r) {
     cx<T> a[5], b[5];
+    T en = T(0);
     if (kAhead) {
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         a[m] = na[m];
         b[m] = nb[m];
       }
-      if (r + 1 < nrows) load_row(r + 1, na, nb);
+      en = ne;
+      if (r + 1 < nrows) load_row(r + 1, na, nb, ne);
     } else {
-      load_row(r, a, b);
+      load_row(r, a, b, en);
+    }
+    if constexpr (kExt) {
+      e4 = e3;
+      e3 = e2;
+      e2 = e1;
+      e1 = e0;
+      e0 = en;
     }
     // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y; slot k of this lane's LDS
     // holds stage k's pending rows.  The plain split applies its single U at stage 0.
@@ -446,12 +476,13 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
     // scale; one exact multiplication by 1/256 ends each half.
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain || j == 0) potential(a, b, plain ? A.ang_full : substep_angles(A.ang, j));
+      if (!plain || j == 0)
+        potential<T, kExt>(a, b, plain ? A.ang_full : substep_angles(A.ang, j), j == 0 ? e0 : e1);
       y_stage_lds<T, 1>(a, b, my + j * 10 * kLanes);
     }
 #pragma unroll 1
     for (int j = 2; j < 4; ++j) {
-      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), j == 2 ? e2 : e3);
       y_stage_lds<T, 0>(a, b, my + j * 10 * kLanes);
     }
     if (r < 8) continue;
@@ -459,12 +490,12 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
     scale_by(a, b, T(1.0 / 256.0));
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), e4);
       iprime4_lanes<T, 1>(a, b);
     }
 #pragma unroll 1
     for (int j = 2; j < 4; ++j) {
-      if (!plain) potential(a, b, substep_angles(A.ang, j));
+      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), e4);
       iprime4_lanes<T, 0>(a, b);
     }
     scale_by(a, b, T(1.0 / 256.0));
@@ -599,6 +630,7 @@ __device__ __forceinline__ void load_psi_d(const cx<T>* __restrict__ st, const I
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict__ st, LaunchGeom g, int ndim,
                                                        double g0, double g1, double g2,
+                                                       const double* __restrict__ pot, double mu,
                                                        double* __restrict__ part) {
   const SiteRef r = site_of(g);
   double v[kNObs];
@@ -656,6 +688,8 @@ __global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict_
     const double si = 2.0 * (pr[0] * pi[4] + pi[0] * pr[4]) - 2.0 * (pr[1] * pi[3] + pi[1] * pr[3]) +
                       2.0 * pr[2] * pi[2];
     v[8] = 0.5 * (g0 * n * n + g1 * (Fx * Fx + Fy * Fy + Fz * Fz) + g2 * (sr * sr + si * si) / 5.0);
+    // external and chemical potential energy density (V + mu) n
+    if (pot || mu != 0.0) v[8] += ((pot ? pot[d.psi_off / 5 + r.s] : 0.0) + mu) * n;
   }
   block_sum_store(v, part + (int64_t)blockIdx.x * kNObs);
 }
@@ -711,8 +745,8 @@ static Angles<T> angles(double a, double b, double c) {
 
 template <typename T>
 static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, double tg0, double tg1,
-                             double tg25, double full_factor, double* ovpart, int steps, int rows,
-                             bool plain, bool overlap) {
+                             double tg25, double full_factor, const ExtPot& ext, double* ovpart, int steps,
+                             int rows, bool plain, bool overlap) {
   StepArgs<T> A;
   A.in = (const cx<T>*)in;
   A.out = (cx<T>*)out;
@@ -727,6 +761,9 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
     A.ang[j].fs = f;
   }
   A.ang_full = angles<T>(full_factor * tg0, full_factor * tg1, full_factor * tg25);
+  A.pot = ext.V;
+  A.mu = ext.mu;
+  A.th_ext = T(plain ? full_factor * ext.theta : ext.theta);
   A.ntiles = g.ntiles;
   A.steps = steps;
   A.tile_rows = rows;
@@ -746,46 +783,56 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
 }
 
 hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
+                         double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
   if (steps < 1 || 8 * steps >= kLanes) return hipErrorInvalidValue;
   // the plain split's single U uses theta = eps^2 = 4x the interleaved 1D angle
+  const bool xt = ext.on();
   if (pair) {
     const dim3 grid((g.ntiles + kPairTiles - 1) / kPairTiles), block(kLanes * kPairWaves);
-    if (dtype == 0)
-      launch_timed(k_step1d_pair<float>, grid, block, 0, st, ev0, ev1,
-                   step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
-    else
-      launch_timed(k_step1d_pair<double>, grid, block, 0, st, ev0, ev1,
-                   step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+    if (dtype == 0) {
+      const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+      if (xt) launch_timed(k_step1d_pair<float, true>, grid, block, 0, st, ev0, ev1, args);
+      else launch_timed(k_step1d_pair<float, false>, grid, block, 0, st, ev0, ev1, args);
+    } else {
+      const auto args = step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+      if (xt) launch_timed(k_step1d_pair<double, true>, grid, block, 0, st, ev0, ev1, args);
+      else launch_timed(k_step1d_pair<double, false>, grid, block, 0, st, ev0, ev1, args);
+    }
     return hipGetLastError();
   }
   const dim3 grid((g.ntiles + 3) / 4), block(256);
-  if (dtype == 0)
-    launch_timed(k_step1d<float>, grid, block, 0, st, ev0, ev1,
-                 step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
-  else
-    launch_timed(k_step1d<double>, grid, block, 0, st, ev0, ev1,
-                 step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ovpart, steps, 0, plain, overlap));
+  if (dtype == 0) {
+    const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+    if (xt) launch_timed(k_step1d<float, true>, grid, block, 0, st, ev0, ev1, args);
+    else launch_timed(k_step1d<float, false>, grid, block, 0, st, ev0, ev1, args);
+  } else {
+    const auto args = step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+    if (xt) launch_timed(k_step1d<double, true>, grid, block, 0, st, ev0, ev1, args);
+    else launch_timed(k_step1d<double, false>, grid, block, 0, st, ev0, ev1, args);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, double* ovpart,
-                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
+                         double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
   if (tile_rows < 1) return hipErrorInvalidValue;
   const dim3 grid((g.ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
   // 2D interleaved angles are eps^2/8; the plain split's single U uses eps^2 = 8x
+  const bool xt = ext.on();
   if (dtype == 0) {
     const size_t lds = sizeof(cx<float>) * kStageSlots * kLanes * k2DWaves;
-    launch_timed(k_step2d<float>, grid, block, lds, st, ev0, ev1,
-                 step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+    const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ext, ovpart, 1, tile_rows, plain, overlap);
+    if (xt) launch_timed(k_step2d<float, true>, grid, block, lds, st, ev0, ev1, args);
+    else launch_timed(k_step2d<float, false>, grid, block, lds, st, ev0, ev1, args);
   } else {
     const size_t lds = sizeof(cx<double>) * kStageSlots * kLanes * k2DWaves;
-    launch_timed(k_step2d<double>, grid, block, lds, st, ev0, ev1,
-                 step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ovpart, 1, tile_rows, plain, overlap));
+    const auto args = step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ext, ovpart, 1, tile_rows, plain, overlap);
+    if (xt) launch_timed(k_step2d<double, true>, grid, block, lds, st, ev0, ev1, args);
+    else launch_timed(k_step2d<double, false>, grid, block, lds, st, ev0, ev1, args);
   }
   return hipGetLastError();
 }
@@ -808,13 +855,13 @@ QLG_ELEMWISE(launch_set_qubits, k_set_qubits, const void*, void*)
 QLG_ELEMWISE(launch_get_qubits, k_get_qubits, const void*, void*)
 
 hipError_t launch_observables(int dtype, int ndim, const void* state, const LaunchGeom& g, double g0,
-                              double g1, double g2, double* part, hipStream_t st) {
+                              double g1, double g2, const ExtPot& ext, double* part, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_observables<float>, dim3(g.nchunks), dim3(kChunk), 0, st, (const cx<float>*)state,
-                       g, ndim, g0, g1, g2, part);
+                       g, ndim, g0, g1, g2, ext.V, ext.mu, part);
   else
     hipLaunchKernelGGL(k_observables<double>, dim3(g.nchunks), dim3(kChunk), 0, st,
-                       (const cx<double>*)state, g, ndim, g0, g1, g2, part);
+                       (const cx<double>*)state, g, ndim, g0, g1, g2, ext.V, ext.mu, part);
   return hipGetLastError();
 }
 

@@ -177,8 +177,11 @@ struct WCoef {
   T d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;   // d^2_{m'm}(beta), m' >= |m|
 };
 
-template <typename T>
-QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angles<T> ang, WCoef<T>& W) {
+// kExt: the equation of motion carries the psi-independent term (V(x) + mu) psi_m
+// (Sec. II, "Additional terms"); ext = theta (V(x) + mu) joins the density phase.
+template <typename T, bool kExt = false>
+QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angles<T> ang, WCoef<T>& W,
+                           T ext = T(0)) {
   const T r6 = T(Consts::r6), r32 = T(Consts::r32), r38 = T(Consts::r38);
   T q[5];
 #pragma unroll
@@ -207,7 +210,8 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
   // half-angle phases: mu = exp(-i x) - 1 = -2 sin(x/2) (sin(x/2) + i cos(x/2))
   T s0, c0, s1, c1, s2, c2;
   const T h2 = T(0.5) * ang.tg25 * n;
-  sincos_t(T(0.5) * ang.tg0 * n, &s0, &c0);
+  if constexpr (kExt) sincos_t(T(0.5) * (ang.tg0 * n + ext), &s0, &c0);
+  else sincos_t(T(0.5) * ang.tg0 * n, &s0, &c0);
   sincos_t(T(0.5) * ang.tg1 * Fn, &s1, &c1);
   sincos_t(h2, &s2, &c2);
   const cx<T> mu0{T(-2) * s0 * s0, T(-2) * s0 * c0};
@@ -319,10 +323,10 @@ QLG_HD void w_apply(cx<T> (&x)[5], const WCoef<T>& W) {
   x[4] = x[4] + cfma(t5[4], W.u2, sv[4]);
 }
 
-template <typename T>
-QLG_HD void potential(cx<T> (&a)[5], cx<T> (&b)[5], const Angles<T> ang) {
+template <typename T, bool kExt = false>
+QLG_HD void potential(cx<T> (&a)[5], cx<T> (&b)[5], const Angles<T> ang, T ext = T(0)) {
   WCoef<T> W;
-  w_coefficients(a, b, ang, W);
+  w_coefficients<T, kExt>(a, b, ang, W, ext);
   w_apply(a, W);
   w_apply(b, W);
 }

@@ -26,7 +26,7 @@ RECORD_DOUBLES = 16   # QLG_RECORD_DOUBLES
 # every symbol declared in include/qlg.h
 EXPORTED = [
     "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
-    "qlg_get_qubits", "qlg_fields", "qlg_vorticity", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
+    "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
     "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_get_psi": (i32, [vp, vp]),
         "qlg_set_qubits": (i32, [vp, vp]),
         "qlg_get_qubits": (i32, [vp, vp]),
+        "qlg_set_potential": (i32, [vp, vp, dbl]),
         "qlg_fields": (i32, [vp, vp, vp, vp, vp]),
         "qlg_vorticity": (i32, [vp, i32, vp, vp]),
         "qlg_step": (i32, [vp, i64]),
@@ -175,6 +176,7 @@ class Lattice:
         sb, cb = query_sizes(self.params)
         self.state_buf = _device_bytes(sb, self.device)
         self.scratch_buf = _device_bytes(cb, self.device)
+        self._pot = None   # device copy of the external potential while one is set
         ctx = ctypes.c_void_p()
         st = lib().qlg_init(ctypes.byref(self.params), self.state_buf.data_ptr(), sb,
                             self.scratch_buf.data_ptr(), cb, ctypes.c_void_p(self.stream.cuda_stream),
@@ -242,6 +244,27 @@ class Lattice:
         flat = torch.empty(10 * self.sites, dtype=self.torch_dtype, device=self.device)
         self._check(lib().qlg_get_qubits(self.ctx, flat.data_ptr()), "qlg_get_qubits")
         return self._unflat(flat, 10)
+
+    def set_potential(self, V=None, mu: float = 0.0):
+        """External potential V(x) (per instance an array of the lattice's spatial shape, or None)
+        and chemical potential mu (Sec. II "Additional terms"); set_potential() removes both.
+        The device copy of V is kept by this object for as long as the library uses it."""
+        if V is None:
+            self._pot = None
+        else:
+            fields = V if isinstance(V, (list, tuple)) else [V]
+            if len(fields) != self.nbatch:
+                raise ValueError("need one potential per instance (%d)" % self.nbatch)
+            parts = []
+            for i, f in enumerate(fields):
+                t = torch.as_tensor(f).to(device=self.device, dtype=torch.float64)
+                if t.numel() != self.nx[i] * self.ny[i]:
+                    raise ValueError("potential %d has %d values, expected %d" %
+                                     (i, t.numel(), self.nx[i] * self.ny[i]))
+                parts.append(t.reshape(-1))
+            self._pot = torch.cat(parts).contiguous()
+        self._check(lib().qlg_set_potential(self.ctx, self._pot.data_ptr() if self._pot is not None else None,
+                                            float(mu)), "qlg_set_potential")
 
     def _unflat_scalar(self, flat: torch.Tensor) -> List[torch.Tensor]:
         out, o = [], 0
