@@ -14,7 +14,7 @@ the paper (Taylor, Smith, Yepez, arXiv:1907.12834):
 * collide C, stream S, I'_q = S_q C S_q^T C, the plain split
   psi(t+tau) = I'_1 I'_1 I'_2 I'_2 U psi(t) and the interleaved split
   I'_1 U^{1/4} I'_1 U^{1/4} I'_2 U^{1/4} I'_2 U^{1/4} (Lie product n = 4 in
-  1D, n = 8 in 2D): Sec. VII "Operator interleaving";
+  1D, n = 8 in 2D, n = 12 in 3D): Sec. VII "Operator interleaving";
 * scaling x -> a x, t -> a^2 t: Sec. VII "Scaling";
 * overlap energy E = i(<psi_t|psi_t> - <psi_t|psi_{t-1}>)/<psi_t|psi_t>: Sec. IV,
   eq. (disecrete_energy);
@@ -42,8 +42,9 @@ readings (each listed in the design doc with its evidence):
 * One step advances physical time eps^2; U^{1/(4d)} uses theta = eps^2/(4d),
   the plain split theta = eps^2.
 
-Layout: a, b are complex128 tensors of shape (5, L) or (5, Ny, Nx), component
-index 0..4 <-> m = 2, 1, 0, -1, -2; x is the last axis, y the one before.
+Layout: a, b are complex128 tensors of shape (5, L), (5, Ny, Nx) or (5, Nz, Ny, Nx),
+component index 0..4 <-> m = 2, 1, 0, -1, -2; x is the last axis, y the one before,
+z the one before that.
 """
 from __future__ import annotations
 
@@ -111,7 +112,8 @@ def collide(a: torch.Tensor, b: torch.Tensor) -> Tuple[torch.Tensor, torch.Tenso
 
 
 def _dim(x: torch.Tensor, axis: str) -> int:
-    return x.dim() - 1 if axis == "x" else x.dim() - 2
+    """Tensor dimension of a lattice axis: x is the last, y the one before, z the one before that."""
+    return x.dim() - 1 - "xyz".index(axis)
 
 
 def stream(x: torch.Tensor, axis: str, transpose: bool) -> torch.Tensor:
@@ -208,9 +210,10 @@ def kinetic_sequence(ndim: int):
 
     1D: I'_2 I'_2 then I'_1 I'_1, i.e. (x,b), (x,b), (x,a), (x,a).
     2D: the same four for y, then the same four for x (n = 8 Lie product).
+    3D: z, then y, then x (n = 12), the same reading extended to the third axis.
     """
     one = [("b",), ("b",), ("a",), ("a",)]
-    axes = ["x"] if ndim == 1 else ["y", "x"]
+    axes = ["x", "y", "z"][:ndim][::-1]
     return [(ax, q[0]) for ax in axes for q in one]
 
 
@@ -268,7 +271,7 @@ def energy(psi: torch.Tensor, eps: float, g, V=None, mu: float = 0.0) -> torch.T
     g0, g1, g2 = g
     d = psi.dim() - 1
     kin = torch.zeros((), dtype=RDT)
-    for ax in (["x"] if d == 1 else ["y", "x"]):
+    for ax in ["x", "y", "z"][:d]:
         diff = torch.roll(psi, shifts=-1, dims=_dim(psi, ax)) - psi
         kin = kin + (diff.abs() ** 2).sum() / (eps * eps)
     n, F, v = invariants(psi)

@@ -127,8 +127,9 @@ def _kin_matrix(kappa, q):
 
 
 def _step_symbol(kappas, ndim):
+    """Free-step symbol for wave numbers kappas = (..., k_y, k_x); axes in time order z, y, x."""
     M = np.eye(2, dtype=complex)
-    axes = [("x", kappas[-1])] if ndim == 1 else [("y", kappas[0]), ("x", kappas[1])]
+    axes = list(zip("zyx"[3 - ndim:], kappas[-ndim:]))
     for _, kap in axes:
         for q in ("b", "b", "a", "a"):
             M = _kin_matrix(kap, q) @ M
@@ -168,6 +169,52 @@ def test_free_limit_fft_2d():
     ra, rb = np.fft.ifft2(ra), np.fft.ifft2(rb)
     err = max(np.abs(A.numpy() - ra).max(), np.abs(B.numpy() - rb).max())
     assert err < 1e-12
+
+
+def test_free_limit_fft_3d():
+    nz, ny, nx, nsteps = 4, 5, 6, 6
+    a, b = qi.random_qubits((nz, ny, nx), seed=14)
+    A, B = O.run(t(a), t(b), nsteps, 0.1, (0.0, 0.0, 0.0), 3)
+    ah, bh = np.fft.fftn(a, axes=(1, 2, 3)), np.fft.fftn(b, axes=(1, 2, 3))
+    ks = [2 * np.pi * np.fft.fftfreq(n) for n in (nz, ny, nx)]
+    ra, rb = np.empty_like(ah), np.empty_like(bh)
+    for iz, vz in enumerate(ks[0]):
+        for iy, vy in enumerate(ks[1]):
+            for ix, vx in enumerate(ks[2]):
+                M = np.linalg.matrix_power(_step_symbol([vz, vy, vx], 3), nsteps)
+                v = M @ np.stack([ah[:, iz, iy, ix], bh[:, iz, iy, ix]])
+                ra[:, iz, iy, ix], rb[:, iz, iy, ix] = v[0], v[1]
+    ra, rb = np.fft.ifftn(ra, axes=(1, 2, 3)), np.fft.ifftn(rb, axes=(1, 2, 3))
+    err = max(np.abs(A.numpy() - ra).max(), np.abs(B.numpy() - rb).max())
+    assert err < 1e-12
+
+
+def test_free_3d_reduces_to_2d_and_1d():
+    """On a field uniform along an axis, S along it is the identity, so each I' of that axis is
+    C^2 = SWAP and its four I' multiply to 1: a free (g = 0) z-uniform 3D field evolves exactly as
+    the 2D field, and an (x, y)-uniform one as the 1D field along z."""
+    nsteps, eps = 7, 0.2
+    a, b = qi.random_qubits((6, 9), seed=15)
+    A2, B2 = O.run(t(a), t(b), nsteps, eps, (0.0, 0.0, 0.0), 2)
+    A3, B3 = O.run(t(np.repeat(a[:, None], 3, axis=1)), t(np.repeat(b[:, None], 3, axis=1)), nsteps, eps,
+                   (0.0, 0.0, 0.0), 3)
+    for k in range(3):
+        assert torch.allclose(A3[:, k], A2, atol=1e-13) and torch.allclose(B3[:, k], B2, atol=1e-13)
+    a1, b1 = qi.random_qubits((11,), seed=16)
+    A1, B1 = O.run(t(a1), t(b1), nsteps, eps, (0.0, 0.0, 0.0), 1)
+    A3, B3 = O.run(t(np.tile(a1[:, :, None, None], (1, 1, 2, 3))), t(np.tile(b1[:, :, None, None], (1, 1, 2, 3))),
+                   nsteps, eps, (0.0, 0.0, 0.0), 3)
+    assert torch.allclose(A3, A1[:, :, None, None].expand_as(A3), atol=1e-13)
+    assert torch.allclose(B3, B1[:, :, None, None].expand_as(B3), atol=1e-13)
+
+
+def test_uniform_tf_state_3d_pure_phase():
+    """P4 in 3D: a uniform real Table I state acquires exactly e^{-i E eps^2} per step."""
+    E, eps, nsteps = 2.0, 0.1, 30
+    c = qi.table1_coeffs(6, E, *TABLE_G).real
+    psi = np.tile(c[:, None, None, None], (1, 3, 2, 4)).astype(complex)
+    A, B = O.run_psi(psi, nsteps, eps, TABLE_G)
+    assert np.abs((A + B).numpy() - psi * np.exp(-1j * E * eps ** 2 * nsteps)).max() < 1e-12
 
 
 def test_bosonic_dispersion_sign():
@@ -296,7 +343,7 @@ class Dense:
         """Permutation: q(r) <- q(r - e) (S), or q(r) <- q(r + e) (S^T)."""
         M = np.eye(self.dim, dtype=complex)
         coords = list(np.ndindex(*self.shape))
-        ax = len(self.shape) - 1 if axis == "x" else len(self.shape) - 2
+        ax = len(self.shape) - 1 - {"x": 0, "y": 1, "z": 2}[axis]
         qi_ = 0 if q == "a" else 1
         for m in range(5):
             for s, r in enumerate(coords):
@@ -330,7 +377,8 @@ class Dense:
 
 @pytest.mark.parametrize("shape,split", [((8,), "interleaved"), ((5,), "interleaved"),
                                          ((8,), "plain"), ((2, 4), "interleaved"),
-                                         ((2, 2), "interleaved")])
+                                         ((2, 2), "interleaved"), ((2, 2, 2), "interleaved"),
+                                         ((2, 1, 3), "plain"), ((1, 3, 2), "interleaved")])
 def test_dense_brute_force(shape, split):
     g, eps, nsteps = (0.8, -0.6, 1.1), 0.7, 3
     a, b = qi.random_qubits(shape, seed=5, scale=0.6)
@@ -338,7 +386,7 @@ def test_dense_brute_force(shape, split):
     z = np.concatenate([a.reshape(-1), b.reshape(-1)])
     C = D.collide()
     ndim = len(shape)
-    seq = [("x", q) for q in "bbaa"] if ndim == 1 else [(ax, q) for ax in "yx" for q in "bbaa"]
+    seq = [(ax, q) for ax in "zyx"[3 - ndim:] for q in "bbaa"]
     Ip = {}
     for ax, q in set(seq):
         Ip[(ax, q)] = D.shift(ax, q, False) @ C @ D.shift(ax, q, True) @ C
@@ -638,6 +686,26 @@ def test_energy_matches_numpy_definition():
     want = eps * (kin + pot)
     got = float(O.energy(t(psi), eps, g))
     assert abs(got - want) < 1e-12 * abs(want)
+
+
+def test_energy_3d_plane_waves():
+    """Free energy of a plane wave along each axis of a 3D lattice: eps^3 N |c|^2 4 sin^2(k/2) / eps^2
+    (forward differences), and a z-uniform field has eps * nz times its 2D energy."""
+    nz, ny, nx, eps = 4, 6, 5, 0.3
+    c = qi.random_field((1,), seed=3, scale=0.7)[:, 0]
+    N = nz * ny * nx
+    for axis, n_ax in ((1, nz), (2, ny), (3, nx)):
+        k = 2 * np.pi * 1 / n_ax
+        shape = [1, 1, 1]
+        shape[axis - 1] = n_ax
+        ph = np.exp(1j * k * np.arange(n_ax)).reshape(shape)
+        psi = c[:, None, None, None] * np.broadcast_to(ph, (nz, ny, nx))[None]
+        want = eps ** 3 * N * np.vdot(c, c).real * 4 * math.sin(k / 2) ** 2 / eps ** 2
+        assert abs(float(O.energy(t(psi), eps, (0.0, 0.0, 0.0))) - want) < 1e-12 * want
+    p2 = qi.random_field((ny, nx), seed=4, scale=0.5)
+    e2 = float(O.energy(t(p2), eps, TABLE_G))
+    e3 = float(O.energy(t(np.repeat(p2[:, None], nz, axis=1)), eps, TABLE_G))
+    assert abs(e3 - eps * nz * e2) < 1e-12 * abs(e3)
 
 
 def test_energy_gradient_is_hloc():
