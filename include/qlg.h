@@ -10,7 +10,8 @@
  *     (Sec. III "Local quantum entanglement": 10 qubits per site);
  *   - step: I'_q = S_q C S_q^T C, plain split psi(t+tau) = I'_1 I'_1 I'_2 I'_2 U psi(t)
  *     and the interleaved split I'_1 U^{1/4} I'_1 U^{1/4} I'_2 U^{1/4} I'_2 U^{1/4}
- *     (Lie product n = 4 in 1D, n = 8 in 2D) of Sec. VII "Operator interleaving";
+ *     (Lie product n = 4 in 1D, n = 8 in 2D, n = 12 in 3D, the axes in the order
+ *     z, y, x) of Sec. VII "Operator interleaving";
  *   - lattice scaling x -> a x, t -> a^2 t (Sec. VII "Scaling"): one step
  *     advances physical time eps^2 on a lattice of spacing eps.
  * The definitions of C, S and U that the paper defers to its references are
@@ -36,9 +37,9 @@
  * Field layout (the canonical layout for psi_dev / qubits_dev arguments):
  *   complex numbers are interleaved (re, im), float for QLG_C64 and double for
  *   QLG_C128.  Instances follow one another; within instance i,
- *     psi[m][y][x]        m index 0..4 <-> m_f = 2, 1, 0, -1, -2, x fastest;
- *     qubits[q][m][y][x]  q = 0 for a (the paper's qubit 1), 1 for b (qubit 2).
- *   ny == 1 for 1D instances.
+ *     psi[m][z][y][x]        m index 0..4 <-> m_f = 2, 1, 0, -1, -2, x fastest;
+ *     qubits[q][m][z][y][x]  q = 0 for a (the paper's qubit 1), 1 for b (qubit 2).
+ *   nz == 1 for 1D and 2D instances, ny == 1 for 1D instances.
  */
 #ifndef QLG_H
 #define QLG_H
@@ -53,7 +54,7 @@ extern "C" {
 typedef enum {
   QLG_OK = 0,
   QLG_ERR_ARG = 1,      /* NULL pointer, bad enum, non-finite coupling, buffer too small */
-  QLG_ERR_SHAPE = 2,    /* ndim not 1 or 2, extent < 1, lattice too large */
+  QLG_ERR_SHAPE = 2,    /* ndim not 1..3, extent < 1, lattice too large, call not for this ndim */
   QLG_ERR_DTYPE = 3,    /* dtype not QLG_C64 / QLG_C128 */
   QLG_ERR_DEVICE = 4,   /* a HIP call failed; message in qlg_last_error */
   QLG_ERR_OOM = 5,      /* the library's own small metadata allocation failed */
@@ -69,12 +70,13 @@ typedef enum {
 } qlg_split;
 
 typedef struct qlg_params {
-  int32_t ndim;          /* 1 or 2 */
+  int32_t ndim;          /* 1, 2 or 3 */
   int32_t dtype;         /* qlg_dtype */
   int32_t split;         /* qlg_split */
   int32_t nbatch;        /* >= 1 independent lattices; they may differ in size */
   const int64_t* nx;     /* [nbatch] x extents (host memory, copied at qlg_init) */
   const int64_t* ny;     /* [nbatch] y extents, or NULL for ndim == 1 */
+  const int64_t* nz;     /* [nbatch] z extents, or NULL for ndim < 3 */
   double g0, g1, g2;     /* couplings of eq. (eomspin2), shared by all instances */
   double eps;            /* lattice spacing: one step = physical time eps^2; norms use eps^ndim */
 } qlg_params;
@@ -98,12 +100,15 @@ typedef struct qlg_obs {
 /* Launch plan of the fused step; chosen by qlg_autotune or set by the caller. */
 typedef struct qlg_tuning {
   int32_t steps_per_pass; /* 1D: steps fused per HBM pass (1..7; 4 S halo sites per side
-                             of each 64-site tile); 2D: must be 1 */
-  int32_t tile_rows;      /* 2D: rows per streaming tile (8..256); 1D: ignored */
+                             of each 64-site tile); 2D and 3D: must be 1 */
+  int32_t tile_rows;      /* 2D and 3D: rows per streaming tile (8..256); 1D: ignored.
+                             A 3D step is two HBM passes: the four z substeps streaming
+                             along z, then the y and x substeps streaming along y, both
+                             in bands of tile_rows */
   int32_t use_graph;      /* 1: replay qlg_step's launches from a captured hipGraph */
   int32_t pair_waves;     /* 1D: 1 = the two qubit amplitudes of a tile on two wavefronts
                              (twice the SIMDs for lattices too small to fill the chip);
-                             2D: must be 0 */
+                             2D and 3D: must be 0 */
 } qlg_tuning;
 
 typedef struct qlg_ctx qlg_ctx;
@@ -217,6 +222,8 @@ qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_h
 
 /* ---------------------------------------------------------------------------
  * Adjoint (reverse-mode derivative of a final-state objective).
+ *
+ * 1D and 2D lattices only (QLG_ERR_SHAPE for ndim == 3).
  *
  * Cotangents use the convention lambda = dL/dRe z + i dL/dIm z for every
  * complex amplitude z (so d|z|^2 has cotangent 2 z).  Adjoint vectors are

@@ -33,6 +33,7 @@ struct Sizes {
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
 qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
+  if (p && p->ndim == 3) return QLG_ERR_SHAPE;   // the adjoint covers 1D and 2D lattices
   if (nsteps < 0 || K < 1) return QLG_ERR_ARG;
   size_t state_bytes = 0, scratch_bytes = 0;
   qlg_status st = qlg_query_sizes(p, &state_bytes, &scratch_bytes);
@@ -78,6 +79,8 @@ qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t K, void* ckp
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
   if (qlg::ctx_view(ctx).has_ext)
     return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
+  if (qlg::ctx_view(ctx).p->ndim == 3)
+    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   qlg::CtxView v = qlg::ctx_view(ctx);
   Sizes s;
   qlg_status st = sizes_for(v.p, nsteps, K, &s);
@@ -102,6 +105,8 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
   if (qlg::ctx_view(ctx).has_ext)
     return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
+  if (qlg::ctx_view(ctx).p->ndim == 3)
+    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   if (!lambda_dev || !value_host) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or value pointer is NULL");
   if (kind != 0 && kind != 1) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "kind must be 0 (energy) or 1 (fidelity)");
   if (kind == 1 && !target_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "fidelity needs a target");
@@ -146,6 +151,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
   if (qlg::ctx_view(ctx).has_ext)
     return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
+  if (qlg::ctx_view(ctx).p->ndim == 3)
+    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   const qlg::CtxView v = qlg::ctx_view(ctx);
   const qlg_params& p = *v.p;
   Sizes s;

@@ -36,6 +36,7 @@ struct Layout {
   int64_t psi_elems = 0;
   int32_t nchunks = 0;
   int32_t max_tiles = 0;          // tiles at the densest plan (used to size scratch)
+  int32_t max_tiles_z = 0;        // 3D z pass: tiles at the densest plan
 };
 
 int tiles_1d(int64_t nx, int steps) {
@@ -48,22 +49,34 @@ void tiles_2d(int64_t nx, int64_t ny, int rows, int* ntx, int* nty) {
   *nty = (int)((ny + rows - 1) / rows);
 }
 
+// 3D z pass: 64-column tiles (no x halo), bands of `rows` along z
+void tiles_z(int64_t nx, int64_t nz, int rows, int* ntx, int* ntz) {
+  *ntx = (int)((nx + qlg::kLanes - 1) / qlg::kLanes);
+  *ntz = (int)((nz + rows - 1) / rows);
+}
+
 qlg_status validate(const qlg_params* p, std::string* msg) {
   if (!p) { *msg = "params is NULL"; return QLG_ERR_ARG; }
-  if (p->ndim != 1 && p->ndim != 2) { *msg = "ndim must be 1 or 2"; return QLG_ERR_SHAPE; }
+  if (p->ndim < 1 || p->ndim > 3) { *msg = "ndim must be 1, 2 or 3"; return QLG_ERR_SHAPE; }
   if (p->dtype != QLG_C64 && p->dtype != QLG_C128) { *msg = "dtype must be QLG_C64 or QLG_C128"; return QLG_ERR_DTYPE; }
   if (p->split != QLG_SPLIT_INTERLEAVED && p->split != QLG_SPLIT_PLAIN) { *msg = "unknown split"; return QLG_ERR_ARG; }
   if (p->nbatch < 1) { *msg = "nbatch must be >= 1"; return QLG_ERR_SHAPE; }
   if (!p->nx) { *msg = "nx is NULL"; return QLG_ERR_ARG; }
-  if (p->ndim == 2 && !p->ny) { *msg = "ny is NULL for a 2D lattice"; return QLG_ERR_ARG; }
+  if (p->ndim >= 2 && !p->ny) { *msg = "ny is NULL for a 2D or 3D lattice"; return QLG_ERR_ARG; }
+  if (p->ndim == 3 && !p->nz) { *msg = "nz is NULL for a 3D lattice"; return QLG_ERR_ARG; }
   if (!std::isfinite(p->g0) || !std::isfinite(p->g1) || !std::isfinite(p->g2)) { *msg = "couplings must be finite"; return QLG_ERR_ARG; }
   if (!std::isfinite(p->eps) || !(p->eps > 0)) { *msg = "eps must be finite and > 0"; return QLG_ERR_ARG; }
   for (int i = 0; i < p->nbatch; ++i) {
     const int64_t nx = p->nx[i];
-    const int64_t ny = p->ndim == 2 ? p->ny[i] : (p->ny ? p->ny[i] : 1);
-    if (nx < 1 || ny < 1 || nx > kMaxExtent || ny > kMaxExtent) { *msg = "extents must be in [1, 2^30]"; return QLG_ERR_SHAPE; }
+    const int64_t ny = p->ndim >= 2 ? p->ny[i] : (p->ny ? p->ny[i] : 1);
+    const int64_t nz = p->ndim == 3 ? p->nz[i] : (p->nz ? p->nz[i] : 1);
+    if (nx < 1 || ny < 1 || nz < 1 || nx > kMaxExtent || ny > kMaxExtent || nz > kMaxExtent) {
+      *msg = "extents must be in [1, 2^30]";
+      return QLG_ERR_SHAPE;
+    }
     if (p->ndim == 1 && ny != 1) { *msg = "ny must be 1 (or NULL) for ndim == 1"; return QLG_ERR_SHAPE; }
-    if (nx * ny > kMaxSites) { *msg = "an instance exceeds 2^31-1 sites"; return QLG_ERR_SHAPE; }
+    if (p->ndim < 3 && nz != 1) { *msg = "nz must be 1 (or NULL) for ndim < 3"; return QLG_ERR_SHAPE; }
+    if (nx * ny > kMaxSites || nx * ny * nz > kMaxSites) { *msg = "an instance exceeds 2^31-1 sites"; return QLG_ERR_SHAPE; }
   }
   return QLG_OK;
 }
@@ -76,8 +89,9 @@ Layout make_layout(const qlg_params* p) {
   for (int i = 0; i < p->nbatch; ++i) {
     InstDesc d{};
     d.nx = (int32_t)p->nx[i];
-    d.ny = p->ndim == 2 ? (int32_t)p->ny[i] : 1;
-    d.sites = d.nx * d.ny;
+    d.ny = p->ndim >= 2 ? (int32_t)p->ny[i] : 1;
+    d.nz = p->ndim == 3 ? (int32_t)p->nz[i] : 1;
+    d.sites = d.nx * d.ny * d.nz;
     d.stride = round_up(d.sites, 64);
     d.off = off;
     d.psi_off = poff;
@@ -88,7 +102,8 @@ Layout make_layout(const qlg_params* p) {
     poff += 5 * (int64_t)d.sites;
     chunk += d.nchunks;
     if (p->ndim == 1) maxt += tiles_1d(d.nx, kMaxSteps1D);
-    else { int a, b; tiles_2d(d.nx, d.ny, kMinTileRows, &a, &b); maxt += a * b; }
+    else { int a, b; tiles_2d(d.nx, d.ny, kMinTileRows, &a, &b); maxt += a * b * d.nz; }
+    if (p->ndim == 3) { int a, b; tiles_z(d.nx, d.nz, kMinTileRows, &a, &b); L.max_tiles_z += a * b * d.ny; }
     L.inst.push_back(d);
   }
   L.elems_per_copy = off;
@@ -122,7 +137,7 @@ std::map<std::string, qlg_tuning> g_tune_cache;
 
 struct qlg_ctx {
   qlg_params p{};
-  std::vector<int64_t> nx, ny;
+  std::vector<int64_t> nx, ny, nz;
   Layout L;
   ScratchLayout S{};
   char* state = nullptr;
@@ -136,7 +151,8 @@ struct qlg_ctx {
   InstDesc* d_inst = nullptr;
   int32_t* d_tile2inst = nullptr;
   int32_t* d_chunk2inst = nullptr;
-  int32_t ntiles = 0;
+  int32_t* d_tile2inst_z = nullptr;   // 3D z pass
+  int32_t ntiles = 0, ntiles_z = 0;
   qlg_tuning tuning{1, 32, 0, 0};
   qlg::ExtPot ext;               // external potential (caller's device array) and mu
   bool tuned = false;
@@ -159,7 +175,9 @@ struct qlg_ctx {
     g.inst = d_inst;
     g.tile2inst = d_tile2inst;
     g.chunk2inst = d_chunk2inst;
+    g.tile2inst_z = d_tile2inst_z;
     g.ntiles = ntiles;
+    g.ntiles_z = ntiles_z;
     g.nchunks = L.nchunks;
     g.nbatch = p.nbatch;
     return g;
@@ -190,7 +208,7 @@ void drop_graphs(qlg_ctx* c) {
 
 // Rebuild the wave-tile tables for the current plan.
 qlg_status build_tiles(qlg_ctx* c) {
-  std::vector<int32_t> t2i;
+  std::vector<int32_t> t2i, t2i_z;
   for (int i = 0; i < c->p.nbatch; ++i) {
     InstDesc& d = c->L.inst[i];
     d.tile_begin = (int32_t)t2i.size();
@@ -200,10 +218,17 @@ qlg_status build_tiles(qlg_ctx* c) {
     } else {
       tiles_2d(d.nx, d.ny, c->tuning.tile_rows, &d.ntx, &d.nty);
     }
-    for (int k = 0; k < d.ntx * d.nty; ++k) t2i.push_back(i);
+    for (int64_t k = 0; k < (int64_t)d.ntx * d.nty * d.nz; ++k) t2i.push_back(i);
+    if (c->p.ndim == 3) {
+      d.tile_begin_z = (int32_t)t2i_z.size();
+      tiles_z(d.nx, d.nz, c->tuning.tile_rows, &d.ntx_z, &d.ntz);
+      for (int64_t k = 0; k < (int64_t)d.ntx_z * d.ntz * d.ny; ++k) t2i_z.push_back(i);
+    }
   }
-  if ((int32_t)t2i.size() > c->L.max_tiles) return fail(c, QLG_ERR_ARG, "tile table overflow");
+  if ((int32_t)t2i.size() > c->L.max_tiles || (int32_t)t2i_z.size() > c->L.max_tiles_z)
+    return fail(c, QLG_ERR_ARG, "tile table overflow");
   c->ntiles = (int32_t)t2i.size();
+  c->ntiles_z = (int32_t)t2i_z.size();
   c->has_overlap = false;   // overlap partials refer to the previous tile layout
   qlg_status s = hip_check(c, hipMemcpyAsync(c->d_inst, c->L.inst.data(), sizeof(InstDesc) * c->L.inst.size(),
                                              hipMemcpyHostToDevice, c->stream), "copy instance table");
@@ -211,6 +236,11 @@ qlg_status build_tiles(qlg_ctx* c) {
   s = hip_check(c, hipMemcpyAsync(c->d_tile2inst, t2i.data(), sizeof(int32_t) * t2i.size(),
                                   hipMemcpyHostToDevice, c->stream), "copy tile table");
   if (s) return s;
+  if (!t2i_z.empty()) {
+    s = hip_check(c, hipMemcpyAsync(c->d_tile2inst_z, t2i_z.data(), sizeof(int32_t) * t2i_z.size(),
+                                    hipMemcpyHostToDevice, c->stream), "copy z tile table");
+    if (s) return s;
+  }
   // the host vectors must outlive the async copies
   s = hip_check(c, hipStreamSynchronize(c->stream), "sync after table upload");
   drop_graphs(c);
@@ -227,19 +257,35 @@ double angle_scale(const qlg_ctx* c) {   // interleaved theta = eps^2 / (4 d)
   return c->p.eps * c->p.eps / (4.0 * c->p.ndim);
 }
 
-hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, const void* in, void* out,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+// One pass of the fused step from `in` to `out` (1D: `steps` steps; 2D: one step).
+// 3D: one step as two passes, the z pass from `in` to `out` and the y-x pass from `out`
+// back to `in`, so the state stays in `in`; with keep_state (timing runs) both passes
+// read `in` and write `out`, leaving `in` unchanged.  ev0 / ev1 are stamped at the
+// start of the first and the end of the last kernel.
+hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, void* in, void* out, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr, bool keep_state = false) {
   const double th = angle_scale(c);
   const LaunchGeom g = c->geom();
   double* ov = c->sc(c->S.ov_part);
   const bool plain = c->p.split == QLG_SPLIT_PLAIN;
+  const double tg0 = th * c->p.g0, tg1 = th * c->p.g1, tg25 = th * c->p.g2 / 5.0;
   qlg::ExtPot ext = c->ext;
   ext.theta = th;
+  const int rows = c->tuning.tile_rows;
   if (c->p.ndim == 1)
-    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.pair_waves != 0, plain, overlap, in, out, g,
-                              th * c->p.g0, th * c->p.g1, th * c->p.g2 / 5.0, ext, ov, c->stream, ev0, ev1);
-  return qlg::launch_step2d(c->p.dtype, plain, overlap, c->tuning.tile_rows, in, out, g, th * c->p.g0,
-                            th * c->p.g1, th * c->p.g2 / 5.0, ext, ov, c->stream, ev0, ev1);
+    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.pair_waves != 0, plain, overlap, in, out, g, tg0, tg1,
+                              tg25, ext, ov, c->stream, ev0, ev1);
+  if (c->p.ndim == 2)
+    return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, true, 8.0, in, out, in, g, tg0, tg1, tg25,
+                              ext, ov, c->stream, ev0, ev1);
+  hipError_t e = qlg::launch_step2d(c->p.dtype, plain, false, rows, true, true, 12.0, in, out, in, g, tg0, tg1,
+                                    tg25, ext, ov, c->stream, ev0, nullptr);
+  if (e != hipSuccess) return e;
+  if (keep_state)
+    return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, false, 12.0, in, out, in, g, tg0, tg1,
+                              tg25, ext, ov, c->stream, nullptr, ev1);
+  return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, false, 12.0, out, in, in, g, tg0, tg1, tg25,
+                            ext, ov, c->stream, nullptr, ev1);
 }
 
 // Enqueue nsteps as passes of steps_per_pass (1D) or single steps (2D), ping-ponging
@@ -258,7 +304,7 @@ qlg_status enqueue_steps(qlg_ctx* c, int64_t nsteps, int* cur, bool timed) {
     }
     hipError_t e = launch_pass(c, s, last, c->copy(*cur), c->copy(1 - *cur), e0, e1);
     if (e != hipSuccess) return hip_check(c, e, "step kernel launch");
-    *cur = 1 - *cur;
+    if (c->p.ndim < 3) *cur = 1 - *cur;   // a 3D step returns to its own copy
     left -= s;
     ++launch;
   }
@@ -284,7 +330,7 @@ std::string tune_key(const qlg_ctx* c) {
 
 extern "C" {
 
-int32_t qlg_version(void) { return 10000; }
+int32_t qlg_version(void) { return 10100; }
 
 const char* qlg_status_string(qlg_status s) {
   switch (s) {
@@ -331,10 +377,13 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
   if (!c) return QLG_ERR_OOM;
   c->p = *p;
   c->nx.assign(p->nx, p->nx + p->nbatch);
-  if (p->ndim == 2) c->ny.assign(p->ny, p->ny + p->nbatch);
+  if (p->ndim >= 2) c->ny.assign(p->ny, p->ny + p->nbatch);
   else c->ny.assign(p->nbatch, 1);
+  if (p->ndim == 3) c->nz.assign(p->nz, p->nz + p->nbatch);
+  else c->nz.assign(p->nbatch, 1);
   c->p.nx = c->nx.data();
   c->p.ny = c->ny.data();
+  c->p.nz = c->nz.data();
   c->L = make_layout(&c->p);
   c->S = scratch_layout(c->L, p->nbatch);
   c->state = (char*)state_dev;
@@ -343,12 +392,14 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
   c->scratch_bytes = scratch_bytes;
   c->stream = (hipStream_t)hip_stream;
   c->elem_bytes = p->dtype == QLG_C64 ? 8 : 16;
-  if (p->ndim == 2) c->tuning = qlg_tuning{1, 32, 0, 0};
+  if (p->ndim >= 2) c->tuning = qlg_tuning{1, 32, 0, 0};
   else c->tuning = qlg_tuning{1, 0, 0, 0};
 
   hipError_t e = hipMalloc(&c->d_inst, sizeof(InstDesc) * p->nbatch);
   if (e == hipSuccess) e = hipMalloc(&c->d_tile2inst, sizeof(int32_t) * std::max(c->L.max_tiles, 1));
   if (e == hipSuccess) e = hipMalloc(&c->d_chunk2inst, sizeof(int32_t) * std::max(c->L.nchunks, 1));
+  if (e == hipSuccess && p->ndim == 3)
+    e = hipMalloc(&c->d_tile2inst_z, sizeof(int32_t) * std::max(c->L.max_tiles_z, 1));
   if (e != hipSuccess) {
     qlg_destroy(c);
     return e == hipErrorOutOfMemory ? QLG_ERR_OOM : QLG_ERR_DEVICE;
@@ -382,6 +433,7 @@ void qlg_destroy(qlg_ctx* c) {
   if (c->d_inst) (void)hipFree(c->d_inst);
   if (c->d_tile2inst) (void)hipFree(c->d_tile2inst);
   if (c->d_chunk2inst) (void)hipFree(c->d_chunk2inst);
+  if (c->d_tile2inst_z) (void)hipFree(c->d_tile2inst_z);
   delete c;
 }
 
@@ -527,7 +579,7 @@ qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
     }
     s = hip_check(c, hipGraphLaunch(it->second, c->stream), "graph launch");
     if (s) return s;
-    if (launches % 2) c->cur = 1 - c->cur;
+    if (launches % 2 && c->p.ndim < 3) c->cur = 1 - c->cur;
   } else {
     int cur = c->cur;
     s = enqueue_steps(c, nsteps, &cur, false);
@@ -618,8 +670,8 @@ qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
     if (n.pair_waves != 0 && n.pair_waves != 1) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 or 1");
     n.tile_rows = 0;
   } else {
-    if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D");
-    if (n.pair_waves != 0) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 in 2D");
+    if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D and 3D");
+    if (n.pair_waves != 0) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 in 2D and 3D");
     if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return fail(c, QLG_ERR_ARG, "tile_rows must be 8..256");
   }
   n.use_graph = n.use_graph ? 1 : 0;
@@ -653,7 +705,7 @@ qlg_status qlg_autotune(qlg_ctx* c) {
     const int64_t nsimd = 4 * (int64_t)cus;
     auto ntiles = [&](int r) {
       int64_t t = 0;
-      for (const auto& d : c->L.inst) { int a, b; tiles_2d(d.nx, d.ny, r, &a, &b); t += (int64_t)a * b; }
+      for (const auto& d : c->L.inst) { int a, b; tiles_2d(d.nx, d.ny, r, &a, &b); t += (int64_t)a * b * d.nz; }
       return t;
     };
     for (int k = 1; k <= 4 && nsimd > 0; ++k) {
@@ -674,13 +726,13 @@ qlg_status qlg_autotune(qlg_ctx* c) {
     const int S = c->p.ndim == 1 ? t.steps_per_pass : 1;
     // passes read the current copy and write the other one without swapping: the state is
     // unchanged.  One warm-up pass, then the best of two timed batches.
-    hipError_t e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur));
+    hipError_t e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur), nullptr, nullptr, true);
     const int reps = 8;
     double per_step = 1e300;
     for (int round = 0; round < 2 && e == hipSuccess; ++round) {
       e = hipEventRecord(e0, c->stream);
       for (int k = 0; k < reps && e == hipSuccess; ++k)
-        e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur));
+        e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur), nullptr, nullptr, true);
       if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

@@ -13,10 +13,12 @@ struct InstDesc {
   int64_t psi_off;    // first element of the instance in the canonical psi layout
   int64_t qb_off;     // first element of the instance in the canonical qubits layout
   int64_t stride;     // plane stride (>= sites, multiple of 64)
-  int32_t nx, ny;     // extents (ny = 1 in 1D)
-  int32_t sites;      // nx * ny
-  int32_t tile_begin; // first global wave tile of the fused step
-  int32_t ntx, nty;   // tiles along x and y (nty = 1 in 1D)
+  int32_t nx, ny, nz; // extents (ny = 1 in 1D, nz = 1 in 1D and 2D)
+  int32_t sites;      // nx * ny * nz
+  int32_t tile_begin; // first global wave tile of the fused step (3D: of its y-x pass)
+  int32_t ntx, nty;   // tiles along x and bands along y (nty = 1 in 1D); 3D: ntx * nty * nz tiles
+  int32_t tile_begin_z;  // 3D z pass: first tile, 64-column tiles along x, bands along z,
+  int32_t ntx_z, ntz;    // ntx_z * ntz * ny tiles
   int32_t chunk_begin;// first 256-site chunk for elementwise / reduction kernels
   int32_t nchunks;
 };
@@ -29,10 +31,11 @@ constexpr int kHalo2D = 4;       // x halo of the 2D kernel (4 I' per axis per s
 constexpr int kValid2D = kLanes - 2 * kHalo2D;
 
 struct LaunchGeom {
-  const InstDesc* inst;      // device [nbatch]
-  const int32_t* tile2inst;  // device [ntiles]
-  const int32_t* chunk2inst; // device [nchunks]
-  int32_t ntiles, nchunks, nbatch;
+  const InstDesc* inst;        // device [nbatch]
+  const int32_t* tile2inst;    // device [ntiles]
+  const int32_t* chunk2inst;   // device [nchunks]
+  const int32_t* tile2inst_z;  // device [ntiles_z], 3D z pass
+  int32_t ntiles, nchunks, nbatch, ntiles_z;
 };
 
 // The psi-independent diagonal term (V(x) + mu) psi_m of the equation of motion
@@ -53,9 +56,15 @@ struct ExtPot {
 hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
                          double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
-                         double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// 2D step, or one pass of a 3D step: zpass = the four z substeps only (rows along z,
+// 64-column tiles, the 3D z-pass tile table); otherwise the y and x substeps of each
+// z plane.  full_factor: theta of the plain split's single U over the interleaved theta
+// (4 ndim); plain_u: this pass applies that U (2D, 3D z pass).  prev (may equal out):
+// the state before the step, for the overlap partials.
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+                         double full_factor, const void* in, void* out, const void* prev, const LaunchGeom& g,
+                         double tg0, double tg1, double tg25, const ExtPot& ext, double* ovpart,
+                         hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_set_psi(int dtype, const void* psi, void* state, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_get_psi(int dtype, const void* state, void* psi, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_set_qubits(int dtype, const void* qb, void* state, const LaunchGeom& g, hipStream_t st);

@@ -105,6 +105,9 @@ struct StepArgs {
   const double* __restrict__ pot;  // V(x), canonical scalar layout (nullptr: none); kExt kernels only
   double mu;                     // chemical potential; kExt kernels only
   T th_ext;                      // theta of the (V + mu) phase: eps^2/(4d), or eps^2 for the plain split
+  const cx<T>* prev;             // 2D/3D: the state before the step (overlap); may equal out
+  int32_t zpass;                 // 3D: this launch is the z pass (four z substeps only)
+  int32_t plain_u;               // plain split: this launch applies the step's single U
   int32_t ntiles;
   int32_t steps;                 // 1D: steps fused in this pass
   int32_t tile_rows;             // 2D: rows per streaming tile
@@ -413,14 +416,25 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   const int lane = threadIdx.x & (kLanes - 1);
   cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStageSlots * kLanes) + lane;
   const InstDesc d = A.inst[A.tile2inst[w]];
-  const int t = w - d.tile_begin;
-  const int tx = t % d.ntx, ty = t / d.ntx;
-  const int nx = d.nx, ny = d.ny;
-  const int x = tx * kValid2D - kHalo2D + lane;
+  // Tile -> (x tile, band, plane).  The rows of a band stream along y (2D, and the y-x
+  // pass of a 3D step: one z plane per band) or along z (the z pass of a 3D step: one y
+  // plane per band, 64-column tiles without x halo since no x substep follows).
+  const bool zp = A.zpass != 0;
+  const int t = w - (zp ? d.tile_begin_z : d.tile_begin);
+  const int ntx = zp ? d.ntx_z : d.ntx, nband = zp ? d.ntz : d.nty;
+  const int tx = t % ntx, tb = t / ntx;
+  const int ty = tb % nband, plane = tb / nband;
+  const int nx = d.nx;
+  const int nrow = zp ? d.nz : d.ny;                                     // extent along the rows
+  const int64_t rstride = zp ? (int64_t)d.nx * d.ny : (int64_t)d.nx;     // sites between rows
+  const int64_t pbase = zp ? (int64_t)plane * d.nx : (int64_t)plane * d.nx * d.ny;
+  const int halo = zp ? 0 : kHalo2D;
+  const int x = tx * (kLanes - 2 * halo) - halo + lane;
   const int xw = (int)wrap64(x, nx);
   const int y0 = ty * A.tile_rows;
-  const bool xvalid = lane >= kHalo2D && lane < kLanes - kHalo2D && x < nx;
+  const bool xvalid = lane >= halo && lane < kLanes - halo && x < nx;
   const bool plain = A.plain != 0;
+  const bool plain_u = A.plain_u != 0;
 #pragma unroll
   for (int j = 0; j < kStageSlots; ++j) my[j * kLanes] = cx<T>{T(0), T(0)};
 
@@ -432,14 +446,14 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   constexpr bool kAhead = sizeof(T) == 4;
   // with kExt, e is the (V + mu) angle of the row's site in this lane
   auto load_row = [&](int r, cx<T>(&a)[5], cx<T>(&b)[5], T& e) {
-    const int yw = (int)wrap64(y0 - 4 + r, ny);
-    const cx<T>* src = A.in + d.off + (int64_t)yw * nx + xw;
+    const int64_t s = pbase + wrap64(y0 - 4 + r, nrow) * rstride + xw;
+    const cx<T>* src = A.in + d.off + s;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       a[m] = src[m * d.stride];
       b[m] = src[(5 + m) * d.stride];
     }
-    if constexpr (kExt) e = ext_angle(A, d, (int64_t)yw * nx + xw);
+    if constexpr (kExt) e = ext_angle(A, d, s);
   };
   // (V + mu) angles of the rows at the four y stages and of the row leaving for the
   // x half: stage j works on the row loaded j iterations ago, the x half on the row
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
     // scale; one exact multiplication by 1/256 ends each half.
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (!plain || j == 0)
+      if (!plain || (j == 0 && plain_u))
         potential<T, kExt>(a, b, plain ? A.ang_full : substep_angles(A.ang, j), j == 0 ? e0 : e1);
       y_stage_lds<T, 1>(a, b, my + j * 10 * kLanes);
     }
@@ -488,6 +502,18 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
     if (r < 8) continue;
     // x half for rows that have left the y pipeline complete (r >= 8)
     scale_by(a, b, T(1.0 / 256.0));
+    const int yo = y0 - 8 + r;           // row leaving the pipeline
+    if (zp) {                            // 3D z pass: the rows are complete
+      if (xvalid && yo < nrow) {
+        cx<T>* dst = A.out + d.off + pbase + yo * rstride + x;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          dst[m * d.stride] = a[m];
+          dst[(5 + m) * d.stride] = b[m];
+        }
+      }
+      continue;
+    }
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
       if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), e4);
@@ -499,17 +525,13 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
       iprime4_lanes<T, 0>(a, b);
     }
     scale_by(a, b, T(1.0 / 256.0));
-    const int yo = y0 - 8 + r;           // row leaving the pipeline
-    if (xvalid && yo < ny) {
-      const int64_t o = d.off + (int64_t)yo * nx + x;
+    if (xvalid && yo < nrow) {
+      const int64_t o = d.off + pbase + yo * rstride + x;
       cx<T>* dst = A.out + o;
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        dst[m * d.stride] = a[m];
-        dst[(5 + m) * d.stride] = b[m];
-      }
       if (A.overlap) {
-        const cx<T>* old = A.in + o;
+        // the state before the step at this site; in a 3D step it is the location this lane
+        // writes below (and no other lane reads or writes it), so it is read first
+        const cx<T>* old = A.prev + o;
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
           const cx<T> po = old[m * d.stride] + old[(5 + m) * d.stride];
@@ -517,6 +539,11 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
           ore += (double)c.re;
           oim += (double)c.im;
         }
+      }
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        dst[m * d.stride] = a[m];
+        dst[(5 + m) * d.stride] = b[m];
       }
     }
   }
@@ -640,7 +667,8 @@ __global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict_
     const InstDesc& d = r.d;
     double pr[5], pi[5], nq;
     load_psi_d(st, d, r.s, pr, pi, &nq);
-    const int x = r.s % d.nx, y = r.s / d.nx;
+    const int plane = d.nx * d.ny;
+    const int x = r.s % d.nx, y = (r.s / d.nx) % d.ny, z = r.s / plane;
     double q[5], n = 0.0;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
@@ -651,28 +679,20 @@ __global__ __launch_bounds__(kChunk) void k_observables(const cx<T>* __restrict_
     v[1] = n;
 #pragma unroll
     for (int m = 0; m < 5; ++m) v[2 + m] = q[m];
-    // kinetic: forward differences along x (and y), periodic
+    // kinetic: forward differences along x (and y, z), periodic
     double ek = 0.0;
-    {
+    auto add_diff = [&](int sn) {
       double nr[5], ni[5];
-      const int sx = y * d.nx + (x + 1 == d.nx ? 0 : x + 1);
-      load_psi_d<T>(st, d, sx, nr, ni, nullptr);
+      load_psi_d<T>(st, d, sn, nr, ni, nullptr);
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const double dr = nr[m] - pr[m], di = ni[m] - pi[m];
         ek += dr * dr + di * di;
       }
-    }
-    if (ndim == 2) {
-      double nr[5], ni[5];
-      const int sy = (y + 1 == d.ny ? 0 : y + 1) * d.nx + x;
-      load_psi_d<T>(st, d, sy, nr, ni, nullptr);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const double dr = nr[m] - pr[m], di = ni[m] - pi[m];
-        ek += dr * dr + di * di;
-      }
-    }
+    };
+    add_diff(r.s - x + (x + 1 == d.nx ? 0 : x + 1));
+    if (ndim >= 2) add_diff(r.s + ((y + 1 == d.ny ? 0 : y + 1) - y) * d.nx);
+    if (ndim == 3) add_diff(r.s + ((z + 1 == d.nz ? 0 : z + 1) - z) * plane);
     v[7] = ek;
     // interaction energy density (g0 n^2 + g1 |F|^2 + g2 |sigma|^2 / 5) / 2
     const double r6 = Consts::r6;
@@ -717,7 +737,7 @@ __global__ __launch_bounds__(kChunk) void k_reduce_record(LaunchGeom g, const do
 #pragma unroll
   for (int k = 0; k < kNObs; ++k) v[k] = 0.0;
   if (ovpart) {
-    const int nt = d.ntx * d.nty;
+    const int nt = d.ntx * d.nty * d.nz;
     for (int t = threadIdx.x; t < nt; t += kChunk) {
       v[0] += ovpart[2 * (d.tile_begin + t)];
       v[1] += ovpart[2 * (d.tile_begin + t) + 1];
@@ -764,6 +784,9 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
   A.pot = ext.V;
   A.mu = ext.mu;
   A.th_ext = T(plain ? full_factor * ext.theta : ext.theta);
+  A.prev = (const cx<T>*)in;
+  A.zpass = 0;
+  A.plain_u = 1;
   A.ntiles = g.ntiles;
   A.steps = steps;
   A.tile_rows = rows;
@@ -776,7 +799,7 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
 template <typename K, typename A>
 static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1, A args) {
-  if (ev0 && ev1)
+  if (ev0 || ev1)
     hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, ev0, ev1, 0u, args);
   else
     hipLaunchKernelGGL(kernel, grid, block, lds, st, args);
@@ -815,26 +838,38 @@ hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overl
   return hipGetLastError();
 }
 
-hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, const void* in, void* out,
-                         const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
-                         double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (g.ntiles == 0) return hipSuccess;
-  if (tile_rows < 1) return hipErrorInvalidValue;
-  const dim3 grid((g.ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
-  // 2D interleaved angles are eps^2/8; the plain split's single U uses eps^2 = 8x
-  const bool xt = ext.on();
-  if (dtype == 0) {
-    const size_t lds = sizeof(cx<float>) * kStageSlots * kLanes * k2DWaves;
-    const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 8.0, ext, ovpart, 1, tile_rows, plain, overlap);
-    if (xt) launch_timed(k_step2d<float, true>, grid, block, lds, st, ev0, ev1, args);
-    else launch_timed(k_step2d<float, false>, grid, block, lds, st, ev0, ev1, args);
-  } else {
-    const size_t lds = sizeof(cx<double>) * kStageSlots * kLanes * k2DWaves;
-    const auto args = step_args<double>(in, out, g, tg0, tg1, tg25, 8.0, ext, ovpart, 1, tile_rows, plain, overlap);
-    if (xt) launch_timed(k_step2d<double, true>, grid, block, lds, st, ev0, ev1, args);
-    else launch_timed(k_step2d<double, false>, grid, block, lds, st, ev0, ev1, args);
+template <typename T>
+static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+                                  double full_factor, const void* in, void* out, const void* prev,
+                                  const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
+                                  double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int ntiles = zpass ? g.ntiles_z : g.ntiles;
+  if (ntiles == 0) return hipSuccess;
+  const dim3 grid((ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
+  const size_t lds = sizeof(cx<T>) * kStageSlots * kLanes * k2DWaves;
+  auto args = step_args<T>(in, out, g, tg0, tg1, tg25, full_factor, ext, ovpart, 1, tile_rows, plain, overlap);
+  args.prev = (const cx<T>*)prev;
+  args.zpass = zpass ? 1 : 0;
+  args.plain_u = plain_u ? 1 : 0;
+  if (zpass) {
+    args.tile2inst = g.tile2inst_z;
+    args.ntiles = g.ntiles_z;
   }
+  if (ext.on()) launch_timed(k_step2d<T, true>, grid, block, lds, st, ev0, ev1, args);
+  else launch_timed(k_step2d<T, false>, grid, block, lds, st, ev0, ev1, args);
   return hipGetLastError();
+}
+
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+                         double full_factor, const void* in, void* out, const void* prev, const LaunchGeom& g,
+                         double tg0, double tg1, double tg25, const ExtPot& ext, double* ovpart,
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (tile_rows < 1) return hipErrorInvalidValue;
+  if (dtype == 0)
+    return launch_step2d_t<float>(plain, overlap, tile_rows, zpass, plain_u, full_factor, in, out, prev, g, tg0,
+                                  tg1, tg25, ext, ovpart, st, ev0, ev1);
+  return launch_step2d_t<double>(plain, overlap, tile_rows, zpass, plain_u, full_factor, in, out, prev, g, tg0,
+                                 tg1, tg25, ext, ovpart, st, ev0, ev1);
 }
 
 #define QLG_ELEMWISE(NAME, KERNEL, SRC_T, DST_T)                                                    \

@@ -37,7 +37,8 @@ EXPORTED = [
 class Params(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("nbatch", ctypes.c_int32), ("nx", ctypes.POINTER(ctypes.c_int64)),
-                ("ny", ctypes.POINTER(ctypes.c_int64)), ("g0", ctypes.c_double),
+                ("ny", ctypes.POINTER(ctypes.c_int64)), ("nz", ctypes.POINTER(ctypes.c_int64)),
+                ("g0", ctypes.c_double),
                 ("g1", ctypes.c_double), ("g2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
@@ -123,14 +124,17 @@ def lib() -> ctypes.CDLL:
 
 
 def make_params(ndim: int, nx: Sequence[int], ny: Optional[Sequence[int]], g, eps: float,
-                dtype: int = C128, split: int = INTERLEAVED):
+                dtype: int = C128, split: int = INTERLEAVED, nz: Optional[Sequence[int]] = None):
     nb = len(nx)
+    P64 = ctypes.POINTER(ctypes.c_int64)
     nx_arr = (ctypes.c_int64 * nb)(*[int(v) for v in nx])
     ny_arr = (ctypes.c_int64 * nb)(*[int(v) for v in ny]) if ny is not None else None
+    nz_arr = (ctypes.c_int64 * nb)(*[int(v) for v in nz]) if nz is not None else None
     p = Params(ndim, dtype, split, nb, nx_arr,
-               ctypes.cast(ny_arr, ctypes.POINTER(ctypes.c_int64)) if ny_arr is not None else None,
+               ctypes.cast(ny_arr, P64) if ny_arr is not None else None,
+               ctypes.cast(nz_arr, P64) if nz_arr is not None else None,
                float(g[0]), float(g[1]), float(g[2]), float(eps))
-    return p, (nx_arr, ny_arr)
+    return p, (nx_arr, ny_arr, nz_arr)
 
 
 def query_sizes(params: Params):
@@ -152,11 +156,12 @@ class Lattice:
     """One context over caller-owned (torch) device buffers.
 
     ``psi`` arguments use the canonical layout: a complex tensor per instance
-    of shape (5, nx) in 1D or (5, ny, nx) in 2D, components ordered m = 2..-2;
-    batches are passed as lists.
+    of shape (5, nx) in 1D, (5, ny, nx) in 2D or (5, nz, ny, nx) in 3D,
+    components ordered m = 2..-2; batches are passed as lists.
     """
 
     def __init__(self, ndim: int, nx: Sequence[int], ny: Optional[Sequence[int]] = None,
+                 nz: Optional[Sequence[int]] = None,
                  g=(1.0, -0.5, 0.5), eps: float = 0.1, dtype: str = "c128",
                  split: str = "interleaved", device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
         if not torch.cuda.is_available():
@@ -164,15 +169,17 @@ class Lattice:
         self.ndim = ndim
         self.nx = [int(v) for v in nx]
         self.ny = [int(v) for v in ny] if ny is not None else [1] * len(self.nx)
+        self.nz = [int(v) for v in nz] if nz is not None else [1] * len(self.nx)
         self.g = tuple(float(v) for v in g)
         self.eps = float(eps)
         self.dtype_code = {"c64": C64, "c128": C128}[dtype]
         self.torch_dtype = torch.complex64 if self.dtype_code == C64 else torch.complex128
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.params, self._keep = make_params(ndim, self.nx, ny if ndim == 2 else None, self.g, self.eps,
+        self.params, self._keep = make_params(ndim, self.nx, ny if ndim >= 2 else None, self.g, self.eps,
                                               self.dtype_code,
-                                              {"interleaved": INTERLEAVED, "plain": PLAIN}[split])
+                                              {"interleaved": INTERLEAVED, "plain": PLAIN}[split],
+                                              nz if ndim == 3 else None)
         sb, cb = query_sizes(self.params)
         self.state_buf = _device_bytes(sb, self.device)
         self.scratch_buf = _device_bytes(cb, self.device)
@@ -192,7 +199,7 @@ class Lattice:
 
     @property
     def sites(self) -> int:
-        return int(sum(a * b for a, b in zip(self.nx, self.ny)))
+        return int(sum(a * b * c for a, b, c in zip(self.nx, self.ny, self.nz)))
 
     def _check(self, st: int, where: str):
         if st != QLG_OK:
@@ -200,23 +207,24 @@ class Lattice:
             raise QLGError(st, where, msg.decode() if msg else "")
 
     def _shape(self, i: int):
-        return (5, self.nx[i]) if self.ndim == 1 else (5, self.ny[i], self.nx[i])
+        return (5, self.nx[i]) if self.ndim == 1 else (5, self.ny[i], self.nx[i]) if self.ndim == 2 \
+            else (5, self.nz[i], self.ny[i], self.nx[i])
 
     def _flat(self, fields: List, per_site: int) -> torch.Tensor:
         parts = []
         for i, f in enumerate(fields):
             t = torch.as_tensor(f) if not isinstance(f, torch.Tensor) else f
             t = t.to(device=self.device, dtype=self.torch_dtype)
-            if t.numel() != per_site * self.nx[i] * self.ny[i]:
-                raise ValueError("field %d has %d elements, expected %d" %
-                                 (i, t.numel(), per_site * self.nx[i] * self.ny[i]))
+            n = per_site * self.nx[i] * self.ny[i] * self.nz[i]
+            if t.numel() != n:
+                raise ValueError("field %d has %d elements, expected %d" % (i, t.numel(), n))
             parts.append(t.reshape(-1))
         return torch.cat(parts).contiguous()
 
     def _unflat(self, flat: torch.Tensor, per_site: int):
         out, o = [], 0
         for i in range(self.nbatch):
-            n = per_site * self.nx[i] * self.ny[i]
+            n = per_site * self.nx[i] * self.ny[i] * self.nz[i]
             shape = self._shape(i)
             shape = shape if per_site == 5 else (2,) + shape
             out.append(flat[o:o + n].reshape(shape))
@@ -258,9 +266,9 @@ class Lattice:
             parts = []
             for i, f in enumerate(fields):
                 t = torch.as_tensor(f).to(device=self.device, dtype=torch.float64)
-                if t.numel() != self.nx[i] * self.ny[i]:
+                if t.numel() != self.nx[i] * self.ny[i] * self.nz[i]:
                     raise ValueError("potential %d has %d values, expected %d" %
-                                     (i, t.numel(), self.nx[i] * self.ny[i]))
+                                     (i, t.numel(), self.nx[i] * self.ny[i] * self.nz[i]))
                 parts.append(t.reshape(-1))
             self._pot = torch.cat(parts).contiguous()
         self._check(lib().qlg_set_potential(self.ctx, self._pot.data_ptr() if self._pot is not None else None,
@@ -269,7 +277,7 @@ class Lattice:
     def _unflat_scalar(self, flat: torch.Tensor) -> List[torch.Tensor]:
         out, o = [], 0
         for i in range(self.nbatch):
-            n = self.nx[i] * self.ny[i]
+            n = self.nx[i] * self.ny[i] * self.nz[i]
             out.append(flat[o:o + n].reshape(self._shape(i)[1:]))
             o += n
         return out

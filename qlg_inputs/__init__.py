@@ -194,11 +194,12 @@ class Workload:
     ndim: int
     nx: List[int]
     ny: List[int]
-    psi: List[np.ndarray]             # one complex128 array per instance, (5, ny, nx) or (5, nx)
+    psi: List[np.ndarray]             # one complex128 array per instance, (5, [nz,] [ny,] nx)
     g: tuple
     eps: float
     nsteps: int
     meta: dict = field(default_factory=dict)
+    nz: List[int] = field(default_factory=lambda: [1])
 
     @property
     def nbatch(self) -> int:
@@ -206,7 +207,8 @@ class Workload:
 
     @property
     def sites(self) -> int:
-        return int(sum(a * b for a, b in zip(self.nx, self.ny)))
+        return int(sum(a * b * c for a, b, c in zip(self.nx, self.ny, self.nz * len(self.nx)
+                                                      if len(self.nz) == 1 else self.nz)))
 
 
 def c1_single_bright(L: int = 1024, width: float = 32.0, eps: float = 0.1, seed: int = 1907,
@@ -283,6 +285,34 @@ def c5_adjoint(n: int = 512, sep: float = 128.0, eps: float = 0.1, seed: int = 2
     psi = vortex_pair_2d(n, n, sep, eps, rng)
     return Workload("2d_adjoint_%dx%d" % (n, n), 2, [n], [n], [psi], (1.0, -0.3, 0.2), eps,
                     nsteps, {"sep": sep, "seed": seed, "checkpoint_every": checkpoint_every})
+
+
+def vortex_lines_3d(n: int, sep: float, eps: float, rng: np.random.Generator, amp: float = 4.0,
+                    coeffs=(0.3, 0.05, 0.4), jitter: float = 0.05) -> np.ndarray:
+    """The 2D vortex pair of vortex_pair_2d extruded along z into two vortex lines on an n^3
+    lattice, each line displaced along x by amp * sin(2 pi z / n + phase) (one period over the
+    lattice, seeded phases), so that the lines bend and move in 3D."""
+    a1, a2, b1 = (c * (1.0 + jitter * rng.uniform(-1.0, 1.0)) for c in coeffs)
+    pha, phb = rng.uniform(0.0, 2 * math.pi, size=2)
+    amp0 = math.sqrt(1.0 / 3.0)
+    psi = np.zeros((5, n, n, n), dtype=np.complex128)
+    for z in range(n):
+        cxa = n / 2 - sep / 2 + amp * math.sin(2 * math.pi * z / n + pha)
+        cxb = n / 2 + sep / 2 + amp * math.sin(2 * math.pi * z / n + phb)
+        va = vortex_2d(n, n, cxa, n / 2, +1, eps, a1, a2, b1)
+        vb = vortex_2d(n, n, cxb, n / 2, -1, eps, a1, a2, b1)
+        psi[0, z] = amp0 * va
+        psi[4, z] = amp0 * va
+        psi[2, z] = amp0 * vb
+    return psi
+
+
+def c6_vortex_lines(n: int = 256, sep: float = 64.0, eps: float = 0.1, seed: int = 2020,
+                    nsteps: int = 1000) -> Workload:
+    rng = np.random.default_rng(seed)
+    psi = vortex_lines_3d(n, sep, eps, rng)
+    return Workload("3d_vortex_lines_%d" % n, 3, [n], [n], [psi], (1.0, -0.3, 0.2), eps, nsteps,
+                    {"sep": sep, "seed": seed}, nz=[n])
 
 
 def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:

@@ -40,10 +40,11 @@ def test_version_and_status_strings(Q):
 
 
 def _sizes(Q, **kw):
-    args = dict(ndim=1, nx=[100], ny=None, g=(1, -0.5, 0.5), eps=0.1, dtype=Q.C128, split=Q.INTERLEAVED)
+    args = dict(ndim=1, nx=[100], ny=None, nz=None, g=(1, -0.5, 0.5), eps=0.1, dtype=Q.C128,
+                split=Q.INTERLEAVED)
     args.update(kw)
     p, keep = Q.make_params(args["ndim"], args["nx"], args["ny"], args["g"], args["eps"], args["dtype"],
-                            args["split"])
+                            args["split"], args["nz"])
     s, c = ctypes.c_size_t(), ctypes.c_size_t()
     st = Q.lib().qlg_query_sizes(ctypes.byref(p), ctypes.byref(s), ctypes.byref(c))
     return st, s.value, c.value
@@ -58,10 +59,16 @@ def test_query_sizes_layout(Q):
     assert st == 0 and s64 == s // 2
     st, s2, _ = _sizes(Q, ndim=2, nx=[30, 7], ny=[10, 3])
     assert st == 0 and s2 == 2 * 10 * (320 + 64) * 16
+    # 3D: 10 x 4 x 3 = 120 sites, padded to 128, and 1 x 1 x 65 = 65 sites, padded to 128
+    st, s3, _ = _sizes(Q, ndim=3, nx=[10, 1], ny=[4, 1], nz=[3, 65])
+    assert st == 0 and s3 == 2 * 10 * (128 + 128) * 16
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(ndim=3), 2), (dict(ndim=0), 2), (dict(nx=[0]), 2), (dict(nx=[-5]), 2),
+    (dict(ndim=4), 2), (dict(ndim=0), 2), (dict(nx=[0]), 2), (dict(nx=[-5]), 2),
+    (dict(ndim=3, nx=[4], ny=[4]), 1), (dict(ndim=3, nx=[4], ny=[4], nz=[0]), 2),
+    (dict(ndim=3, nx=[2048], ny=[2048], nz=[1024]), 2), (dict(ndim=2, nx=[4], ny=[4], nz=[2]), 2),
+    (dict(nx=[4], nz=[3]), 2),
     (dict(nx=[1 << 31]), 2), (dict(ndim=2, nx=[70000], ny=[70000]), 2),
     (dict(dtype=5), 3), (dict(split=9), 1), (dict(eps=0.0), 1), (dict(eps=float("nan")), 1),
     (dict(g=(float("inf"), 0, 0)), 1), (dict(ndim=2, nx=[4], ny=None), 1),
