@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -31,9 +33,11 @@ sys.path.insert(0, ROOT)
 # self-interaction are not counted.
 FLOPS_U = 894          # one application of U (coefficients 190 + 2 x 352 per 5-vector)
 FLOPS_IPRIME = 85      # one I' (two collides 2 x 40 + its share of the exact 1/256 per step, 5)
-FLOPS_PER_SITE_STEP = {1: 4 * (FLOPS_U + FLOPS_IPRIME), 2: 8 * (FLOPS_U + FLOPS_IPRIME)}
+FLOPS_PER_SITE_STEP = {d: 4 * d * (FLOPS_U + FLOPS_IPRIME) for d in (1, 2, 3)}
 # plain split: one U (theta = eps^2) and the 4 d I' of a step
-FLOPS_PER_SITE_STEP_PLAIN = {1: FLOPS_U + 4 * FLOPS_IPRIME, 2: FLOPS_U + 8 * FLOPS_IPRIME}
+FLOPS_PER_SITE_STEP_PLAIN = {d: FLOPS_U + 4 * d * FLOPS_IPRIME for d in (1, 2, 3)}
+# HBM passes per step: 1D and 2D one fused pass, 3D a z pass and a y-x pass
+PASSES_PER_STEP = {1: 1, 2: 1, 3: 2}
 # HBM bytes per site per pass: read + write of 10 complex amplitudes
 BYTES_PER_SITE_PASS = {"c64": 2 * 10 * 8, "c128": 2 * 10 * 16}
 # MI355X published peaks
@@ -41,24 +45,31 @@ PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vect
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 
-# HBM traffic of one launch of the fused step on the two workloads (complex64), by kernel and
-# plan (steps per pass in 1D, band height in 2D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
+# HBM traffic of one launch of the fused step on the three workloads (complex64), by kernel and
+# plan (steps per pass in 1D, band height in 2D and 3D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
 # mean over the dispatches of that plan), each scaled by what the same counter reads for a
 # 256 MiB device copy in the same run (FETCH_SIZE: x2.000, WRITE_SIZE: x1.000).  Valid only
 # for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "7937ff896441d2cc", "fetch_scale": 262144.0 / 131088.6, "write_scale": 1.0,
+TRAFFIC = {"sources_sha256_16": "14ec845cefda21a3", "fetch_scale": 262144.0 / 131088.1, "write_scale": 1.0,
            "kib": {"k_step1d/S1": (783.6, 1280.0), "k_step1d/S2": (784.4, 1280.0), "k_step1d/S3": (783.9, 1280.0),
                    "k_step1d/S4": (783.0, 1280.0), "k_step1d/S5": (793.8, 1280.0), "k_step1d/S6": (833.5, 1281.0),
                    "k_step1d/S7": (796.1, 1280.0), "k_step1d_pair/S1": (762.7, 1280.0),
                    "k_step1d_pair/S2": (763.4, 1280.0), "k_step1d_pair/S3": (762.9, 1280.0),
                    "k_step1d_pair/S4": (762.0, 1280.0),
                    # 2D vortex-pair workload, 2048^2 (bands of rows)
-                   "k_step2d/rows38": (234817.7, 328501.9), "k_step2d/rows76": (214313.9, 328202.3),
-                   "k_step2d/rows64": (220021.2, 328337.3), "k_step2d/rows32": (231682.5, 328670.1),
-                   "k_step2d/rows25": (238789.6, 329221.1), "k_step2d/rows19": (260713.5, 329018.8),
-                   "k_step2d/rows16": (273047.8, 330039.3), "k_step2d/rows128": (182792.4, 327976.4)}}
+                   "k_step2d/rows38": (234741.7, 328517.5), "k_step2d/rows76": (214411.0, 328190.6),
+                   "k_step2d/rows64": (220341.3, 328306.9), "k_step2d/rows32": (231872.2, 328746.0),
+                   "k_step2d/rows25": (238950.0, 329296.8), "k_step2d/rows19": (260701.3, 329088.3),
+                   "k_step2d/rows16": (273389.8, 329942.6), "k_step2d/rows128": (182862.8, 327874.4),
+                   # 3D vortex-line workload, 256^3: one step = z pass + y-x pass (sums of the two)
+                   "k_step3d/rows16": (983193.2 + 1214106.1, 1310720.0 + 1323797.8),
+                   "k_step3d/rows32": (819383.3 + 1062733.6, 1310720.0 + 1316973.2),
+                   "k_step3d/rows64": (737439.6 + 921646.7, 1310720.0 + 1313911.2),
+                   "k_step3d/rows86": (722071.8 + 876737.2, 1310720.0 + 1314446.8),
+                   "k_step3d/rows128": (696468.0 + 798938.1, 1310720.0 + 1315712.0),
+                   "k_step3d/rows256": (675981.0 + 829576.0, 1310720.0 + 1317831.7)}}
 
 
 def parse():
@@ -103,22 +114,37 @@ WORKLOADS = {
     # name: (ndim, description)
     "1d_two_soliton_scattering": (1, "1D L = 16384 two bright solitons, w = 48, k = -+0.05 pi"),
     "2d_vortex_pair": (2, "2D 2048^2 uniform background with a Pade vortex pair 128 sites apart"),
+    "3d_vortex_lines": (3, "3D 256^3 uniform background with two wavy Pade vortex lines 64 sites apart"),
 }
 
 
 def workload_input(name, steps):
     import qlg_inputs as qi
-    return qi.c2_two_solitons(nsteps=steps) if name == "1d_two_soliton_scattering" else qi.c3_vortex_pair(nsteps=steps)
+    if name == "1d_two_soliton_scattering":
+        return qi.c2_two_solitons(nsteps=steps)
+    if name == "2d_vortex_pair":
+        return qi.c3_vortex_pair(nsteps=steps)
+    return qi.c6_vortex_lines(nsteps=steps)
+
+
+def workload_lattice(w, ndim, dtype, split="interleaved"):
+    from paper_1907_12834_amd.qlg import Lattice
+    return Lattice(ndim, w.nx, w.ny if ndim >= 2 else None, w.nz if ndim == 3 else None, g=w.g, eps=w.eps,
+                   dtype=dtype, split=split)
+
+
+def workload_shape(w, ndim):
+    return [w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]] if ndim == 2 else [w.nz[0], w.ny[0], w.nx[0]]
 
 
 def trap_potential(w, ndim):
     """A weak harmonic trap V = omega^2 r^2 / 4 centred on the lattice (m = 1/2), with omega chosen
     so that V reaches 1/2 at the edge midpoints, plus mu = 0.5."""
-    import numpy as np
-    half = [0.5 * w.eps * n for n in ([w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]])]
+    shape = workload_shape(w, ndim)
+    half = [0.5 * w.eps * n for n in shape]
     omega = math.sqrt(2.0) / max(half)
-    axes = [w.eps * (np.arange(n) - n / 2) for n in ([w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]])]
-    r2 = axes[0] ** 2 if ndim == 1 else axes[0][:, None] ** 2 + axes[1][None, :] ** 2
+    axes = [w.eps * (np.arange(n) - n / 2) for n in shape]
+    r2 = sum(np.expand_dims(a ** 2, [k for k in range(ndim) if k != i]) for i, a in enumerate(axes))
     return omega ** 2 * r2 / 4, 0.5
 
 
@@ -126,12 +152,11 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     """Run the workload (with a harmonic trap and mu if `trap`); return rate, wall time,
     per-launch kernel time and plan."""
     import torch
-    from paper_1907_12834_amd.qlg import Lattice
 
     w = workload_input(workload, steps)
     ndim = WORKLOADS[workload][0]
-    L = w.nx[0] * (w.ny[0] if ndim == 2 else 1)   # sites
-    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype, split=split)
+    L = int(np.prod(workload_shape(w, ndim)))   # sites
+    lat = workload_lattice(w, ndim, dtype, split)
     if trap:
         lat.set_potential(*trap_potential(w, ndim))
     lat.set_psi([torch.from_numpy(w.psi[0])])
@@ -182,11 +207,11 @@ def diagnostics(workload, dtype, reps):
     lattice after 20 steps: average time per launch over `reps` back-to-back launches, from HIP
     events on the library's stream, against the algorithmic HBM bytes of each kernel."""
     import torch
-    from paper_1907_12834_amd.qlg import Lattice, lib
+    from paper_1907_12834_amd.qlg import lib
 
     w = workload_input(workload, 20)
     ndim = WORKLOADS[workload][0]
-    lat = Lattice(ndim, w.nx, w.ny if ndim == 2 else None, g=w.g, eps=w.eps, dtype=dtype)
+    lat = workload_lattice(w, ndim, dtype)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     lat.step(20)
     n = lat.sites
@@ -313,7 +338,7 @@ def main():
     flops_site = (FLOPS_PER_SITE_STEP if args.split == "interleaved" else FLOPS_PER_SITE_STEP_PLAIN)[ndim]
     flops_launch = flops_site * sites_per_launch
     achieved_tflops = flops_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
-    bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L
+    bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L * PASSES_PER_STEP[ndim]
     hbm_gbs = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     # the roofline that bounds this launch: flops per algorithmic byte against the ridge point
     intensity = flops_launch / bytes_launch
@@ -321,9 +346,12 @@ def main():
     if ndim == 1:
         kernel = "k_step1d_pair" if m["tuning"].get("pair_waves") else "k_step1d"
         key = "%s/S%d" % (kernel, S)
-    else:
+    elif ndim == 2:
         kernel = "k_step2d"
         key = "%s/rows%d" % (kernel, m["tuning"]["tile_rows"])
+    else:   # a launch here is one step: the z pass and the y-x pass of the same kernel
+        kernel = "k_step2d (z pass + y-x pass)"
+        key = "k_step3d/rows%d" % m["tuning"]["tile_rows"]
     traffic = None
     if args.dtype == "c64" and key in TRAFFIC["kib"] and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
         fk, wk = TRAFFIC["kib"][key]
@@ -363,7 +391,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload,
-            "lattice": [w.nx[0]] if ndim == 1 else [w.ny[0], w.nx[0]],
+            "lattice": workload_shape(w, ndim),
             "storage": args.dtype,
             "split": args.split,
             "g": list(w.g),
@@ -399,19 +427,22 @@ def main():
     print(json.dumps(out))
 
 
-def cpu_baseline(w, nsteps, ndim=1):
-    """The FP64 oracle, as it stands, on the first `nsteps` steps of the same workload."""
+def cpu_baseline(w, nsteps, ndim=1, box3d=96):
+    """The FP64 oracle, as it stands, on the first `nsteps` steps of the same workload (3D: of a
+    box3d^3 corner of its state, the whole 256^3 lattice being far beyond a bounded sample)."""
     import torch
     from oracle import qlg_oracle as O
     threads = torch.get_num_threads()
+    psi = w.psi[0] if ndim < 3 else np.ascontiguousarray(w.psi[0][:, :box3d, :box3d, :box3d])
     t0 = time.perf_counter()
-    O.run_psi(w.psi[0], nsteps, w.eps, w.g)
+    O.run_psi(psi, nsteps, w.eps, w.g)
     dt = time.perf_counter() - t0
-    sites = w.nx[0] * (w.ny[0] if ndim == 2 else 1)
-    shape = "L=%d" % w.nx[0] if ndim == 1 else "%dx%d" % (w.ny[0], w.nx[0])
+    sites = int(np.prod(psi.shape[1:]))
+    shape = "x".join(str(v) for v in psi.shape[1:]) if ndim > 1 else "L=%d" % w.nx[0]
+    what = "same %dD %s workload" % (ndim, shape) if ndim < 3 else \
+        "a %s corner of the 3D %s workload" % (shape, "x".join(str(v) for v in workload_shape(w, ndim)))
     return {"value": sites * nsteps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "same %dD %s workload, first %d steps (FP64 torch CPU, %d threads), %.1f s"
-                      % (ndim, shape, nsteps, threads, dt)}
+            "sample": "%s, first %d steps (FP64 torch CPU, %d threads), %.1f s" % (what, nsteps, threads, dt)}
 
 
 if __name__ == "__main__":
