@@ -525,6 +525,24 @@ qlg_status qlg_vorticity(qlg_ctx* c, int32_t m_index, double* omega, int32_t* wi
   return QLG_OK;
 }
 
+qlg_status qlg_find_vortices(qlg_ctx* c, int32_t m_index, int32_t* winding, int32_t* cores, int64_t capacity,
+                             int64_t* count) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  if (c->p.ndim != 2) return fail(c, QLG_ERR_SHAPE, "vortex cores need a 2D lattice");
+  if (m_index < 0 || m_index > 4) return fail(c, QLG_ERR_ARG, "m_index must be in 0..4");
+  if (!winding || !count) return fail(c, QLG_ERR_ARG, "winding or count is NULL");
+  if (capacity < 0 || (capacity > 0 && !cores)) return fail(c, QLG_ERR_ARG, "bad capacity or NULL cores");
+  for (const qlg::InstDesc& d : c->L.inst) {
+    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->copy(c->cur), d, m_index, nullptr, winding, c->stream),
+                  "vorticity kernel");
+    if (s) return s;
+  }
+  int64_t* counts = reinterpret_cast<int64_t*>(c->sc(c->S.obs_part));   // nchunks int64 fit in the partials
+  return hip_check(c, qlg::launch_vortex_cores(winding, c->geom(), counts, cores, capacity, count, c->stream),
+                   "vortex core kernels");
+}
+
 qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
   qlg_status s = check_ctx(c);
   if (s) return s;

@@ -18,4 +18,10 @@ hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, doub
 hipError_t launch_vorticity(int dtype, const void* state, const InstDesc& d, int m, double* omega,
                             int32_t* winding, hipStream_t st);
 
+// The non-zero entries of a winding field (canonical scalar layout) as an ordered
+// list out[k] = {instance, y, x, winding}, k < capacity; *total (device) receives
+// the number of cores.  counts: nchunks int64 of workspace.
+hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int64_t* counts, int32_t* out,
+                               int64_t capacity, int64_t* total, hipStream_t st);
+
 }  // namespace qlg

@@ -146,6 +146,79 @@ __global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vortex cores: the plaquettes with a non-zero winding, as an ordered list
+// ---------------------------------------------------------------------------
+// Three launches, no atomics, so the list is in (instance, y, x) order on every
+// run: the non-zero count of every 256-site chunk; one workgroup's exclusive
+// scan of the counts (the chunks of an instance are consecutive, and so are the
+// instances); then every chunk writes its cores at its offset, ranked inside the
+// chunk by wave ballots.
+__global__ __launch_bounds__(kChunk) void k_core_count(const int32_t* __restrict__ wind, LaunchGeom g,
+                                                      int64_t* __restrict__ counts) {
+  __shared__ int wsum[kChunk / kLanes];
+  const InstDesc d = g.inst[g.chunk2inst[blockIdx.x]];
+  const int s = (blockIdx.x - d.chunk_begin) * kChunk + threadIdx.x;
+  const bool core = s < d.sites && wind[d.psi_off / 5 + s] != 0;
+  const int c = __popcll(__ballot(core));
+  if ((threadIdx.x & (kLanes - 1)) == 0) wsum[threadIdx.x / kLanes] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < kChunk / kLanes; ++k) t += wsum[k];
+    counts[blockIdx.x] = t;
+  }
+}
+
+constexpr int kScanThreads = 1024;
+
+// In place: counts[c] <- sum of counts[0..c), and *total <- the sum of all.
+__global__ __launch_bounds__(kScanThreads) void k_core_scan(int64_t* __restrict__ counts, int nchunks,
+                                                           int64_t* __restrict__ total) {
+  __shared__ int64_t buf[kScanThreads];
+  int64_t carry = 0;
+  for (int base = 0; base < nchunks; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    const int64_t v = i < nchunks ? counts[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the block
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const int64_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nchunks) counts[i] = carry + buf[threadIdx.x] - v;
+    carry += buf[kScanThreads - 1];
+    __syncthreads();   // buf is rewritten by the next block of chunks
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kChunk) void k_core_scatter(const int32_t* __restrict__ wind, LaunchGeom g,
+                                                        const int64_t* __restrict__ offsets,
+                                                        int32_t* __restrict__ out, int64_t capacity) {
+  __shared__ int wsum[kChunk / kLanes];
+  const int inst = g.chunk2inst[blockIdx.x];
+  const InstDesc d = g.inst[inst];
+  const int s = (blockIdx.x - d.chunk_begin) * kChunk + threadIdx.x;
+  const int32_t w = s < d.sites ? wind[d.psi_off / 5 + s] : 0;
+  const unsigned long long mask = __ballot(w != 0);
+  const int lane = threadIdx.x & (kLanes - 1), wv = threadIdx.x / kLanes;
+  if (lane == 0) wsum[wv] = __popcll(mask);
+  __syncthreads();
+  if (w == 0) return;
+  int64_t k = offsets[blockIdx.x] + __popcll(mask & ((1ull << lane) - 1ull));
+  for (int j = 0; j < wv; ++j) k += wsum[j];
+  if (k >= capacity) return;
+  int32_t* e = out + 4 * k;
+  e[0] = inst;
+  e[1] = s / d.nx;
+  e[2] = s % d.nx;
+  e[3] = w;
+}
+
 }  // namespace
 
 hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, double* n, double* f_par,
@@ -181,6 +254,19 @@ hipError_t launch_vorticity(int dtype, const void* state, const InstDesc& d, int
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int64_t* counts, int32_t* out,
+                               int64_t capacity, int64_t* total, hipStream_t st) {
+  if (g.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_core_count, dim3(g.nchunks), dim3(kChunk), 0, st, winding, g, counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_core_scan, dim3(1), dim3(kScanThreads), 0, st, counts, g.nchunks, total);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_core_scatter, dim3(g.nchunks), dim3(kChunk), 0, st, winding, g, counts, out, capacity);
+  return hipGetLastError();
 }
 
 }  // namespace qlg

@@ -26,7 +26,7 @@ RECORD_DOUBLES = 16   # QLG_RECORD_DOUBLES
 # every symbol declared in include/qlg.h
 EXPORTED = [
     "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
-    "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
+    "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_find_vortices", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
     "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_set_potential": (i32, [vp, vp, dbl]),
         "qlg_fields": (i32, [vp, vp, vp, vp, vp]),
         "qlg_vorticity": (i32, [vp, i32, vp, vp]),
+        "qlg_find_vortices": (i32, [vp, i32, vp, vp, i64, vp]),
         "qlg_step": (i32, [vp, i64]),
         "qlg_observables": (i32, [vp, P(Obs)]),
         "qlg_record_observables": (i32, [vp, vp]),
@@ -305,6 +306,32 @@ class Lattice:
             if buf is not None:
                 for i, v in enumerate(self._unflat_scalar(buf)):
                     out[i][key] = v
+        return out
+
+    def find_vortices(self, m_index: int, capacity: int = 4096) -> torch.Tensor:
+        """Vortex cores of component m_index (Sec. VI): an int32 tensor (k, 4) of
+        (instance, y, x, winding) rows in (instance, y, x) order, on the device."""
+        wind = torch.empty(self.sites, dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        while True:
+            cores = torch.empty((max(int(capacity), 1), 4), dtype=torch.int32, device=self.device)
+            self._check(lib().qlg_find_vortices(self.ctx, int(m_index), wind.data_ptr(), cores.data_ptr(),
+                                                int(capacity), count.data_ptr()), "qlg_find_vortices")
+            n = int(count.item())
+            if n <= capacity:
+                return cores[:n]
+            capacity = n
+
+    def track_vortices(self, m_index: int, nsteps: int, every: int) -> List[tuple]:
+        """Advance nsteps, listing the cores of component m_index every `every` steps (and at the
+        start): [(step, cores (k, 4) on the device), ...], the paper's vortex tracks."""
+        out = [(0, self.find_vortices(m_index))]
+        done = 0
+        while done < nsteps:
+            n = min(int(every), nsteps - done)
+            self.step(n)
+            done += n
+            out.append((done, self.find_vortices(m_index)))
         return out
 
     def step(self, nsteps: int = 1):

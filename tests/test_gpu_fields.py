@@ -161,3 +161,75 @@ def test_diagnostics_argument_errors():
         lat2.vorticity(0, omega=False, winding=False)
     # the context stays usable after argument errors
     check_vorticity(lat2, 3)
+
+
+def oracle_cores(psis, m_index):
+    """np.argwhere of the oracle's winding field, as (instance, y, x, winding) rows in order."""
+    rows = []
+    for i, psi in enumerate(psis):
+        _, w = O.vorticity(psi[m_index])
+        rows += [(i, int(y), int(x), int(w[y, x])) for y, x in np.argwhere(w)]
+    return np.array(rows, dtype=np.int64).reshape(-1, 4)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_find_vortices_ragged_batch(dtype):
+    """Core lists of random fields on ragged instances (thousands of cores across many 256-site
+    chunks and instances) equal the oracle's, entry by entry and in order; a capacity below the
+    count writes the first entries and reports the full count."""
+    nx, ny = [70, 33, 1, 2, 130, 3, 300], [45, 130, 7, 1, 17, 3, 40]
+    lat = lattice(2, nx, ny, g=(1.0, -0.3, 0.2), eps=0.5, dtype=dtype)
+    lat.set_psi([torch.from_numpy(qi.random_field((y, x), seed=17 + i)) for i, (x, y) in enumerate(zip(nx, ny))])
+    lat.step(2)
+    psis = [p.cpu().numpy() for p in lat.get_psi()]
+    for m in (0, 3):
+        ref = oracle_cores(psis, m)
+        assert len(ref) > 1000
+        got = lat.find_vortices(m, capacity=64).cpu().numpy()       # grows to the count by itself
+        assert np.array_equal(got, ref), (m, got[:5], ref[:5])
+    from paper_1907_12834_amd.qlg import lib
+    wind = torch.empty(lat.sites, dtype=torch.int32, device="cuda")
+    cores = torch.full((10, 4), -7, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert lib().qlg_find_vortices(lat.ctx, 0, wind.data_ptr(), cores.data_ptr(), 10, count.data_ptr()) == 0
+    ref = oracle_cores(psis, 0)
+    assert int(count.item()) == len(ref) and np.array_equal(cores.cpu().numpy(), ref[:10])
+    assert lib().qlg_find_vortices(lat.ctx, 0, wind.data_ptr(), None, 0, count.data_ptr()) == 0
+    assert int(count.item()) == len(ref)
+
+
+def test_track_vortices_kicked_quadrupole():
+    """Vortex tracks (Sec. VI): a Pade quadrupole in m = +1 on a flow of k = 2 pi / n per site; every
+    25 steps the four cores (two +1, two -1) equal the oracle's, and they drift with the flow, about
+    2k sites per step along x."""
+    n, eps = 96, 0.25
+    g = (1.0, -0.3, 0.2)
+    k = 2 * np.pi / n
+    psi = qi.pade_quadrupole_2d(n, eps, 24.3, g[0] + g[1], 1) * np.exp(1j * k * np.arange(n))[None, None, :]
+    lat = lattice(2, [n], [n], g=g, eps=eps, dtype="c128")
+    lat.set_psi([torch.from_numpy(psi)])
+    tracks = lat.track_vortices(1, 100, 25)
+    a, b = O.encode(torch.from_numpy(psi))
+    for i, (step, cores) in enumerate(tracks):
+        assert step == 25 * i
+        if i:
+            a, b = O.run(a, b, 25, eps, g, 2)
+        ref = oracle_cores([(a + b).numpy()], 1)
+        got = cores.cpu().numpy()
+        assert np.array_equal(got, ref), (step, got, ref)
+        assert sorted(got[:, 3].tolist()) == [-1, -1, 1, 1]
+    x0 = tracks[0][1][:, 2].double().mean().item()
+    x1 = tracks[-1][1][:, 2].double().mean().item()
+    assert 0.6 * 2 * k * 100 < x1 - x0 < 1.6 * 2 * k * 100, (x0, x1)
+
+
+def test_find_vortices_argument_errors():
+    from paper_1907_12834_amd.qlg import QLGError
+    lat1 = lattice(1, [64], None, g=(1, 0, 0), eps=0.5, dtype="c128")
+    lat1.set_psi([torch.from_numpy(qi.random_field((64,), seed=1))])
+    with pytest.raises(QLGError, match="QLG_ERR_SHAPE"):
+        lat1.find_vortices(0)
+    lat2 = lattice(2, [16], [16], g=(1, 0, 0), eps=0.5, dtype="c128")
+    lat2.set_psi([torch.from_numpy(qi.random_field((16, 16), seed=1))])
+    with pytest.raises(QLGError, match="QLG_ERR_ARG"):
+        lat2.find_vortices(7)
