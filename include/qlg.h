@@ -147,9 +147,10 @@ qlg_status qlg_get_qubits(qlg_ctx* ctx, void* qubits_dev);
  * later qlg_step and observables call reads it, so it must stay allocated until
  * the potential is replaced or the context destroyed (its values may change
  * between calls).  mu: finite, else QLG_ERR_ARG.  qlg_set_potential(ctx, NULL, 0)
- * returns to the plain equation.  While a potential is set the adjoint entry
- * points (qlg_forward_record, qlg_objective_grad, qlg_adjoint_step) return
- * QLG_ERR_STATE.  Host-side only; drops the captured step graphs. */
+ * returns to the plain equation.  The adjoint entry points differentiate the
+ * run with the potential in place, V and mu being constants (no derivative with
+ * respect to them); the energy objective includes its (V + mu) n term.
+ * Host-side only; drops the captured step graphs. */
 qlg_status qlg_set_potential(qlg_ctx* ctx, const double* V_dev, double mu);
 
 /* Per-site diagnostic fields of the current state (Sec. III, eq. (cmap)), in

@@ -19,12 +19,15 @@ from .qlg import Lattice
 class QLGObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, psi0: torch.Tensor, g: torch.Tensor, ndim: int, eps: float, nsteps: int,
-                checkpoint_every: int, dtype: str, split: str, kind: str, target: Optional[torch.Tensor]):
+                checkpoint_every: int, dtype: str, split: str, kind: str, target: Optional[torch.Tensor],
+                V, mu: float):
         shape = psi0.shape
         nx = [shape[-1]]
         ny = [shape[-2]] if ndim == 2 else None
         lat = Lattice(ndim, nx, ny, g=[float(v) for v in g.detach().cpu()], eps=eps, dtype=dtype, split=split,
                       device=psi0.device if psi0.is_cuda else "cuda:0")
+        if V is not None or mu != 0.0:
+            lat.set_potential(V, mu)
         lat.set_psi([psi0.detach()])
         ckpt = lat.forward_record(nsteps, checkpoint_every)
         value, lam, dg_explicit = lat.objective_grad(kind, [target.detach()] if target is not None else None)
@@ -45,13 +48,15 @@ class QLGObjective(torch.autograd.Function):
         go = grad_out.to(torch.float64)
         dpsi = (go.to(dpsi.device) * dpsi).to(ctx.psi_dtype).to(ctx.psi_device)
         lat.close()
-        return dpsi, go.to(dgt.device) * dgt, None, None, None, None, None, None, None, None
+        return dpsi, go.to(dgt.device) * dgt, None, None, None, None, None, None, None, None, None, None
 
 
 def qlg_objective(psi0: torch.Tensor, g: torch.Tensor, *, eps: float, nsteps: int, checkpoint_every: int = 64,
                   dtype: str = "c128", split: str = "interleaved", kind: str = "energy",
-                  target: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """L(psi_T) for psi0 of shape (5, nx) (1D) or (5, ny, nx) (2D); differentiable in psi0 and g."""
+                  target: Optional[torch.Tensor] = None, V=None, mu: float = 0.0) -> torch.Tensor:
+    """L(psi_T) for psi0 of shape (5, nx) (1D) or (5, ny, nx) (2D); differentiable in psi0 and g.
+    V (an array of the spatial shape, or None) and mu add the external and chemical potential
+    (V + mu) psi_m to the equation of motion; they are constants of the derivative."""
     ndim = psi0.dim() - 1
     return QLGObjective.apply(psi0, g, ndim, float(eps), int(nsteps), int(checkpoint_every), dtype, split,
-                              kind, target)
+                              kind, target, V, float(mu))

@@ -77,8 +77,6 @@ qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t c
 qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t K, void* ckpt_dev, size_t ckpt_bytes) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).has_ext)
-    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   if (qlg::ctx_view(ctx).p->ndim == 3)
     return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   qlg::CtxView v = qlg::ctx_view(ctx);
@@ -103,8 +101,6 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
                               double* value_host, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).has_ext)
-    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   if (qlg::ctx_view(ctx).p->ndim == 3)
     return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   if (!lambda_dev || !value_host) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or value pointer is NULL");
@@ -117,7 +113,8 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
   const double meas = std::pow(p.eps, p.ndim);
   hipError_t e;
   if (kind == 0) {
-    e = qlg::launch_energy_grad(p.dtype, p.ndim, cur, lambda_dev, v.geom, p.eps, p.g0, p.g1, p.g2, v.part, v.stream);
+    e = qlg::launch_energy_grad(p.dtype, p.ndim, cur, lambda_dev, v.geom, p.eps, p.g0, p.g1, p.g2, v.ext, v.part,
+                                v.stream);
     if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "energy gradient kernel");
     std::vector<double> part((size_t)nc * 6);
     e = hipMemcpyAsync(part.data(), v.part, part.size() * 8, hipMemcpyDeviceToHost, v.stream);
@@ -149,8 +146,6 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
                             void* work_dev, size_t work_bytes, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).has_ext)
-    return qlg::ctx_fail(ctx, QLG_ERR_STATE, "the adjoint does not support an external or chemical potential");
   if (qlg::ctx_view(ctx).p->ndim == 3)
     return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   const qlg::CtxView v = qlg::ctx_view(ctx);
@@ -202,7 +197,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         if (j == n_in - 1 && k > (plain ? 0 : nsub - 1)) break;   // later links feed nothing recorded
         e = qlg::launch_chain(dt, src, ybuf[yb], has_u ? zbuf(j, plain ? 0 : k) : nullptr, g,
                               first ? -1 : axis_of(kp), qb_of(kp), has_u, theta_u * p.g0, theta_u * p.g1,
-                              theta_u * p.g2 / 5.0, str);
+                              theta_u * p.g2 / 5.0, v.ext, theta_u, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
         src = ybuf[yb];
         yb ^= 1;
@@ -216,13 +211,13 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         } else {
           // kinetic pull-back and self-interaction VJP of substep k in one kernel
           e = qlg::launch_sub_adj(dt, zbuf(j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
-                                  p.g1, p.g2, part + (size_t)3 * k * nchunks, str);
+                                  p.g1, p.g2, v.ext, part + (size_t)3 * k * nchunks, str);
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep kernel");
         }
         lc = 1 - lc;
       }
       if (plain) {
-        e = qlg::launch_sub_vjp(dt, zbuf(j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, part, acc, str);
+        e = qlg::launch_sub_vjp(dt, zbuf(j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
       } else {
         e = qlg::launch_dg_accumulate(part, nsub * nchunks, acc, str);

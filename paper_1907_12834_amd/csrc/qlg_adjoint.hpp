@@ -16,7 +16,7 @@ struct CtxView {
   LaunchGeom geom;
   double* part;             // scratch: >= nchunks * 10 doubles
   double* res;              // scratch: >= nbatch * 16 doubles
-  bool has_ext;             // an external or chemical potential is set (not differentiated)
+  ExtPot ext;               // external and chemical potential (constants of the derivative)
 };
 
 CtxView ctx_view(qlg_ctx* c);

@@ -123,17 +123,27 @@ __device__ __forceinline__ void iprime_site(const cx<T>* __restrict__ in, const 
 //   out <- U(z) (out <- z when !with_u).
 // Successive links walk the substeps "U_k then I'_k" of consecutive steps as
 // "I'_{k-1} then U_k", so every input z of a self-interaction is written once.
+// theta (V + mu) at a site, for a context with an external or chemical potential
+__device__ __forceinline__ double ext_here(const Site& r, const double* pot, double mu, double theta) {
+  return theta * ((pot ? pot[r.d.psi_off / 5 + r.s] : 0.0) + mu);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_chain(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                  cx<T>* __restrict__ rec, LaunchGeom g, int axis, int qb,
-                                                 int with_u, Angles<T> ang) {
+                                                 int with_u, Angles<T> ang, const double* __restrict__ pot,
+                                                 double mu, double theta) {
   const Site r = site_here(g);
   if (!r.ok) return;
   cx<T> a[5], b[5];
   if (axis >= 0) iprime_site(in, r, axis, qb, a, b);
   else load_site(in, r.d, r.s, a, b);
   if (rec) store_site(rec, r.d, r.s, a, b);
-  if (with_u) potential(a, b, ang);
+  if (with_u) {
+    // the same per-site angle as the fused forward kernels: T(theta) T(V + mu)
+    if (pot || mu != 0.0) potential<T, true>(a, b, ang, T(theta) * T((pot ? pot[r.d.psi_off / 5 + r.s] : 0.0) + mu));
+    else potential(a, b, ang);
+  }
   store_site(out, r.d, r.s, a, b);
 }
 
@@ -205,6 +215,7 @@ __device__ __forceinline__ void block_sum3(double v0, double v1, double v2, doub
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z, cx<double>* __restrict__ lam,
                                                    LaunchGeom g, double theta, double g0, double g1, double g2,
+                                                   const double* __restrict__ pot, double mu,
                                                    double* __restrict__ part) {
   const Site r = site_here(g);
   double dg[3] = {0.0, 0.0, 0.0};
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z,
     cx<double> a[5], b[5], la[5], lb[5];
     load_site(z, r.d, r.s, a, b);
     load_site(lam, r.d, r.s, la, lb);
-    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg);
+    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lam, r.d, r.s, la, lb);
   }
   block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
@@ -226,6 +237,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
                                                    const cx<double>* __restrict__ lin,
                                                    cx<double>* __restrict__ lout, LaunchGeom g, int axis, int qb,
                                                    double theta, double g0, double g1, double g2,
+                                                   const double* __restrict__ pot, double mu,
                                                    double* __restrict__ part) {
   const Site r = site_here(g);
   double dg[3] = {0.0, 0.0, 0.0};
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
     iprime_adj_site(lin, r, axis, qb, la, lb);
     cx<double> a[5], b[5];
     load_site(z, r.d, r.s, a, b);
-    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg);
+    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lout, r.d, r.s, la, lb);
   }
   block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
@@ -261,7 +273,8 @@ __global__ __launch_bounds__(kChunk) void k_dg_accumulate(const double* __restri
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict__ st, cx<double>* __restrict__ lam,
                                                        LaunchGeom g, int ndim, double eps, double g0,
-                                                       double g1, double g2, double* __restrict__ part) {
+                                                       double g1, double g2, const double* __restrict__ pot,
+                                                       double mu, double* __restrict__ part) {
   const Site r = site_here(g);
   double e = 0.0, en = 0.0, ef = 0.0, es = 0.0;
   if (r.ok) {
@@ -307,6 +320,7 @@ __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict_
       fm[i + 1] = cf[i] * p[i];
     }
     const cx<double> cpl{0.5 * Fx, -0.5 * Fy}, cmi{0.5 * Fx, 0.5 * Fy};
+    const double vmu = ext_here(r, pot, mu, 1.0);   // V + mu at this site (0 without a potential)
     cx<double> Sp[5];
     {
       cx<double> pc[5];
@@ -316,7 +330,7 @@ __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict_
     }
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      cx<double> h = (g0 * n) * p[m] + g1 * ((Fz * (2 - m)) * p[m] + cpl * fp[m] + cmi * fm[m]);
+      cx<double> h = (g0 * n + vmu) * p[m] + g1 * ((Fz * (2 - m)) * p[m] + cpl * fp[m] + cmi * fm[m]);
       h = h + (g2 / 5.0) * (sig * Sp[m]);
       const cx<double> l = (2.0 * meas) * (ie2 * lap[m] + h);
       const int64_t o = r.d.qb_off + (int64_t)m * r.d.sites + r.s;
@@ -324,7 +338,7 @@ __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict_
       lam[o + 5 * (int64_t)r.d.sites] = l;
     }
     const double f2s = Fx * Fx + Fy * Fy + Fz * Fz, s2 = sig.re * sig.re + sig.im * sig.im;
-    e = ekin * ie2 + 0.5 * (g0 * n * n + g1 * f2s + g2 * s2 / 5.0);
+    e = ekin * ie2 + 0.5 * (g0 * n * n + g1 * f2s + g2 * s2 / 5.0) + vmu * n;
     en = 0.5 * n * n;
     ef = 0.5 * f2s;
     es = 0.1 * s2;
@@ -395,14 +409,16 @@ __global__ __launch_bounds__(kChunk) void k_fid_grad(const cx<T>* __restrict__ t
 #define QLG_GRID dim3(g.nchunks), dim3(kChunk), 0, st
 
 hipError_t launch_chain(int dtype, const void* in, void* out, void* rec, const LaunchGeom& g, int axis, int qb,
-                        bool with_u, double tg0, double tg1, double tg25, hipStream_t st) {
+                        bool with_u, double tg0, double tg1, double tg25, const ExtPot& ext, double theta,
+                        hipStream_t st) {
   if (g.nchunks == 0) return hipSuccess;
   if (dtype == 0)
     hipLaunchKernelGGL(k_chain<float>, QLG_GRID, (const cx<float>*)in, (cx<float>*)out, (cx<float>*)rec, g, axis,
-                       qb, with_u ? 1 : 0, Angles<float>{(float)tg0, (float)tg1, (float)tg25});
+                       qb, with_u ? 1 : 0, Angles<float>{(float)tg0, (float)tg1, (float)tg25}, ext.V, ext.mu,
+                       theta);
   else
     hipLaunchKernelGGL(k_chain<double>, QLG_GRID, (const cx<double>*)in, (cx<double>*)out, (cx<double>*)rec, g,
-                       axis, qb, with_u ? 1 : 0, Angles<double>{tg0, tg1, tg25});
+                       axis, qb, with_u ? 1 : 0, Angles<double>{tg0, tg1, tg25}, ext.V, ext.mu, theta);
   return hipGetLastError();
 }
 
@@ -412,13 +428,13 @@ hipError_t launch_sub_iprime_adj(const void* in, void* out, const LaunchGeom& g,
 }
 
 hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom& g, double theta, double g0,
-                          double g1, double g2, double* part, double* acc, hipStream_t st) {
+                          double g1, double g2, const ExtPot& ext, double* part, double* acc, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_sub_vjp<float>, QLG_GRID, (const cx<float>*)z, (cx<double>*)lam, g, theta, g0, g1, g2,
-                       part);
+                       ext.V, ext.mu, part);
   else
     hipLaunchKernelGGL(k_sub_vjp<double>, QLG_GRID, (const cx<double>*)z, (cx<double>*)lam, g, theta, g0, g1,
-                       g2, part);
+                       g2, ext.V, ext.mu, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, (const double*)part, g.nchunks, acc);
@@ -426,14 +442,15 @@ hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom&
 }
 
 hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* lam_out, const LaunchGeom& g, int axis,
-                          int qb, double theta, double g0, double g1, double g2, double* part, hipStream_t st) {
+                          int qb, double theta, double g0, double g1, double g2, const ExtPot& ext, double* part,
+                          hipStream_t st) {
   if (g.nchunks == 0) return hipSuccess;
   if (dtype == 0)
     hipLaunchKernelGGL(k_sub_adj<float>, QLG_GRID, (const cx<float>*)z, (const cx<double>*)lam_in,
-                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, part);
+                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, ext.V, ext.mu, part);
   else
     hipLaunchKernelGGL(k_sub_adj<double>, QLG_GRID, (const cx<double>*)z, (const cx<double>*)lam_in,
-                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, part);
+                       (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, ext.V, ext.mu, part);
   return hipGetLastError();
 }
 
@@ -443,13 +460,13 @@ hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hip
 }
 
 hipError_t launch_energy_grad(int dtype, int ndim, const void* state, void* lam, const LaunchGeom& g, double eps,
-                              double g0, double g1, double g2, double* part, hipStream_t st) {
+                              double g0, double g1, double g2, const ExtPot& ext, double* part, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_energy_grad<float>, QLG_GRID, (const cx<float>*)state, (cx<double>*)lam, g, ndim, eps,
-                       g0, g1, g2, part);
+                       g0, g1, g2, ext.V, ext.mu, part);
   else
     hipLaunchKernelGGL(k_energy_grad<double>, QLG_GRID, (const cx<double>*)state, (cx<double>*)lam, g, ndim,
-                       eps, g0, g1, g2, part);
+                       eps, g0, g1, g2, ext.V, ext.mu, part);
   return hipGetLastError();
 }
 

@@ -807,7 +807,7 @@ CtxView ctx_view(qlg_ctx* c) {
   v.geom = c->geom();
   v.part = c->sc(c->S.obs_part);
   v.res = c->sc(c->S.obs_res);
-  v.has_ext = c->ext.on();
+  v.ext = c->ext;
   return v;
 }
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg) { return fail(c, s, msg); }

@@ -4,6 +4,7 @@
 // Forward (qlg_math.hpp): for x in {a, b},
 //   y1_x = P x = x + c(n) (v^H x) v,        c(n) = (e^{-i kappa n} - 1)/n, kappa = theta g2/5,
 //   y_x  = e^{-i theta g0 n} R(F) y1_x,      R = exp(-i tau F.f), tau = theta g1,
+// (times e^{-i ext} with ext = theta (V + mu) when the equation carries a potential),
 // with psi = a + b, n = |psi|^2, F_nu = psi^H f_nu psi, v = S psi* (all frozen
 // at the input).  Cotangents follow lambda = dL/dRe z + i dL/dIm z, so for a
 // complex-linear map y = M z the pull-back is lambda_z = M^H lambda_y.
@@ -58,8 +59,11 @@ QLG_HD DMat dmat(const UFrame& f) {
                {f.d2m2, -f.d2m1, f.d20, -f.d21, f.d22}}};
 }
 
+// ext: theta (V + mu) of a psi-independent term (V(x) + mu) psi_m in the equation of
+// motion; it joins the density phase phi0 and, not depending on psi, adds nothing
+// to the derivatives with respect to n, F or the couplings.
 QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double theta, double g0,
-                    double g1, double g2, UFrame& f) {
+                    double g1, double g2, UFrame& f, double ext = 0.0) {
   const double r6 = Consts::r6, r32 = Consts::r32, r38 = Consts::r38;
   double q[5];
   for (int m = 0; m < 5; ++m) {
@@ -75,7 +79,7 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
   const double Fp2 = f.Fx * f.Fx + f.Fy * f.Fy;
   f.Fperp = sqrt(Fp2);
   f.Fn = sqrt(Fp2 + f.Fz * f.Fz);
-  f.phi0 = theta * g0 * f.n;
+  f.phi0 = theta * g0 * f.n + ext;
   f.phi = theta * g1 * f.Fn;
   for (int i = 0; i < 5; ++i) {
     const double m = 2 - i;
@@ -181,9 +185,10 @@ QLG_HD cx<double> dc_dn(double kappa, double n) {
 // In: a, b (input of U), la, lb (cotangents of U's outputs).
 // Out: la, lb replaced by cotangents of a, b; dg[0..2] incremented.
 QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx<double> (&la)[5],
-                          cx<double> (&lb)[5], double theta, double g0, double g1, double g2, double (&dg)[3]) {
+                          cx<double> (&lb)[5], double theta, double g0, double g1, double g2, double (&dg)[3],
+                          double ext = 0.0) {
   UFrame f;
-  u_frame(a, b, theta, g0, g1, g2, f);
+  u_frame(a, b, theta, g0, g1, g2, f, ext);
   const double tau = theta * g1;
   cx<double> v[5];
   {

@@ -24,31 +24,32 @@ def objective(*args, **kw):
     return qlg_objective(*args, **kw)
 
 
-def oracle_grad(psi0, g, eps, nsteps, split="interleaved", kind="energy", target=None):
+def oracle_grad(psi0, g, eps, nsteps, split="interleaved", kind="energy", target=None, V=None, mu=0.0):
     p = torch.from_numpy(np.ascontiguousarray(psi0)).clone().requires_grad_(True)
     gt = torch.tensor(g, dtype=torch.float64, requires_grad=True)
     gg = (gt[0], gt[1], gt[2])
     a, b = O.encode(p)
-    a, b = O.run(a, b, nsteps, eps, gg, p.dim() - 1, split)
+    a, b = O.run(a, b, nsteps, eps, gg, p.dim() - 1, split, V=V, mu=mu)
     psi = a + b
     if kind == "energy":
-        L = O.energy(psi, eps, gg)
+        L = O.energy(psi, eps, gg, V, mu)
     else:
         t = torch.from_numpy(target)
         meas = eps ** (p.dim() - 1)
         L = (meas * (t.conj() * psi).sum()).abs() ** 2
     L.backward()
-    return float(L), p.grad.numpy(), gt.grad.numpy()
+    return float(L.detach()), p.grad.numpy(), gt.grad.numpy()
 
 
-def gpu_grad(psi0, g, eps, nsteps, K=4, dtype="c128", split="interleaved", kind="energy", target=None):
+def gpu_grad(psi0, g, eps, nsteps, K=4, dtype="c128", split="interleaved", kind="energy", target=None, V=None,
+             mu=0.0):
     dev = "cuda:0"
     cdt = torch.complex64 if dtype == "c64" else torch.complex128
     p = torch.from_numpy(psi0).to(dev, cdt).requires_grad_(True)
     gt = torch.tensor(g, dtype=torch.float64, requires_grad=True)
     tg = torch.from_numpy(target).to(dev, cdt) if target is not None else None
     L = objective(p, gt, eps=eps, nsteps=nsteps, checkpoint_every=K, dtype=dtype, split=split, kind=kind,
-                  target=tg)
+                  target=tg, V=V, mu=mu)
     L.backward()
     return float(L), p.grad.detach().cpu().numpy().astype(np.complex128), gt.grad.numpy()
 
@@ -70,6 +71,27 @@ def test_energy_gradient_matches_oracle_autograd(shape, split):
     assert abs(L1 - L0) <= 1e-12 * abs(L0)
     assert rel(gp1, gp0) <= 1e-10, rel(gp1, gp0)
     assert rel(gg1, gg0) <= 1e-10, (gg1, gg0)
+
+
+@pytest.mark.parametrize("kind", ["energy", "fidelity"])
+@pytest.mark.parametrize("split", ["interleaved", "plain"])
+@pytest.mark.parametrize("shape", [(40,), (8, 10)])
+def test_gradient_with_potential_matches_oracle_autograd(shape, split, kind):
+    """An external potential V(x) and a chemical potential mu in the run (Sec. II "Additional terms"):
+    the reverse sweep differentiates U with its (V + mu) phase, and the energy objective includes
+    eps^d sum (V + mu) n."""
+    psi0 = qi.random_field(shape, seed=45, scale=0.4)
+    target = qi.random_field(shape, seed=46, scale=0.3) if kind == "fidelity" else None
+    V = np.random.default_rng(47).uniform(0.0, 2.5, size=shape)
+    eps, nsteps, mu = 0.3, 9, 0.7
+    L0, gp0, gg0 = oracle_grad(psi0, G, eps, nsteps, split, kind, target, V=V, mu=mu)
+    L1, gp1, gg1 = gpu_grad(psi0, G, eps, nsteps, K=4, split=split, kind=kind, target=target, V=V, mu=mu)
+    assert abs(L1 - L0) <= 1e-12 * abs(L0), (L1, L0)
+    assert rel(gp1, gp0) <= 1e-10, rel(gp1, gp0)
+    assert rel(gg1, gg0) <= 1e-10, (gg1, gg0)
+    # the potential changes the gradient (it is not silently ignored)
+    _, gp2, _ = oracle_grad(psi0, G, eps, nsteps, split, kind, target)
+    assert rel(gp2, gp0) > 1e-3
 
 
 def test_fidelity_gradient_matches_oracle_autograd():

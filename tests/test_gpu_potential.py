@@ -6,8 +6,8 @@ ragged 1D and 2D lattices in every launch plan (1D: one- and two-wave tiles,
 1..7 steps per pass; 2D: several band heights), both splits, batches of
 instances with their own potentials; the energy observable with the (V + mu) n
 term; harmonic-trap physics on the GPU; removal of the potential restoring the
-plain kernels bit for bit; graph replay and potentials whose values change
-between calls; and the adjoint's refusal while a potential is set.
+plain kernels bit for bit; and graph replay and potentials whose values change
+between calls.  (Gradients with a potential: tests/test_gpu_adjoint.py.)
 """
 import numpy as np
 import pytest
@@ -191,19 +191,6 @@ def test_graph_replay_and_changing_values():
     A, B = O.run_psi(psi.numpy(), 8, eps, g, V=V1, mu=0.2)
     A, B = O.run(A, B, 4, eps, g, 2, V=V2, mu=0.2)
     assert rel_l2(res[0], np.stack([A.numpy(), B.numpy()])) <= 1e-12
-
-
-def test_adjoint_refuses_while_a_potential_is_set():
-    from paper_1907_12834_amd.qlg import QLGError
-    lat = lattice(1, [64], g=(1.0, -0.3, 0.5), eps=0.3, dtype="c128")
-    lat.set_psi([torch.from_numpy(qi.random_field((64,), seed=1))])
-    lat.set_potential(None, 0.5)
-    with pytest.raises(QLGError, match="QLG_ERR_STATE"):
-        lat.forward_record(4, 2)
-    with pytest.raises(QLGError, match="QLG_ERR_STATE"):
-        lat.objective_grad("energy")
-    lat.set_potential(None, 0.0)
-    lat.forward_record(4, 2)                         # usable again without a potential
 
 
 def test_set_potential_argument_errors():
