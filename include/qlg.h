@@ -239,8 +239,6 @@ qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_h
 /* ---------------------------------------------------------------------------
  * Adjoint (reverse-mode derivative of a final-state objective).
  *
- * 1D and 2D lattices only (QLG_ERR_SHAPE for ndim == 3).
- *
  * Cotangents use the convention lambda = dL/dRe z + i dL/dIm z for every
  * complex amplitude z (so d|z|^2 has cotangent 2 z).  Adjoint vectors are
  * complex128 in the qubits layout, whatever the forward dtype; the

@@ -23,8 +23,9 @@ class QLGObjective(torch.autograd.Function):
                 V, mu: float):
         shape = psi0.shape
         nx = [shape[-1]]
-        ny = [shape[-2]] if ndim == 2 else None
-        lat = Lattice(ndim, nx, ny, g=[float(v) for v in g.detach().cpu()], eps=eps, dtype=dtype, split=split,
+        ny = [shape[-2]] if ndim >= 2 else None
+        nz = [shape[-3]] if ndim == 3 else None
+        lat = Lattice(ndim, nx, ny, nz, g=[float(v) for v in g.detach().cpu()], eps=eps, dtype=dtype, split=split,
                       device=psi0.device if psi0.is_cuda else "cuda:0")
         if V is not None or mu != 0.0:
             lat.set_potential(V, mu)
@@ -54,7 +55,7 @@ class QLGObjective(torch.autograd.Function):
 def qlg_objective(psi0: torch.Tensor, g: torch.Tensor, *, eps: float, nsteps: int, checkpoint_every: int = 64,
                   dtype: str = "c128", split: str = "interleaved", kind: str = "energy",
                   target: Optional[torch.Tensor] = None, V=None, mu: float = 0.0) -> torch.Tensor:
-    """L(psi_T) for psi0 of shape (5, nx) (1D) or (5, ny, nx) (2D); differentiable in psi0 and g.
+    """L(psi_T) for psi0 of shape (5, nx), (5, ny, nx) or (5, nz, ny, nx); differentiable in psi0 and g.
     V (an array of the spatial shape, or None) and mu add the external and chemical potential
     (V + mu) psi_m to the equation of motion; they are constants of the derivative."""
     ndim = psi0.dim() - 1

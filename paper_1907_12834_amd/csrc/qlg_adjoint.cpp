@@ -33,7 +33,6 @@ struct Sizes {
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
 qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
-  if (p && p->ndim == 3) return QLG_ERR_SHAPE;   // the adjoint covers 1D and 2D lattices
   if (nsteps < 0 || K < 1) return QLG_ERR_ARG;
   size_t state_bytes = 0, scratch_bytes = 0;
   qlg_status st = qlg_query_sizes(p, &state_bytes, &scratch_bytes);
@@ -77,8 +76,6 @@ qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t c
 qlg_status qlg_forward_record(qlg_ctx* ctx, int64_t nsteps, int32_t K, void* ckpt_dev, size_t ckpt_bytes) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).p->ndim == 3)
-    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   qlg::CtxView v = qlg::ctx_view(ctx);
   Sizes s;
   qlg_status st = sizes_for(v.p, nsteps, K, &s);
@@ -101,8 +98,6 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
                               double* value_host, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).p->ndim == 3)
-    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   if (!lambda_dev || !value_host) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or value pointer is NULL");
   if (kind != 0 && kind != 1) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "kind must be 0 (energy) or 1 (fidelity)");
   if (kind == 1 && !target_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "fidelity needs a target");
@@ -146,8 +141,6 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
                             void* work_dev, size_t work_bytes, double* dg_host) {
   if (!ctx) return QLG_ERR_ARG;
   if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
-  if (qlg::ctx_view(ctx).p->ndim == 3)
-    return qlg::ctx_fail(ctx, QLG_ERR_SHAPE, "the adjoint supports 1D and 2D lattices");
   const qlg::CtxView v = qlg::ctx_view(ctx);
   const qlg_params& p = *v.p;
   Sizes s;
@@ -173,7 +166,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   const bool plain = p.split == QLG_SPLIT_PLAIN;
   const double theta = p.eps * p.eps / (4.0 * nd);
   const double theta_u = plain ? p.eps * p.eps : theta;
-  auto axis_of = [&](int k) { return nd == 1 ? 0 : (k < 4 ? 1 : 0); };
+  // substep k of a step acts along z, y, x in that order (the last axis of each dimension first)
+  auto axis_of = [&](int k) { return nd - 1 - k / 4; };
   auto qb_of = [&](int k) { return (k % 4) < 2 ? 1 : 0; };
   auto zbuf = [&](int64_t j, int r) { return zrec + ((size_t)j * nrec + r) * s.copy; };
 

@@ -21,7 +21,7 @@ namespace {
 
 struct Site {
   InstDesc d;
-  int s, x, y;
+  int s, x, y, z;
   bool ok;
 };
 
@@ -32,20 +32,19 @@ __device__ __forceinline__ Site site_here(const LaunchGeom& g) {
   r.s = (c - r.d.chunk_begin) * kChunk + threadIdx.x;
   r.ok = r.s < r.d.sites;
   r.x = r.ok ? r.s % r.d.nx : 0;
-  r.y = r.ok ? r.s / r.d.nx : 0;
+  r.y = r.ok ? (r.s / r.d.nx) % r.d.ny : 0;
+  r.z = r.ok ? r.s / (r.d.nx * r.d.ny) : 0;
   return r;
 }
 
-// site index of the neighbour at offset dir (+1 / -1) along axis (0 = x, 1 = y), periodic
+// site index of the neighbour at offset dir (+1 / -1) along axis (0 = x, 1 = y, 2 = z), periodic
 __device__ __forceinline__ int neighbour(const Site& r, int axis, int dir) {
-  if (axis == 0) {
-    int x = r.x + dir;
-    x = x < 0 ? x + r.d.nx : (x >= r.d.nx ? x - r.d.nx : x);
-    return r.y * r.d.nx + x;
-  }
-  int y = r.y + dir;
-  y = y < 0 ? y + r.d.ny : (y >= r.d.ny ? y - r.d.ny : y);
-  return y * r.d.nx + r.x;
+  const int n = axis == 0 ? r.d.nx : axis == 1 ? r.d.ny : r.d.nz;
+  const int stride = axis == 0 ? 1 : axis == 1 ? r.d.nx : r.d.nx * r.d.ny;
+  const int c = axis == 0 ? r.x : axis == 1 ? r.y : r.z;
+  int v = c + dir;
+  v = v < 0 ? v + n : (v >= n ? v - n : v);
+  return r.s + (v - c) * stride;
 }
 
 template <typename T, typename S>
@@ -278,7 +277,7 @@ __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict_
   const Site r = site_here(g);
   double e = 0.0, en = 0.0, ef = 0.0, es = 0.0;
   if (r.ok) {
-    const double meas = ndim == 1 ? eps : eps * eps;
+    const double meas = ndim == 1 ? eps : ndim == 2 ? eps * eps : eps * eps * eps;
     const double ie2 = 1.0 / (eps * eps);
     cx<double> a[5], b[5], p[5], lap[5];
     load_site(st, r.d, r.s, a, b);

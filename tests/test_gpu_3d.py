@@ -180,8 +180,6 @@ def test_3d_calls_that_need_a_lower_dimension():
     lat.set_psi([torch.from_numpy(qi.random_field((4, 5, 6), seed=2))])
     with pytest.raises(QLGError, match="QLG_ERR_SHAPE"):
         lat.vorticity(0)
-    with pytest.raises(QLGError, match="QLG_ERR_SHAPE"):
-        lat.forward_record(2, 1)
     f = lat.fields(("n",))[0]["n"]
     assert f.shape == (4, 5, 6)
     ref = (np.abs(lat.get_psi()[0].cpu().numpy()) ** 2).sum(0)
