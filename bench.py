@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per site-update (derivation in DESIGN.md, "Work per site-update").
+# Algorithmic work per site-update, counted from the per-site formulas.
 # Flops count add/sub/mul as 1 and fma as 2 in the per-site formulas of
 # qlg_math.hpp; the three sincos, two square roots and five divisions of each
 # self-interaction are not counted.
@@ -121,10 +121,10 @@ WORKLOADS = {
 def workload_input(name, steps):
     import qlg_inputs as qi
     if name == "1d_two_soliton_scattering":
-        return qi.c2_two_solitons(nsteps=steps)
+        return qi.two_solitons_1d_L16384(nsteps=steps)
     if name == "2d_vortex_pair":
-        return qi.c3_vortex_pair(nsteps=steps)
-    return qi.c6_vortex_lines(nsteps=steps)
+        return qi.vortex_pair_2d_2048(nsteps=steps)
+    return qi.vortex_lines_3d_256(nsteps=steps)
 
 
 def workload_lattice(w, ndim, dtype, split="interleaved"):
@@ -249,7 +249,7 @@ def batched_ratio(steps):
     import qlg_inputs as qi
     from paper_1907_12834_amd.qlg import Lattice
 
-    wb = qi.c4_batched(nsteps=steps)
+    wb = qi.batched_two_solitons_1d_256(nsteps=steps)
     psis = [torch.from_numpy(p) for p in wb.psi]
     lat = Lattice(1, wb.nx, g=wb.g, eps=wb.eps, dtype="c64")
     lat.set_psi(psis)
@@ -285,7 +285,7 @@ def adjoint_ratio(steps, K):
     import qlg_inputs as qi
     from paper_1907_12834_amd.qlg import Lattice
 
-    w = qi.c5_adjoint(nsteps=steps, checkpoint_every=K)
+    w = qi.adjoint_vortex_pair_2d_512(nsteps=steps, checkpoint_every=K)
     psi = torch.from_numpy(w.psi[0])
     lat = Lattice(2, w.nx, w.ny, g=w.g, eps=w.eps, dtype="c64")
     lat.set_psi([psi])

@@ -26,7 +26,7 @@ the paper (Taylor, Smith, Yepez, arXiv:1907.12834):
   winding numbers (Sec. VI, "Calculating quantum vorticity on a lattice").
 
 The paper defers C, S and U to earlier work, so the definitions below are
-readings (each listed in the design doc with its evidence):
+readings, each pinned by the tests of this oracle:
 
 * C is the sqrt(SWAP) gate [[alpha, beta], [beta, alpha]] with
   alpha = (1 - i)/2, beta = (1 + i)/2 acting on the qubit pair (a_m, b_m) of

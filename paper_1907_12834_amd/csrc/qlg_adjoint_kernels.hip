@@ -39,12 +39,20 @@ __device__ __forceinline__ Site site_here(const LaunchGeom& g) {
 
 // site index of the neighbour at offset dir (+1 / -1) along axis (0 = x, 1 = y, 2 = z), periodic
 __device__ __forceinline__ int neighbour(const Site& r, int axis, int dir) {
-  const int n = axis == 0 ? r.d.nx : axis == 1 ? r.d.ny : r.d.nz;
-  const int stride = axis == 0 ? 1 : axis == 1 ? r.d.nx : r.d.nx * r.d.ny;
-  const int c = axis == 0 ? r.x : axis == 1 ? r.y : r.z;
-  int v = c + dir;
-  v = v < 0 ? v + n : (v >= n ? v - n : v);
-  return r.s + (v - c) * stride;
+  // one branch per axis: selecting the extent by a run-time axis index puts them on the stack
+  if (axis == 0) {
+    int x = r.x + dir;
+    x = x < 0 ? x + r.d.nx : (x >= r.d.nx ? x - r.d.nx : x);
+    return r.s - r.x + x;
+  }
+  if (axis == 1) {
+    int y = r.y + dir;
+    y = y < 0 ? y + r.d.ny : (y >= r.d.ny ? y - r.d.ny : y);
+    return r.s + (y - r.y) * r.d.nx;
+  }
+  int z = r.z + dir;
+  z = z < 0 ? z + r.d.nz : (z >= r.d.nz ? z - r.d.nz : z);
+  return r.s + (z - r.z) * r.d.nx * r.d.ny;
 }
 
 template <typename T, typename S>

@@ -211,7 +211,7 @@ class Workload:
                                                       if len(self.nz) == 1 else self.nz)))
 
 
-def c1_single_bright(L: int = 1024, width: float = 32.0, eps: float = 0.1, seed: int = 1907,
+def single_bright_1d_L1024(L: int = 1024, width: float = 32.0, eps: float = 0.1, seed: int = 1907,
                      nsteps: int = 1000) -> Workload:
     """1D periodic lattice, one stationary bright soliton with seeded weights, int n = 1."""
     rng = np.random.default_rng(seed)
@@ -229,7 +229,7 @@ def two_solitons_1d(L: int, width: float, k: float, rng: np.random.Generator, ep
     return left + right * np.exp(1j * rel_phase)
 
 
-def c2_two_solitons(L: int = 16384, width: float = 48.0, k: float = 0.05 * math.pi,
+def two_solitons_1d_L16384(L: int = 16384, width: float = 48.0, k: float = 0.05 * math.pi,
                     c1: float = -0.5, eps: float = 0.1, seed: int = 12834,
                     nsteps: int = 20000, rel_phase: float = 0.0) -> Workload:
     rng = np.random.default_rng(seed)
@@ -256,7 +256,7 @@ def vortex_pair_2d(nx: int, ny: int, sep: float, eps: float, rng: np.random.Gene
     return psi
 
 
-def c3_vortex_pair(n: int = 2048, sep: float = 128.0, eps: float = 0.1, seed: int = 2019,
+def vortex_pair_2d_2048(n: int = 2048, sep: float = 128.0, eps: float = 0.1, seed: int = 2019,
                    nsteps: int = 10000) -> Workload:
     rng = np.random.default_rng(seed)
     psi = vortex_pair_2d(n, n, sep, eps, rng)
@@ -264,7 +264,7 @@ def c3_vortex_pair(n: int = 2048, sep: float = 128.0, eps: float = 0.1, seed: in
                     nsteps, {"sep": sep, "seed": seed})
 
 
-def c4_batched(nbatch: int = 256, seed: int = 4, eps: float = 0.1, nsteps: int = 5000,
+def batched_two_solitons_1d_256(nbatch: int = 256, seed: int = 4, eps: float = 0.1, nsteps: int = 5000,
                lmax_units: int = 16, unit: int = 1024) -> Workload:
     """Independent 1D two-soliton scattering runs of uneven size.
 
@@ -279,7 +279,7 @@ def c4_batched(nbatch: int = 256, seed: int = 4, eps: float = 0.1, nsteps: int =
                     nsteps, {"seed": seed, "k": ks.tolist(), "width": ws.tolist()})
 
 
-def c5_adjoint(n: int = 512, sep: float = 128.0, eps: float = 0.1, seed: int = 2019,
+def adjoint_vortex_pair_2d_512(n: int = 512, sep: float = 128.0, eps: float = 0.1, seed: int = 2019,
                nsteps: int = 2000, checkpoint_every: int = 64) -> Workload:
     rng = np.random.default_rng(seed)
     psi = vortex_pair_2d(n, n, sep, eps, rng)
@@ -307,7 +307,7 @@ def vortex_lines_3d(n: int, sep: float, eps: float, rng: np.random.Generator, am
     return psi
 
 
-def c6_vortex_lines(n: int = 256, sep: float = 64.0, eps: float = 0.1, seed: int = 2020,
+def vortex_lines_3d_256(n: int = 256, sep: float = 64.0, eps: float = 0.1, seed: int = 2020,
                     nsteps: int = 1000) -> Workload:
     rng = np.random.default_rng(seed)
     psi = vortex_lines_3d(n, sep, eps, rng)

@@ -1,14 +1,14 @@
 """Write the oracle's state of the 1D two-soliton workload after its full length.
 
 The 1D two-soliton scattering workload (L = 16384, eps = 0.1, g = (1, -0.5, 0.5),
-interleaved split, seeded initial field from `qlg_inputs.c2_two_solitons`) is run
+interleaved split, seeded initial field from `qlg_inputs.two_solitons_1d_L16384`) is run
 for 20000 steps by the FP64 CPU oracle alone; psi = a + b after 2000 and after
-20000 steps is stored in `c2_oracle_psi.npz` (arrays `psi_2000`, `psi_20000`,
+20000 steps is stored in `two_solitons_L16384_oracle_psi.npz` (arrays `psi_2000`, `psi_20000`,
 complex128, shape (5, 16384)), together with the parameters used.
 
 Usage (from the repository root; about 20 minutes on 8 CPU threads):
 
-    python tests/golden/make_c2_reference.py
+    python tests/golden/make_two_solitons_reference.py
 """
 import os
 import sys
@@ -23,12 +23,12 @@ sys.path.insert(0, ROOT)
 import qlg_inputs as qi  # noqa: E402
 from oracle import qlg_oracle as O  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_psi.npz")
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "two_solitons_L16384_oracle_psi.npz")
 SAVE_AT = (2000, 20000)
 
 
 def main():
-    w = qi.c2_two_solitons()
+    w = qi.two_solitons_1d_L16384()
     assert w.nsteps == SAVE_AT[-1]
     p = torch.from_numpy(np.ascontiguousarray(w.psi[0])).to(torch.complex128)
     a, b = O.encode(p)

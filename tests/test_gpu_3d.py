@@ -151,7 +151,7 @@ def test_3d_graph_replay_and_autotune_keep_results():
 def test_3d_vortex_lines_full_size_light_cone():
     """The 256^3 vortex-line workload (complex64) after 3 steps in the autotuned plan: sampled
     sites against the oracle on periodic light-cone windows (radius 4 per step per axis)."""
-    w = qi.c6_vortex_lines(nsteps=3)
+    w = qi.vortex_lines_3d_256(nsteps=3)
     n = w.nx[0]
     lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype="c64")
     lat.set_psi([torch.from_numpy(w.psi[0])])

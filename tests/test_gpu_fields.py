@@ -131,7 +131,7 @@ def test_vorticity_random_ragged_batch(dtype):
 def test_vorticity_c3_full_size():
     """The 2048^2 vortex-pair workload (complex64) after 20 steps: omega and windings of the three
     occupied components over the whole lattice; each keeps its single core (+1 in m = +-2, -1 in m = 0)."""
-    w = qi.c3_vortex_pair(nsteps=20)
+    w = qi.vortex_pair_2d_2048(nsteps=20)
     lat = lattice(2, w.nx, w.ny, g=w.g, eps=w.eps, dtype="c64")
     lat.set_psi([torch.from_numpy(w.psi[0])])
     lat.autotune()

@@ -32,9 +32,9 @@ def qubits_tensor(a, b):
 # ---------------------------------------------------------------------------
 # 1D
 # ---------------------------------------------------------------------------
-def test_c1_full_fp64_1000_steps():
+def test_single_bright_L1024_fp64_1000_steps():
     """1D L=1024 bright soliton, complex128, 1000 steps: rel-L2 <= 1e-12, N_q to 1e-12."""
-    w = qi.c1_single_bright()
+    w = qi.single_bright_1d_L1024()
     lat = lattice(1, [1024], g=w.g, eps=w.eps, dtype="c128")
     lat.set_psi([torch.from_numpy(w.psi[0])])
     obs0 = lat.observables()[0]
@@ -43,7 +43,7 @@ def test_c1_full_fp64_1000_steps():
     a, b = oracle_psi(w.psi[0], w.nsteps, w.eps, w.g)
     err = rel_l2(got, np.stack([a, b]))
     obs = lat.observables()[0]
-    print("C1 fp64 rel-L2 after 1000 steps: %.3e" % err)
+    print("single bright L=1024 fp64 rel-L2 after 1000 steps: %.3e" % err)
     assert err <= 1e-12
     assert abs(obs["norm_q"] / obs0["norm_q"] - 1) <= 1e-12
 
@@ -95,9 +95,9 @@ def test_1d_zero_steps_and_empty_field():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_c2_two_solitons_reduced(dtype):
+def test_two_solitons_reduced(dtype):
     """1D L=16384 two-soliton scattering workload, 100 steps, whole lattice vs the oracle."""
-    w = qi.c2_two_solitons(nsteps=100)
+    w = qi.two_solitons_1d_L16384(nsteps=100)
     lat = lattice(1, [w.nx[0]], g=w.g, eps=w.eps, dtype=dtype)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     o0 = lat.observables()[0]
@@ -107,20 +107,21 @@ def test_c2_two_solitons_reduced(dtype):
     err = rel_l2(got, a + b)
     o1 = lat.observables()[0]
     drift = abs(o1["norm_q"] / o0["norm_q"] - 1)
-    print("C2 %s rel-L2 %.3e drift %.3e" % (dtype, err, drift))
+    print("two solitons L=16384 %s rel-L2 %.3e drift %.3e" % (dtype, err, drift))
     assert err <= TOL[dtype]
     assert drift <= (1e-12 if dtype == "c128" else 1e-5)
 
 
-C2_REFERENCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_psi.npz")
+TWO_SOLITONS_REFERENCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "two_solitons_L16384_oracle_psi.npz")
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_c2_parity_at_stated_lengths(dtype):
+def test_two_solitons_L16384_parity_at_stated_lengths(dtype):
     """The two-soliton workload in the autotuned launch plan, against the oracle's own states after
-    2000 and 20000 steps (written by tests/golden/make_c2_reference.py from the oracle alone)."""
-    ref = np.load(C2_REFERENCE)
-    w = qi.c2_two_solitons()
+    2000 and 20000 steps (written by tests/golden/make_two_solitons_reference.py from the oracle alone)."""
+    ref = np.load(TWO_SOLITONS_REFERENCE)
+    w = qi.two_solitons_1d_L16384()
     assert int(ref["L"]) == w.nx[0] and float(ref["eps"]) == w.eps and tuple(ref["g"]) == tuple(w.g)
     lat = lattice(1, [w.nx[0]], g=w.g, eps=w.eps, dtype=dtype)
     lat.autotune()
@@ -134,15 +135,15 @@ def test_c2_parity_at_stated_lengths(dtype):
         got = lat.get_psi()[0].cpu().numpy()
         err = rel_l2(got, ref["psi_%d" % n])
         drift = max(abs(o["norm_q"] / o0["norm_q"] - 1) for (o,) in trace)
-        print("C2 %s plan %s: %d steps rel-L2 %.3e, worst norm drift %.3e" % (dtype, lat.tuning(), n, err, drift))
+        print("two solitons L=16384 %s plan %s: %d steps rel-L2 %.3e, worst norm drift %.3e" % (dtype, lat.tuning(), n, err, drift))
         assert err <= TOL[dtype], (n, err)
         assert drift <= (1e-11 if dtype == "c128" else 1e-5), (n, drift)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_c2_full_length_invariants(dtype):
-    """Full C2 length (20000 steps) on the GPU: qubit norm and energy are tracked every 100 steps."""
-    w = qi.c2_two_solitons()
+def test_two_solitons_L16384_full_length_invariants(dtype):
+    """The full length of the L = 16384 two-soliton run (20000 steps) on the GPU: qubit norm and energy are tracked every 100 steps."""
+    w = qi.two_solitons_1d_L16384()
     lat = lattice(1, [w.nx[0]], g=w.g, eps=w.eps, dtype=dtype)
     lat.autotune()
     lat.set_psi([torch.from_numpy(w.psi[0])])
@@ -154,16 +155,16 @@ def test_c2_full_length_invariants(dtype):
         o = lat.observables()[0]
         worst = max(worst, abs(o["norm_q"] / o0["norm_q"] - 1))
         energies.append(o["energy"])
-    print("C2 %s 20000 steps: worst norm drift %.3e, energy %.6f -> %.6f" %
+    print("two solitons L=16384 %s 20000 steps: worst norm drift %.3e, energy %.6f -> %.6f" %
           (dtype, worst, o0["energy"], energies[-1]))
     assert worst <= (1e-11 if dtype == "c128" else 1e-5)
     assert all(math.isfinite(e) for e in energies)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_c2_full_size_light_cone_samples(dtype):
+def test_two_solitons_L16384_light_cone_samples(dtype):
     """Full-size lattice in the autotuned launch configuration, sampled sites vs light-cone oracle."""
-    w = qi.c2_two_solitons()
+    w = qi.two_solitons_1d_L16384()
     nsteps = 40
     lat = lattice(1, [w.nx[0]], g=w.g, eps=w.eps, dtype=dtype)
     lat.autotune()
@@ -279,7 +280,7 @@ def test_2d_random_qubits(dtype, split, shape, rows):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_c3_vortex_pair_reduced(dtype):
+def test_vortex_pair_256_reduced(dtype):
     """2D vortex-pair workload on 256^2 (the 2048^2 construction: separation 128, eps = 0.1,
     seeded Pade cores), 200 steps in the autotuned plan, the whole lattice vs the oracle."""
     rng = np.random.default_rng(2019)
@@ -291,17 +292,17 @@ def test_c3_vortex_pair_reduced(dtype):
     o0 = lat.observables()[0]
     lat.step(nsteps)
     got = lat.get_psi()[0].cpu().numpy()
-    a, b = oracle_psi(psi, nsteps, eps, g, key="c3-256")
+    a, b = oracle_psi(psi, nsteps, eps, g, key="vortex-pair-256")
     err = rel_l2(got, a + b)
     drift = abs(lat.observables()[0]["norm_q"] / o0["norm_q"] - 1)
-    print("C3-256 %s plan %s rel-L2 %.3e drift %.3e" % (dtype, lat.tuning(), err, drift))
+    print("vortex pair 256^2 %s plan %s rel-L2 %.3e drift %.3e" % (dtype, lat.tuning(), err, drift))
     assert err <= TOL[dtype]
     assert drift <= (1e-12 if dtype == "c128" else 1e-5)
 
 
-def test_c3_full_size_light_cone_samples():
+def test_vortex_pair_2048_light_cone_samples():
     """2048^2 complex64 in the autotuned configuration, 20 steps, light-cone windows vs the oracle."""
-    w = qi.c3_vortex_pair()
+    w = qi.vortex_pair_2d_2048()
     nsteps = 20
     lat = lattice(2, [2048], [2048], g=w.g, eps=w.eps, dtype="c64")
     lat.autotune()
@@ -323,7 +324,7 @@ def test_batched_equals_individual_and_oracle(dtype, plan):
     """Batched and one-at-a-time runs under the same plan (steps per pass, kernel variant) are
     bit-identical; the two kernel variants round in different orders, so the plan is pinned."""
     S, pair = plan
-    w = qi.c4_batched(nbatch=8, nsteps=1000)
+    w = qi.batched_two_solitons_1d_256(nbatch=8, nsteps=1000)
     lat = lattice(1, w.nx, g=w.g, eps=w.eps, dtype=dtype)
     lat.set_tuning(steps_per_pass=S, pair_waves=pair)
     lat.set_psi([torch.from_numpy(p) for p in w.psi])
@@ -337,7 +338,7 @@ def test_batched_equals_individual_and_oracle(dtype, plan):
         alone = one.get_psi()[0].cpu().numpy()
         assert np.array_equal(alone, got[i]), i    # same kernels, same arithmetic: bit-identical
     i = int(np.argmin(w.nx))
-    a, b = oracle_psi(w.psi[i], w.nsteps, w.eps, w.g, key="c4-smallest")
+    a, b = oracle_psi(w.psi[i], w.nsteps, w.eps, w.g, key="batched-smallest")
     assert rel_l2(got[i], a + b) <= TOL[dtype]
 
 
@@ -375,7 +376,7 @@ def test_graph_replay_equals_eager(ndim):
 
 
 def test_autotune_keeps_state():
-    w = qi.c1_single_bright(L=2048)
+    w = qi.single_bright_1d_L1024(L=2048)
     lat = lattice(1, [2048], g=w.g, eps=w.eps, dtype="c64")
     lat.set_psi([torch.from_numpy(w.psi[0])])
     before = lat.get_qubits()[0].cpu().numpy()

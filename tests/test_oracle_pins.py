@@ -105,7 +105,7 @@ def test_norm_conserved_each_operator(shape):
 
 
 def test_norm_conserved_long_run():
-    w = qi.c1_single_bright(L=256, width=16.0)
+    w = qi.single_bright_1d_L1024(L=256, width=16.0)
     a, b = O.run_psi(w.psi[0], 200, w.eps, w.g)
     n = O.observables(a, b, w.eps, w.g)["norm_q"]
     # on the bosonic manifold a = b = psi/2, so N_q = N_psi / 2 = 1/2 initially
