@@ -45,7 +45,7 @@ PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vect
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 
-# HBM traffic of one launch of the fused step on the three workloads (complex64), by kernel and
+# HBM traffic of one launch of the fused step (complex64, interleaved split), by workload, kernel and
 # plan (steps per pass in 1D, band height in 2D and 3D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
 # mean over the dispatches of that plan), each scaled by what the same counter reads for a
 # 256 MiB device copy in the same run (FETCH_SIZE: x2.000, WRITE_SIZE: x1.000).  Valid only
@@ -53,23 +53,28 @@ OBS_EVERY = 100
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
 TRAFFIC = {"sources_sha256_16": "14ec845cefda21a3", "fetch_scale": 262144.0 / 131088.1, "write_scale": 1.0,
-           "kib": {"k_step1d/S1": (783.6, 1280.0), "k_step1d/S2": (784.4, 1280.0), "k_step1d/S3": (783.9, 1280.0),
+           "kib": {
+               # 1D two-soliton workload, L = 16384 (steps per pass)
+               "1d_two_soliton_scattering": {
+                   "k_step1d/S1": (783.6, 1280.0), "k_step1d/S2": (784.4, 1280.0), "k_step1d/S3": (783.9, 1280.0),
                    "k_step1d/S4": (783.0, 1280.0), "k_step1d/S5": (793.8, 1280.0), "k_step1d/S6": (833.5, 1281.0),
                    "k_step1d/S7": (796.1, 1280.0), "k_step1d_pair/S1": (762.7, 1280.0),
                    "k_step1d_pair/S2": (763.4, 1280.0), "k_step1d_pair/S3": (762.9, 1280.0),
-                   "k_step1d_pair/S4": (762.0, 1280.0),
-                   # 2D vortex-pair workload, 2048^2 (bands of rows)
+                   "k_step1d_pair/S4": (762.0, 1280.0)},
+               # 2D vortex-pair workload, 2048^2 (bands of rows)
+               "2d_vortex_pair": {
                    "k_step2d/rows38": (234741.7, 328517.5), "k_step2d/rows76": (214411.0, 328190.6),
                    "k_step2d/rows64": (220341.3, 328306.9), "k_step2d/rows32": (231872.2, 328746.0),
                    "k_step2d/rows25": (238950.0, 329296.8), "k_step2d/rows19": (260701.3, 329088.3),
-                   "k_step2d/rows16": (273389.8, 329942.6), "k_step2d/rows128": (182862.8, 327874.4),
-                   # 3D vortex-line workload, 256^3: one step = z pass + y-x pass (sums of the two)
+                   "k_step2d/rows16": (273389.8, 329942.6), "k_step2d/rows128": (182862.8, 327874.4)},
+               # 3D vortex-line workload, 256^3: one step = z pass + y-x pass (sums of the two)
+               "3d_vortex_lines": {
                    "k_step3d/rows16": (983193.2 + 1214106.1, 1310720.0 + 1323797.8),
                    "k_step3d/rows32": (819383.3 + 1062733.6, 1310720.0 + 1316973.2),
                    "k_step3d/rows64": (737439.6 + 921646.7, 1310720.0 + 1313911.2),
                    "k_step3d/rows86": (722071.8 + 876737.2, 1310720.0 + 1314446.8),
                    "k_step3d/rows128": (696468.0 + 798938.1, 1310720.0 + 1315712.0),
-                   "k_step3d/rows256": (675981.0 + 829576.0, 1310720.0 + 1317831.7)}}
+                   "k_step3d/rows256": (675981.0 + 829576.0, 1310720.0 + 1317831.7)}}}
 
 
 def parse():
@@ -115,6 +120,7 @@ WORKLOADS = {
     "1d_two_soliton_scattering": (1, "1D L = 16384 two bright solitons, w = 48, k = -+0.05 pi"),
     "2d_vortex_pair": (2, "2D 2048^2 uniform background with a Pade vortex pair 128 sites apart"),
     "3d_vortex_lines": (3, "3D 256^3 uniform background with two wavy Pade vortex lines 64 sites apart"),
+    "3d_vortex_lines_512": (3, "3D 512^3 uniform background with two wavy Pade vortex lines 128 sites apart"),
 }
 
 
@@ -124,6 +130,8 @@ def workload_input(name, steps):
         return qi.two_solitons_1d_L16384(nsteps=steps)
     if name == "2d_vortex_pair":
         return qi.vortex_pair_2d_2048(nsteps=steps)
+    if name == "3d_vortex_lines_512":
+        return qi.vortex_lines_3d_512(nsteps=steps)
     return qi.vortex_lines_3d_256(nsteps=steps)
 
 
@@ -361,8 +369,10 @@ def main():
         kernel = "k_step2d (z pass + y-x pass)"
         key = "k_step3d/rows%d" % m["tuning"]["tile_rows"]
     traffic = None
-    if args.dtype == "c64" and key in TRAFFIC["kib"] and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
-        fk, wk = TRAFFIC["kib"][key]
+    measured = TRAFFIC["kib"].get(args.workload, {})
+    if args.dtype == "c64" and args.split == "interleaved" and key in measured \
+            and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
+        fk, wk = measured[key]
         traffic = 1024.0 * (fk * TRAFFIC["fetch_scale"] + wk * TRAFFIC["write_scale"])
 
     secondary = None
@@ -379,7 +389,9 @@ def main():
         potential = {"what": "the same workload in a harmonic trap V = omega^2 r^2/4 (V = 1/2 at the edge "
                              "midpoints) with mu = 0.5", "steps": args.trap_steps, "value": mt["value"],
                      "unit": "site-updates/s", "kernel_ms_avg": mt["kern_ms"], "plan": mt["tuning"],
-                     "kernel_time_vs_no_potential": (mt["kern_ms"] / kern_ms) if kern_ms > 0 else None,
+                     # per step: the two runs may choose plans with different steps per pass
+                     "kernel_time_vs_no_potential": (mt["kern_ms"] / mt["tuning"]["steps_per_pass"]) /
+                     (kern_ms / S) if kern_ms > 0 and mt["kern_ms"] > 0 else None,
                      "norm_drift": mt["drift"]}
     cpu = cpu_baseline(w, args.cpu_steps if ndim == 1 else max(1, args.cpu_steps // 500), ndim) \
         if args.cpu_steps > 0 else None
@@ -435,9 +447,21 @@ def main():
     print(json.dumps(out))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, nsteps, ndim=1, box3d=96):
     """The FP64 oracle, as it stands, on the first `nsteps` steps of the same workload (3D: of a
-    box3d^3 corner of its state, the whole 256^3 lattice being far beyond a bounded sample)."""
+    box3d^3 corner of its state, the whole 256^3 lattice being far beyond a bounded sample), on
+    all the threads torch uses; then the per-core rate, one thread on a tenth of that sample (1D:
+    a tenth of the steps; 2D and 3D: one step on a corner with about a tenth of the sites)."""
     import torch
     from oracle import qlg_oracle as O
     threads = torch.get_num_threads()
@@ -449,8 +473,25 @@ def cpu_baseline(w, nsteps, ndim=1, box3d=96):
     shape = "x".join(str(v) for v in psi.shape[1:]) if ndim > 1 else "L=%d" % w.nx[0]
     what = "same %dD %s workload" % (ndim, shape) if ndim < 3 else \
         "a %s corner of the 3D %s workload" % (shape, "x".join(str(v) for v in workload_shape(w, ndim)))
+    if ndim == 1:
+        psi1, steps1 = psi, max(1, nsteps // 10)
+    else:
+        side = max(1, int(round(psi.shape[-1] * 0.1 ** (1.0 / ndim))))
+        psi1, steps1 = np.ascontiguousarray(psi[(slice(None),) + (slice(0, side),) * ndim]), 1
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run_psi(psi1, steps1, w.eps, w.g)
+        dt1 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(threads)
+    sites1 = int(np.prod(psi1.shape[1:]))
+    shape1 = "x".join(str(v) for v in psi1.shape[1:])
     return {"value": sites * nsteps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%s, first %d steps (FP64 torch CPU, %d threads), %.1f s" % (what, nsteps, threads, dt)}
+            "sample": "%s, first %d steps (FP64 torch CPU, %d threads), %.1f s" % (what, nsteps, threads, dt),
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "per_core": {"value": sites1 * steps1 / dt1, "unit": "site-updates/s", "cores": 1,
+                         "sample": "%s sites, first %d steps, 1 thread, %.1f s" % (shape1, steps1, dt1)}}
 
 
 if __name__ == "__main__":

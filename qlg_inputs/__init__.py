@@ -315,6 +315,16 @@ def vortex_lines_3d_256(n: int = 256, sep: float = 64.0, eps: float = 0.1, seed:
                     {"sep": sep, "seed": seed}, nz=[n])
 
 
+def vortex_lines_3d_512(n: int = 512, sep: float = 128.0, eps: float = 0.1, seed: int = 2021,
+                        nsteps: int = 1000) -> Workload:
+    """The 3D vortex-line state on the largest cube the paper names (512^3): lines 128 sites
+    apart, as in the 2D vortex pair, bending by 8 sites along x."""
+    rng = np.random.default_rng(seed)
+    psi = vortex_lines_3d(n, sep, eps, rng, amp=8.0)
+    return Workload("3d_vortex_lines_%d" % n, 3, [n], [n], [psi], (1.0, -0.3, 0.2), eps, nsteps,
+                    {"sep": sep, "seed": seed}, nz=[n])
+
+
 def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """Generic seeded complex field of shape (5, *spatial) for stress tests."""
     rng = np.random.default_rng(seed)

@@ -5,8 +5,8 @@ The HIP path through the C ABI against the FP64 oracle's 3D step: FP64 rel-L2
 tiles along x with a tail, bands with a tail along y and z, 1-site extents) in
 several band heights, both splits; batched 3D instances of different sizes;
 observables and the overlap energy; a potential; graph replay; the exact
-reduction of a z-uniform free field to the 2D step; and the 256^3 vortex-line
-workload at full size on light-cone windows.
+reduction of a z-uniform free field to the 2D step; and the 256^3 and 512^3
+vortex-line states at full size on light-cone windows.
 """
 import numpy as np
 import pytest
@@ -171,6 +171,32 @@ def test_3d_vortex_lines_full_size_light_cone():
         assert np.abs(g_ - ref).max() <= 1e-5 * np.abs(ref).max(), (cz, cy, cx, g_, ref)
     o = lat.observables()[0]
     # encoded as a = b = psi / 2, so the conserved qubit norm is eps^3 sum |psi|^2 / 2
+    assert abs(o["norm_q"] / (0.5 * w.eps ** 3 * (np.abs(w.psi[0]) ** 2).sum()) - 1) < 1e-5
+
+
+def test_3d_vortex_lines_512_light_cone():
+    """The largest cube the paper names, 512^3 (the vortex-line state; complex64, 21.5 GB of qubit
+    state in two copies): 2 steps in the autotuned plan, sampled sites against the oracle on
+    periodic light-cone windows, and the qubit norm."""
+    w = qi.vortex_lines_3d_512(nsteps=2)
+    n = w.nx[0]
+    lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype="c64")
+    lat.set_psi([torch.from_numpy(w.psi[0])])
+    lat.autotune()
+    lat.step(2)
+    got = lat.get_psi()[0]
+    half = 4 * 2 + 2
+    rng = np.random.default_rng(1)
+    pts = [(n // 2, n // 2, n // 2 - 64), (n - 1, n - 1, n - 1), (3, n // 2, n // 2 + 64)] + \
+          [tuple(int(v) for v in rng.integers(0, n, size=3)) for _ in range(2)]
+    for (cz, cy, cx) in pts:
+        idx = [np.arange(c - half, c + half + 1) % n for c in (cz, cy, cx)]
+        win = w.psi[0][:, idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
+        A, B = O.run_psi(win, 2, w.eps, w.g)
+        ref = (A + B).numpy()[:, half, half, half]
+        g_ = got[:, cz, cy, cx].cpu().numpy()
+        assert np.abs(g_ - ref).max() <= 1e-5 * np.abs(ref).max(), (cz, cy, cx, g_, ref)
+    o = lat.observables()[0]
     assert abs(o["norm_q"] / (0.5 * w.eps ** 3 * (np.abs(w.psi[0]) ** 2).sum()) - 1) < 1e-5
 
 
