@@ -360,7 +360,7 @@ def main():
     intensity = flops_launch / bytes_launch
     bound = "alu" if intensity >= PEAK_TFLOPS[args.dtype] * 1e12 / (PEAK_HBM_GBS * 1e9) else "hbm"
     if ndim == 1:
-        kernel = "k_step1d_pair" if m["tuning"].get("pair_waves") else "k_step1d"
+        kernel = ("k_step1d", "k_step1d_pair", "k_step1d_lanes")[m["tuning"]["qubit_split"]]
         key = "%s/S%d" % (kernel, S)
     elif ndim == 2:
         kernel = "k_step2d"

@@ -106,9 +106,13 @@ typedef struct qlg_tuning {
                              along z, then the y and x substeps streaming along y, both
                              in bands of tile_rows */
   int32_t use_graph;      /* 1: replay qlg_step's launches from a captured hipGraph */
-  int32_t pair_waves;     /* 1D: 1 = the two qubit amplitudes of a tile on two wavefronts
-                             (twice the SIMDs for lattices too small to fill the chip);
-                             2D and 3D: must be 0 */
+  int32_t qubit_split;    /* 1D: where the two qubit amplitudes (a_m, b_m) of a site live:
+                             0 = one lane holds both (64-site tiles, steps_per_pass 1..7);
+                             1 = two wavefronts, a on one and b on the other (64-site
+                             tiles, steps_per_pass 1..7); 2 = two neighbouring lanes of
+                             one wavefront (32-site tiles, steps_per_pass 1..3).  1 and 2
+                             spread a lattice too small to fill the chip over twice the
+                             lanes.  2D and 3D: must be 0 */
 } qlg_tuning;
 
 typedef struct qlg_ctx qlg_ctx;

@@ -18,7 +18,7 @@ SOURCES = ["qlg_kernels.hip", "qlg_adjoint_kernels.hip", "qlg_diag_kernels.hip",
 ARCH = os.environ.get("QLG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [
-    "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Werror=dangling-else",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -26,6 +26,8 @@ namespace {
 constexpr int64_t kMaxExtent = int64_t(1) << 30;
 constexpr int64_t kMaxSites = (int64_t(1) << 31) - 1;
 constexpr int kMaxSteps1D = 7;   // 4 * S halo sites per side must leave interior lanes
+constexpr int kMaxStepsLanes = 3;   // qubit_split 2: 32-site tiles
+constexpr int kTunePairSteps = 4;   // the autotuner tries qubit_split 1 up to here (slower beyond)
 constexpr int kMinTileRows = 8, kMaxTileRows = 256;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -39,8 +41,9 @@ struct Layout {
   int32_t max_tiles_z = 0;        // 3D z pass: tiles at the densest plan
 };
 
-int tiles_1d(int64_t nx, int steps) {
-  const int tv = qlg::kLanes - 8 * steps;
+// tiles of 64 sites (qubit_split 0 and 1) or 32 sites (2), 4 * steps halo sites per side
+int tiles_1d(int64_t nx, int steps, int split) {
+  const int tv = (split == 2 ? qlg::kLaneTileSites : qlg::kLanes) - 8 * steps;
   return (int)((nx + tv - 1) / tv);
 }
 
@@ -101,7 +104,7 @@ Layout make_layout(const qlg_params* p) {
     off += 10 * d.stride;
     poff += 5 * (int64_t)d.sites;
     chunk += d.nchunks;
-    if (p->ndim == 1) maxt += tiles_1d(d.nx, kMaxSteps1D);
+    if (p->ndim == 1) maxt += std::max(tiles_1d(d.nx, kMaxSteps1D, 0), tiles_1d(d.nx, kMaxStepsLanes, 2));
     else { int a, b; tiles_2d(d.nx, d.ny, kMinTileRows, &a, &b); maxt += a * b * d.nz; }
     if (p->ndim == 3) { int a, b; tiles_z(d.nx, d.nz, kMinTileRows, &a, &b); L.max_tiles_z += a * b * d.ny; }
     L.inst.push_back(d);
@@ -213,7 +216,7 @@ qlg_status build_tiles(qlg_ctx* c) {
     InstDesc& d = c->L.inst[i];
     d.tile_begin = (int32_t)t2i.size();
     if (c->p.ndim == 1) {
-      d.ntx = tiles_1d(d.nx, c->tuning.steps_per_pass);
+      d.ntx = tiles_1d(d.nx, c->tuning.steps_per_pass, c->tuning.qubit_split);
       d.nty = 1;
     } else {
       tiles_2d(d.nx, d.ny, c->tuning.tile_rows, &d.ntx, &d.nty);
@@ -273,7 +276,7 @@ hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, void* in, void* out,
   ext.theta = th;
   const int rows = c->tuning.tile_rows;
   if (c->p.ndim == 1)
-    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.pair_waves != 0, plain, overlap, in, out, g, tg0, tg1,
+    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.qubit_split, plain, overlap, in, out, g, tg0, tg1,
                               tg25, ext, ov, c->stream, ev0, ev1);
   if (c->p.ndim == 2)
     return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, true, 8.0, in, out, in, g, tg0, tg1, tg25,
@@ -685,11 +688,13 @@ qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
   qlg_tuning n = *t;
   if (c->p.ndim == 1) {
     if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..7 in 1D");
-    if (n.pair_waves != 0 && n.pair_waves != 1) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 or 1");
+    if (n.qubit_split < 0 || n.qubit_split > 2) return fail(c, QLG_ERR_ARG, "qubit_split must be 0, 1 or 2");
+    if (n.qubit_split == 2 && n.steps_per_pass > kMaxStepsLanes)
+      return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..3 with qubit_split 2");
     n.tile_rows = 0;
   } else {
     if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D and 3D");
-    if (n.pair_waves != 0) return fail(c, QLG_ERR_ARG, "pair_waves must be 0 in 2D and 3D");
+    if (n.qubit_split != 0) return fail(c, QLG_ERR_ARG, "qubit_split must be 0 in 2D and 3D");
     if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return fail(c, QLG_ERR_ARG, "tile_rows must be 8..256");
   }
   n.use_graph = n.use_graph ? 1 : 0;
@@ -708,12 +713,14 @@ qlg_status qlg_autotune(qlg_ctx* c) {
   if (s) return s;
   // Candidates in order of preference: among plans within 2 % of the fastest the first one
   // wins, so that timing noise does not flip the plan (fewer launches first, then the
-  // one-wave kernel before the pair kernel; taller 2D bands first).
+  // one-lane-per-site kernel before the split ones; taller 2D bands first).
   std::vector<qlg_tuning> cand;
-  if (c->p.ndim == 1)
+  if (c->p.ndim == 1) {
     for (int S = kMaxSteps1D; S >= 1; --S)
-      for (int pair = 0; pair <= (S <= 4 ? 1 : 0); ++pair) cand.push_back(qlg_tuning{S, 0, c->tuning.use_graph, pair});
-  else {
+      for (int split = 0; split <= 2; ++split)
+        if (S <= (split == 0 ? kMaxSteps1D : split == 1 ? kTunePairSteps : kMaxStepsLanes))
+          cand.push_back(qlg_tuning{S, 0, c->tuning.use_graph, split});
+  } else {
     // powers of two, plus the smallest band heights whose tile count fits k waves per SIMD
     // (k = 1..4): fewer halo rows without a tail of SIMDs that hold one wave more
     std::vector<int> rows = {16, 32, 64, 128};
@@ -763,6 +770,7 @@ qlg_status qlg_autotune(qlg_ctx* c) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s) return s;
+  if (per_step_ms.empty()) return fail(c, QLG_ERR_STATE, "autotune: no candidate plan");
   const double best = *std::min_element(per_step_ms.begin(), per_step_ms.end());
   qlg_tuning best_t = cand[0];
   for (size_t k = 0; k < cand.size(); ++k)

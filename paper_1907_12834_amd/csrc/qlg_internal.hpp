@@ -52,8 +52,11 @@ struct ExtPot {
 // Kernel launchers (qlg_kernels.hip).  All return the hipError_t of the launch.
 // dtype: 0 = complex64, 1 = complex128.  Angles are theta*g0, theta*g1, theta*g2/5.
 // ev0/ev1 (optional): events the dispatch packet itself stamps at kernel start/end.
-// pair: the k_step1d_pair variant (a and b of a tile on two wavefronts).
-hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
+// split: where the two qubit amplitudes of a site live: 0 = one lane holds both
+// (k_step1d, 64-site tiles, steps <= 7); 1 = two wavefronts (k_step1d_pair, 64-site
+// tiles, steps <= 7); 2 = two neighbouring lanes (k_step1d_lanes, 32-site tiles, steps <= 3).
+constexpr int kLaneTileSites = 32;
+hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
                          double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // 2D step, or one pass of a 3D step: zpass = the four z substeps only (rows along z,

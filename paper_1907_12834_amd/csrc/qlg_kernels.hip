@@ -259,33 +259,34 @@ struct PairXchg {
     for (int m = 0; m < 5; ++m) other[m] = cx<T>{buf[cur][v ^ 1][2 * m][lane], buf[cur][v ^ 1][2 * m + 1][lane]};
     cur ^= 1;
   }
+  // S^T (Up: q(x) <- q(x + 1)) or S (q(x) <- q(x - 1)) when this wave holds the
+  // streaming qubit Q (uniform per wavefront): one lane per site
+  template <int Q, bool Up>
+  __device__ __forceinline__ void stream(cx<T> (&x)[5]) const {
+    if (q == Q) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) x[m] = Up ? from_next_lane(x[m]) : from_prev_lane(x[m]);
+    }
+  }
 };
 
-// One substep [U] I'_{x,Q} on this wave's qubit x (Q: qubit that streams).
-template <typename T, int Q, bool kExt>
-__device__ __forceinline__ void pair_substep(cx<T> (&x)[5], PairXchg<T>& X, bool with_u, const Angles<T>& ang,
-                                             T ext) {
+// One substep [U] I'_{x,Q} on this lane's qubit x (Q: qubit that streams).
+template <typename T, int Q, bool kExt, typename Xchg>
+__device__ __forceinline__ void pair_substep(cx<T> (&x)[5], Xchg& X, bool with_u, const Angles<T>& ang, T ext) {
   cx<T> y[5];
   X.swap(x, y);
   if (with_u) {
     WCoef<T> W;
-    w_coefficients<T, kExt>(x, y, ang, W, ext);   // psi = x + y, the same sum on both waves
+    w_coefficients<T, kExt>(x, y, ang, W, ext);   // psi = x + y, the same sum on both holders
     collide_own(x, y);
     w_apply(x, W);
   } else {
     collide_own(x, y);
   }
-  const bool moves = X.q == Q;      // uniform per wavefront
-  if (moves) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) x[m] = from_next_lane(x[m]);   // S^T
-  }
+  X.template stream<Q, true>(x);    // S^T
   X.swap(x, y);
   collide_own(x, y);
-  if (moves) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) x[m] = from_prev_lane(x[m]);   // S
-  }
+  X.template stream<Q, false>(x);   // S
 }
 
 template <typename T, bool kExt>
@@ -355,6 +356,135 @@ __global__ __launch_bounds__(kLanes * kPairWaves) void k_step1d_pair(StepArgs<T>
         A.ovpart[2 * w] = ore;
         A.ovpart[2 * w + 1] = oim;
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D fused step, qubit pair on two lanes
+// ---------------------------------------------------------------------------
+// A wavefront holds a 32-site tile (4*S halo sites on each side, S <= 3), site i
+// of the tile on lanes 2i and 2i+1, one qubit amplitude per lane.  During the two
+// substeps that stream qubit Q the even lane holds Q and the odd lane the other
+// qubit: the lanes trade qubits before the b substeps and before the a substeps
+// (free: the first exchange of a substep fetches the partner anyway, and the
+// trade only renames registers).
+//
+// A substep [U] I'_{x,Q} is evaluated as C U S^T C then S (as in k_step1d_pair),
+// and the streams are relabellings as well: after S^T the streaming amplitude
+// of site i is the one on lane 2i+2, so the second collide pairs lanes 2i+1 and
+// 2i+2 (even lanes read the lane before, odd lanes the lane after), and S puts
+// the labels back.  No amplitude moves for a stream; the two exchanges of a
+// substep are whole-wavefront DPP moves.  On a lattice too small to fill the
+// chip this spends two lanes per site for about 0.7x the instructions per lane,
+// without the LDS round trips of the two-wavefront form.
+constexpr int kDppQuadSwap = 0xB1;      // quad_perm [1, 0, 3, 2]: lane i reads lane i ^ 1
+constexpr int kLaneTile = kLanes / 2;   // sites per wavefront of k_step1d_lanes
+
+template <typename T>
+__device__ __forceinline__ cx<T> from_pair_lane(cx<T> v) {
+  return cx<T>{dpp_move<kDppQuadSwap>(v.re), dpp_move<kDppQuadSwap>(v.im)};
+}
+
+// One substep [U] I'_{x,Q}, the streaming qubit on the even lanes.  Trade: the
+// lanes trade qubits first (x becomes the partner's amplitude).
+template <typename T, bool kExt, bool Trade>
+__device__ __forceinline__ void lanes_substep(cx<T> (&x)[5], bool even, bool with_u, const Angles<T>& ang,
+                                              T ext) {
+  cx<T> y[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> p = from_pair_lane(x[m]);
+    if (Trade) {
+      y[m] = x[m];
+      x[m] = p;
+    } else {
+      y[m] = p;
+    }
+  }
+  if (with_u) {
+    WCoef<T> W;
+    w_coefficients<T, kExt>(x, y, ang, W, ext);   // psi = x + y, the same sum on both lanes
+    collide_own(x, y);
+    w_apply(x, W);
+  } else {
+    collide_own(x, y);
+  }
+  // S^T relabels the streaming amplitudes one site down: the partners are now
+  // (2i+1, 2i+2)
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T> prev = from_prev_lane(x[m]), next = from_next_lane(x[m]);
+    y[m] = even ? prev : next;
+  }
+  collide_own(x, y);
+  // S: the labels return to (2i, 2i+1)
+}
+
+template <typename T, bool kExt>
+__global__ __launch_bounds__(256) void k_step1d_lanes(StepArgs<T> A) {
+  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (w >= A.ntiles) return;   // whole wavefronts only; no block-level synchronisation below
+  const int lane = threadIdx.x & (kLanes - 1);
+  const bool even = (lane & 1) == 0;
+  const int i = lane >> 1;
+  const InstDesc d = A.inst[A.tile2inst[w]];
+  const int H = 4 * A.steps;
+  const int TV = kLaneTile - 2 * H;
+  const int64_t L = d.nx;
+  const int64_t x0 = (int64_t)(w - d.tile_begin) * TV - H + i;
+  const int64_t xw = wrap64(x0, L);
+  // between steps a is on the even lanes (the b substeps of a step trade first)
+  const int64_t q = even ? 0 : 5;
+  const cx<T>* src = A.in + d.off + q * d.stride + xw;
+  cx<T> x[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) x[m] = src[m * d.stride];
+  T ext = T(0);
+  if constexpr (kExt) ext = ext_angle(A, d, xw);
+  const bool plain = A.plain != 0;
+  cx<T> pold[5];
+#pragma unroll 1
+  for (int st = 0; st < A.steps; ++st) {
+    if (A.overlap && st == A.steps - 1) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) pold[m] = x[m] + from_pair_lane(x[m]);
+    }
+    // substeps j = 2h, 2h + 1 stream b (h = 0), then a (h = 1); the arithmetic is the
+    // same for both, the streaming qubit being on the even lanes
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      lanes_substep<T, kExt, true>(x, even, !plain || h == 0,
+                                   plain ? A.ang_full : substep_angles(A.ang, 2 * h), ext);
+      lanes_substep<T, kExt, false>(x, even, !plain, substep_angles(A.ang, 2 * h + 1), ext);
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) x[m] = T(1.0 / 256.0) * x[m];
+  }
+  const bool valid = i >= H && i < kLaneTile - H && x0 < L;
+  if (valid) {
+    cx<T>* dst = A.out + d.off + q * d.stride + x0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) dst[m * d.stride] = x[m];
+  }
+  if (A.overlap) {
+    double ore = 0.0, oim = 0.0;
+    cx<T> y[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) y[m] = from_pair_lane(x[m]);
+    if (valid && even) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const cx<T> c = cmulc(x[m] + y[m], pold[m]);   // conj(psi_t) psi_{t-1}
+        ore += (double)c.re;
+        oim += (double)c.im;
+      }
+    }
+    ore = wave_sum(ore);
+    oim = wave_sum(oim);
+    if (lane == 0) {
+      A.ovpart[2 * w] = ore;
+      A.ovpart[2 * w + 1] = oim;
     }
   }
 }
@@ -805,14 +935,30 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
     hipLaunchKernelGGL(kernel, grid, block, lds, st, args);
 }
 
-hipError_t launch_step1d(int dtype, int steps, bool pair, bool plain, bool overlap, const void* in, void* out,
+hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
                          double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.ntiles == 0) return hipSuccess;
-  if (steps < 1 || 8 * steps >= kLanes) return hipErrorInvalidValue;
+  static_assert(kLaneTile == kLaneTileSites, "two-lane tile size");
+  const int tile = split == 2 ? kLaneTile : kLanes;
+  if (split < 0 || split > 2 || steps < 1 || 8 * steps >= tile)
+    return hipErrorInvalidValue;
   // the plain split's single U uses theta = eps^2 = 4x the interleaved 1D angle
   const bool xt = ext.on();
-  if (pair) {
+  if (split == 2) {
+    const dim3 grid((g.ntiles + 3) / 4), block(256);
+    if (dtype == 0) {
+      const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+      if (xt) launch_timed(k_step1d_lanes<float, true>, grid, block, 0, st, ev0, ev1, args);
+      else launch_timed(k_step1d_lanes<float, false>, grid, block, 0, st, ev0, ev1, args);
+    } else {
+      const auto args = step_args<double>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);
+      if (xt) launch_timed(k_step1d_lanes<double, true>, grid, block, 0, st, ev0, ev1, args);
+      else launch_timed(k_step1d_lanes<double, false>, grid, block, 0, st, ev0, ev1, args);
+    }
+    return hipGetLastError();
+  }
+  if (split == 1) {
     const dim3 grid((g.ntiles + kPairTiles - 1) / kPairTiles), block(kLanes * kPairWaves);
     if (dtype == 0) {
       const auto args = step_args<float>(in, out, g, tg0, tg1, tg25, 4.0, ext, ovpart, steps, 0, plain, overlap);

@@ -61,7 +61,7 @@ class Obs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("steps_per_pass", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("pair_waves", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("qubit_split", ctypes.c_int32)]
 
 
 class QLGError(RuntimeError):
@@ -385,15 +385,15 @@ class Lattice:
         t = Tuning()
         self._check(lib().qlg_get_tuning(self.ctx, ctypes.byref(t)), "qlg_get_tuning")
         return {"steps_per_pass": t.steps_per_pass, "tile_rows": t.tile_rows, "use_graph": t.use_graph,
-                "pair_waves": t.pair_waves}
+                "qubit_split": t.qubit_split}
 
     def set_tuning(self, steps_per_pass: Optional[int] = None, tile_rows: Optional[int] = None,
-                   use_graph: Optional[bool] = None, pair_waves: Optional[bool] = None):
+                   use_graph: Optional[bool] = None, qubit_split: Optional[int] = None):
         cur = self.tuning()
         t = Tuning(steps_per_pass if steps_per_pass is not None else cur["steps_per_pass"],
                    tile_rows if tile_rows is not None else cur["tile_rows"],
                    int(use_graph) if use_graph is not None else cur["use_graph"],
-                   int(pair_waves) if pair_waves is not None else cur["pair_waves"])
+                   int(qubit_split) if qubit_split is not None else cur["qubit_split"])
         self._check(lib().qlg_set_tuning(self.ctx, ctypes.byref(t)), "qlg_set_tuning")
 
     def autotune(self) -> dict:

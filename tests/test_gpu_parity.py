@@ -48,18 +48,24 @@ def test_single_bright_L1024_fp64_1000_steps():
     assert abs(obs["norm_q"] / obs0["norm_q"] - 1) <= 1e-12
 
 
-@pytest.mark.parametrize("pair", [0, 1])
+@pytest.mark.parametrize("qsplit", [0, 1, 2])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("split", ["interleaved", "plain"])
 @pytest.mark.parametrize("steps_per_pass", [1, 2, 3, 4, 5, 6, 7])
-def test_1d_random_qubits_ragged(dtype, split, steps_per_pass, pair):
+def test_1d_random_qubits_ragged(dtype, split, steps_per_pass, qsplit):
     """Off-manifold random (a, b) on a ragged lattice (several tiles + tail), element-wise,
-    with one wavefront per tile and with a and b on two wavefronts."""
+    with both qubits of a site in one lane, on two wavefronts and on two lanes (whose
+    32-site tiles take at most 3 steps per pass)."""
+    from paper_1907_12834_amd.qlg import QLGError
     L, nsteps = 437, 13
     g, eps = (1.2, -0.7, 0.9), 0.35
     a, b = qi.random_qubits((L,), seed=21, scale=0.5)
     lat = lattice(1, [L], g=g, eps=eps, dtype=dtype, split=split)
-    lat.set_tuning(steps_per_pass=steps_per_pass, pair_waves=pair)
+    if qsplit == 2 and steps_per_pass > 3:
+        with pytest.raises(QLGError, match="QLG_ERR_ARG"):
+            lat.set_tuning(steps_per_pass=steps_per_pass, qubit_split=qsplit)
+        return
+    lat.set_tuning(steps_per_pass=steps_per_pass, qubit_split=qsplit)
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)
     got = lat.get_qubits()[0].cpu().numpy()
@@ -68,14 +74,14 @@ def test_1d_random_qubits_ragged(dtype, split, steps_per_pass, pair):
     assert err <= TOL[dtype], err
 
 
-@pytest.mark.parametrize("pair", [0, 1])
-@pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 31, 63, 64, 65, 129])
-def test_1d_tiny_and_edge_sizes(L, pair):
+@pytest.mark.parametrize("qsplit", [0, 1, 2])
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 15, 16, 17, 31, 32, 33, 63, 64, 65, 129])
+def test_1d_tiny_and_edge_sizes(L, qsplit):
     """Lattices smaller than a tile wrap several times inside one wavefront."""
     g, eps, nsteps = (0.8, -0.4, 1.1), 0.3, 7
     a, b = qi.random_qubits((L,), seed=L, scale=0.6)
     lat = lattice(1, [L], g=g, eps=eps, dtype="c128")
-    lat.set_tuning(steps_per_pass=2, pair_waves=pair)
+    lat.set_tuning(steps_per_pass=2, qubit_split=qsplit)
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)
     got = lat.get_qubits()[0].cpu().numpy()
@@ -181,12 +187,16 @@ def test_two_solitons_L16384_light_cone_samples(dtype):
 # ---------------------------------------------------------------------------
 # Observables
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("ndim", [1, 2])
-def test_observables_match_oracle(ndim):
+@pytest.mark.parametrize("ndim,plan", [(1, None), (1, (3, 1)), (1, (2, 2)), (1, (3, 2)), (2, None)])
+def test_observables_match_oracle(ndim, plan):
+    """Observables and the overlap energy of the last step (recorded by the step kernel of the
+    plan: steps per pass, qubit split) against the oracle."""
     g, eps, nsteps = (1.0, -0.5, 0.5), 0.2, 9
     shape = (300,) if ndim == 1 else (19, 70)
     a, b = qi.random_qubits(shape, seed=33, scale=0.4)
     lat = lattice(ndim, [shape[-1]], [shape[0]] if ndim == 2 else None, g=g, eps=eps, dtype="c128")
+    if plan:
+        lat.set_tuning(steps_per_pass=plan[0], qubit_split=plan[1])
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)
     got = lat.observables()[0]
@@ -319,20 +329,20 @@ def test_vortex_pair_2048_light_cone_samples():
 # Batched, graphs, autotune
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("plan", [(3, 0), (2, 1)])
+@pytest.mark.parametrize("plan", [(3, 0), (2, 1), (2, 2)])
 def test_batched_equals_individual_and_oracle(dtype, plan):
     """Batched and one-at-a-time runs under the same plan (steps per pass, kernel variant) are
     bit-identical; the two kernel variants round in different orders, so the plan is pinned."""
-    S, pair = plan
+    S, qsplit = plan
     w = qi.batched_two_solitons_1d_256(nbatch=8, nsteps=1000)
     lat = lattice(1, w.nx, g=w.g, eps=w.eps, dtype=dtype)
-    lat.set_tuning(steps_per_pass=S, pair_waves=pair)
+    lat.set_tuning(steps_per_pass=S, qubit_split=qsplit)
     lat.set_psi([torch.from_numpy(p) for p in w.psi])
     lat.step(w.nsteps)
     got = [t.cpu().numpy() for t in lat.get_psi()]
     for i in (0, 3, 7):
         one = lattice(1, [w.nx[i]], g=w.g, eps=w.eps, dtype=dtype)
-        one.set_tuning(steps_per_pass=S, pair_waves=pair)
+        one.set_tuning(steps_per_pass=S, qubit_split=qsplit)
         one.set_psi([torch.from_numpy(w.psi[i])])
         one.step(w.nsteps)
         alone = one.get_psi()[0].cpu().numpy()

@@ -50,10 +50,10 @@ def qubits_tensor(a, b):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("split", ["interleaved", "plain"])
-@pytest.mark.parametrize("plan", [(1, 0), (3, 0), (7, 0), (2, 1), (4, 1)])
+@pytest.mark.parametrize("plan", [(1, 0), (3, 0), (7, 0), (2, 1), (4, 1), (1, 2), (3, 2)])
 def test_1d_potential_random_qubits(dtype, split, plan):
-    """(steps per pass, pair waves): V + mu on a ragged lattice, element-wise against the oracle."""
-    S, pair = plan
+    """(steps per pass, qubit split): V + mu on a ragged lattice, element-wise against the oracle."""
+    S, qsplit = plan
     L, nsteps = 437, 13
     g, eps, mu = (1.2, -0.7, 0.9), 0.35, 0.6
     # amplitude 0.4: the plain split's large nonlinear phases amplify a relative perturbation
@@ -62,7 +62,7 @@ def test_1d_potential_random_qubits(dtype, split, plan):
     a, b = qi.random_qubits((L,), seed=31, scale=0.4)
     V = smooth_potential((L,), seed=3)
     lat = lattice(1, [L], g=g, eps=eps, dtype=dtype, split=split)
-    lat.set_tuning(steps_per_pass=S, pair_waves=pair)
+    lat.set_tuning(steps_per_pass=S, qubit_split=qsplit)
     lat.set_potential(V, mu)
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)
