@@ -4,7 +4,10 @@
 // per lane, with 4*S halo sites on each side for S fused steps (each I' has
 // dependency radius one site).  All five (a_m, b_m) pairs of a site stay in
 // registers for the whole pass; the +-1 site streams are cross-lane moves.
-// Interior lanes are written back once per pass.
+// Interior lanes are written back once per pass.  Two variants spread a
+// lattice too small to fill the chip over twice the lanes: a and b of a tile
+// on two wavefronts (k_step1d_pair), or a site's a and b on two neighbouring
+// lanes of 32-site tiles (k_step1d_lanes).
 //
 // Fused step, 2D: one wavefront owns 64 columns (56 interior + 4 halo each
 // side) and streams down a band of rows.  The y half of the step (Sec. VII
