@@ -414,7 +414,8 @@ __device__ __forceinline__ void lanes_substep(cx<T> (&x)[5], bool even, bool wit
     collide_own(x, y);
   }
   // S^T relabels the streaming amplitudes one site down: the partners are now
-  // (2i+1, 2i+2)
+  // (2i+1, 2i+2).  Every lane makes both moves before the per-lane select: a DPP
+  // move inside a branch taken by half the lanes would read switched-off lanes.
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const cx<T> prev = from_prev_lane(x[m]), next = from_next_lane(x[m]);
