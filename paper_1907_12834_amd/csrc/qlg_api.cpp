@@ -333,7 +333,7 @@ std::string tune_key(const qlg_ctx* c) {
 
 extern "C" {
 
-int32_t qlg_version(void) { return 10100; }
+int32_t qlg_version(void) { return 10200; }
 
 const char* qlg_status_string(qlg_status s) {
   switch (s) {

@@ -365,15 +365,16 @@ def test_batched_2d_uneven():
         assert rel_l2(gq, np.stack([ra, rb])) <= 1e-12
 
 
-@pytest.mark.parametrize("ndim", [1, 2])
-def test_graph_replay_equals_eager(ndim):
+@pytest.mark.parametrize("ndim,qsplit", [(1, 0), (1, 1), (1, 2), (2, 0)])
+def test_graph_replay_equals_eager(ndim, qsplit):
     shape = (777,) if ndim == 1 else (40, 90)
     a, b = qi.random_qubits(shape, seed=5, scale=0.5)
     res = []
     for use_graph in (False, True):
         lat = lattice(ndim, [shape[-1]], [shape[0]] if ndim == 2 else None, g=(1, -0.5, 0.5), eps=0.3,
                       dtype="c64")
-        lat.set_tuning(use_graph=use_graph, steps_per_pass=2 if ndim == 1 else None)
+        lat.set_tuning(use_graph=use_graph, steps_per_pass=2 if ndim == 1 else None,
+                       qubit_split=qsplit if ndim == 1 else None)
         lat.set_qubits([qubits_tensor(a, b)])
         outs = []
         for rep in range(3):   # replay the same captured graph several times, with eager work between
