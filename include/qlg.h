@@ -99,8 +99,9 @@ typedef struct qlg_obs {
 
 /* Launch plan of the fused step; chosen by qlg_autotune or set by the caller. */
 typedef struct qlg_tuning {
-  int32_t steps_per_pass; /* 1D: steps fused per HBM pass (1..7; 4 S halo sites per side
-                             of each 64-site tile); 2D and 3D: must be 1 */
+  int32_t steps_per_pass; /* 1D: steps fused per HBM pass, 4 S halo sites per side of each
+                             tile (1..7 with 64-site tiles, 1..3 with the 32-site tiles of
+                             qubit_split 2); 2D and 3D: must be 1 */
   int32_t tile_rows;      /* 2D and 3D: rows per streaming tile (8..256); 1D: ignored.
                              A 3D step is two HBM passes: the four z substeps streaming
                              along z, then the y and x substeps streaming along y, both
@@ -225,8 +226,11 @@ qlg_status qlg_observables(qlg_ctx* ctx, qlg_obs* out_host);
 qlg_status qlg_record_observables(qlg_ctx* ctx, double* rec_dev);
 qlg_status qlg_decode_records(qlg_ctx* ctx, const double* rec_host, int64_t nrec, qlg_obs* out_host);
 
-/* Plan control.  qlg_autotune times the candidate plans on the context's own
- * lattice without changing its state and keeps the fastest. */
+/* Plan control.  qlg_set_tuning returns QLG_ERR_ARG for a field out of the ranges
+ * above (the context keeps its plan).  qlg_autotune times the candidate plans on the
+ * context's own lattice without changing its state and keeps the fastest; among plans
+ * within 2 % of the fastest it prefers fewer launches, then qubit_split 0, 1, 2, then
+ * taller bands. */
 qlg_status qlg_set_tuning(qlg_ctx* ctx, const qlg_tuning* tuning);
 qlg_status qlg_get_tuning(const qlg_ctx* ctx, qlg_tuning* tuning);
 qlg_status qlg_autotune(qlg_ctx* ctx);

@@ -389,6 +389,7 @@ class Lattice:
 
     def set_tuning(self, steps_per_pass: Optional[int] = None, tile_rows: Optional[int] = None,
                    use_graph: Optional[bool] = None, qubit_split: Optional[int] = None):
+        """Set the launch plan (qlg_tuning in include/qlg.h); fields left None keep their value."""
         cur = self.tuning()
         t = Tuning(steps_per_pass if steps_per_pass is not None else cur["steps_per_pass"],
                    tile_rows if tile_rows is not None else cur["tile_rows"],
