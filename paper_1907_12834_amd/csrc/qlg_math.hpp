@@ -1,7 +1,7 @@
 // Per-site arithmetic of the spin-2 QLG step: collide and the self-interaction U.
 //
 // Everything here is __host__ __device__ so that the same code can be
-// exercised on the CPU (hostcheck.cpp) before it runs on gfx950.
+// exercised on the CPU before it runs on gfx950.
 //
 // Component order inside a site: index 0..4 <-> m_f = 2, 1, 0, -1, -2.
 #pragma once
