@@ -211,6 +211,18 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     t1 = time.perf_counter()
     obs1 = trace[-1][0] if trace else lat.observables()[0]
     wall = t1 - t0
+    # run-to-run spread: five more timed runs of about 0.2 s each (whole multiples of the
+    # observables interval), continuing the evolution
+    each = max(OBS_EVERY, min(steps, int(0.2 * steps / wall)) // OBS_EVERY * OBS_EVERY) if steps else 0
+    rates = []
+    for _ in range(5 if each else 0):
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        run(each)
+        torch.cuda.synchronize()
+        rates.append(L * each / (time.perf_counter() - r0))
+    repeats = {"runs": len(rates), "steps_each": each, "median": float(np.median(rates)), "min": min(rates),
+               "max": max(rates), "unit": "site-updates/s"} if rates else None
     # Kernel time: the same run again, now with a pair of HIP events on every fused-step
     # launch that its dispatch packet stamps at kernel start and end (library stream).
     # Those events add ~9 us of dispatch gap per launch, so they stay out of the
@@ -221,7 +233,7 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     kern_ms, launches = lat.last_kernel_ms()
     lat.set_timing(False)
     return {"w": w, "L": L, "value": L * steps / wall, "wall": wall, "kern_ms": kern_ms, "launches": launches,
-            "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0}
+            "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0, "repeats": repeats}
 
 
 def diagnostics(workload, dtype, reps):
@@ -453,6 +465,7 @@ def main():
             "hbm_frac": (hbm_gbs / PEAK_HBM_GBS) if hbm_gbs else None,
         },
         "norm_drift": m["drift"],
+        "repeats": m["repeats"],
         "secondary": secondary,
         "batched": batched,
         "adjoint": adjoint,
