@@ -76,7 +76,10 @@ TRAFFIC = {"sources_sha256_16": "93d4cbc578062042", "fetch_scale": 262144.0 / 13
                    "k_step3d/rows64": (737450.9 + 921904.6, 1310720.0 + 1314032.1),
                    "k_step3d/rows86": (722084.4 + 875162.9, 1310720.0 + 1314401.4),
                    "k_step3d/rows128": (696474.5 + 809668.8, 1310720.0 + 1317562.4),
-                   "k_step3d/rows256": (675983.6 + 829412.5, 1310720.0 + 1317913.4)}}}
+                   "k_step3d/rows256": (675983.6 + 829412.5, 1310720.0 + 1317913.4)},
+               # the 512^3 cube, at the plan its autotuner chooses
+               "3d_vortex_lines_512": {
+                   "k_step3d/rows128": (5570906.8 + 8049981.2, 10485760.0 + 10506076.6)}}}
 
 
 def parse():
