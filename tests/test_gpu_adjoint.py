@@ -216,6 +216,34 @@ def test_c64_forward_fp64_jacobian_close_to_oracle():
     assert rel(gg1, gg0) <= 1e-4
 
 
+def test_adjoint_vortex_pair_512_full_size():
+    """The adjoint workload at full size (the 512^2 vortex pair, checkpoints every 64), 128 steps.
+    Complex64 forward with the FP64 Jacobian: the energy is invariant under a global phase, so
+    the gradient is orthogonal to i psi0.  Complex128: dL/dg0 and a directional derivative against
+    central differences of the GPU forward."""
+    w = qi.adjoint_vortex_pair_2d_512(nsteps=128)
+    psi0, g, eps, nsteps, K = w.psi[0], w.g, w.eps, 128, 64
+    L, gp, gg = gpu_grad(psi0, g, eps, nsteps, K=K, dtype="c64")
+    dphase = float(np.real(np.sum(np.conj(gp) * (1j * psi0))))
+    assert abs(dphase) <= 1e-4 * np.linalg.norm(gp) * np.linalg.norm(psi0), dphase
+    L, gp, gg = gpu_grad(psi0, g, eps, nsteps, K=K, dtype="c128")
+    h = 1e-6
+
+    def Lof(p, gv):
+        with torch.no_grad():
+            return float(objective(torch.from_numpy(p).cuda(), torch.tensor(gv, dtype=torch.float64), eps=eps,
+                                   nsteps=nsteps, checkpoint_every=K))
+    gp_, gm_ = list(g), list(g)
+    gp_[0] += h
+    gm_[0] -= h
+    fdg = (Lof(psi0, gp_) - Lof(psi0, gm_)) / (2 * h)
+    assert abs(fdg - gg[0]) <= 1e-6 * abs(gg[0]), (fdg, gg[0])
+    d = qi.random_field(psi0.shape[1:], seed=54, scale=1.0)
+    fd = (Lof(psi0 + h * d, g) - Lof(psi0 - h * d, g)) / (2 * h)
+    an = float(np.real(np.sum(np.conj(gp) * d)))
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
 def test_vortex_pair_2d_fd_check():
     """The 2D vortex-pair construction on 64^2 (eps = 0.4, separation 16) in FP64: FD vs adjoint."""
     rng = np.random.default_rng(2019)

@@ -352,6 +352,35 @@ def test_batched_equals_individual_and_oracle(dtype, plan):
     assert rel_l2(got[i], a + b) <= TOL[dtype]
 
 
+def test_batched_256_full_size_light_cone_samples():
+    """The full 256-instance batch (2.3 M sites) in the autotuned plan, 40 steps: sites of the
+    smallest, the largest and random instances (on the solitons, random, at the periodic seam)
+    against the oracle on light-cone windows (radius 4 per step), and every qubit norm kept."""
+    w = qi.batched_two_solitons_1d_256(nsteps=40)
+    nsteps = 40
+    lat = lattice(1, w.nx, g=w.g, eps=w.eps, dtype="c64")
+    lat.set_psi([torch.from_numpy(p) for p in w.psi])
+    lat.autotune()
+    o0 = lat.observables()
+    lat.step(nsteps)
+    o1 = lat.observables()
+    got = lat.get_psi()
+    half = 4 * nsteps + 2
+    rng = np.random.default_rng(7)
+    inst = [int(np.argmin(w.nx)), int(np.argmax(w.nx))] + [int(v) for v in rng.integers(0, w.nbatch, size=3)]
+    for i in inst:
+        L = w.nx[i]
+        peak = np.abs(w.psi[i]).max()
+        for c in (L // 2 - L // 8, L // 2 + L // 8, int(rng.integers(0, L)), 0, L - 1):
+            idx = np.arange(c - half, c + half + 1) % L
+            A, B = O.run_psi(w.psi[i][:, idx], nsteps, w.eps, w.g)
+            ref = (A + B).numpy()[:, half]
+            g_ = got[i][:, c].cpu().numpy()
+            assert np.abs(g_ - ref).max() <= 1e-5 * peak, (i, c, g_, ref)
+    for i in range(w.nbatch):
+        assert abs(o1[i]["norm_q"] / o0[i]["norm_q"] - 1) <= 1e-5, i
+
+
 def test_batched_2d_uneven():
     g, eps, nsteps = (1.0, -0.3, 0.2), 0.3, 4
     shapes = [(20, 33), (9, 70), (64, 64)]
