@@ -128,7 +128,7 @@ def test_vorticity_random_ragged_batch(dtype):
     assert "omega" not in only[0] and torch.equal(only[1]["winding"], got[1]["winding"])
 
 
-def test_vorticity_c3_full_size():
+def test_vorticity_vortex_pair_2048_full_size():
     """The 2048^2 vortex-pair workload (complex64) after 20 steps: omega and windings of the three
     occupied components over the whole lattice; each keeps its single core (+1 in m = +-2, -1 in m = 0)."""
     w = qi.vortex_pair_2d_2048(nsteps=20)

@@ -109,7 +109,7 @@ def test_two_solitons_reduced(dtype):
     o0 = lat.observables()[0]
     lat.step(w.nsteps)
     got = lat.get_psi()[0].cpu().numpy()
-    a, b = oracle_psi(w.psi[0], w.nsteps, w.eps, w.g, key="c2")
+    a, b = oracle_psi(w.psi[0], w.nsteps, w.eps, w.g, key="two-solitons-L16384")
     err = rel_l2(got, a + b)
     o1 = lat.observables()[0]
     drift = abs(o1["norm_q"] / o0["norm_q"] - 1)
