@@ -206,6 +206,27 @@ def test_batched_adjoint_matches_single_instances():
     assert rel(np.array(dg) + np.array(dg0), tot_dg) <= 1e-13
 
 
+def test_adjoint_independent_of_forward_plan():
+    """The checkpoints come from the fused forward kernels of the context's plan: a site's qubits
+    on one lane, on two wavefronts or on two lanes give the same gradient (the plans round the
+    forward states in different orders, FP64)."""
+    from paper_1907_12834_amd.qlg import Lattice
+    x = qi.random_field((83,), seed=52, scale=0.4)
+    eps, nsteps, K = 0.3, 7, 3
+    res = []
+    for S, qs in ((1, 0), (3, 1), (2, 2), (3, 2)):
+        lat = Lattice(1, [83], g=G, eps=eps, dtype="c128")
+        lat.set_tuning(steps_per_pass=S, qubit_split=qs)
+        lat.set_psi([torch.from_numpy(x)])
+        ck = lat.forward_record(nsteps, K)
+        val, lam, dg0 = lat.objective_grad("energy")
+        dg = lat.adjoint_step(nsteps, K, ck, lam)
+        res.append((val, lam.cpu().numpy(), np.array(dg) + np.array(dg0)))
+    for val, lam, dg in res[1:]:
+        assert abs(val - res[0][0]) <= 1e-13 * abs(res[0][0])
+        assert rel(lam, res[0][1]) <= 1e-12 and rel(dg, res[0][2]) <= 1e-12
+
+
 def test_c64_forward_fp64_jacobian_close_to_oracle():
     psi0 = qi.random_field((40,), seed=52, scale=0.4)
     eps, nsteps = 0.3, 9
