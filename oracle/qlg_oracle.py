@@ -23,7 +23,8 @@ the paper (Taylor, Smith, Yepez, arXiv:1907.12834):
   energy eps^d sum (V + mu) n;
 * per-site F_par, F_perp, |A00| (Sec. III, eq. cmap) and the lattice vorticity
   of one component from central differences of its phase, with plaquette
-  winding numbers (Sec. VI, "Calculating quantum vorticity on a lattice").
+  winding numbers (Sec. VI, "Calculating quantum vorticity on a lattice"); on
+  3D lattices the same in each family of lattice planes (three components).
 
 The paper defers C, S and U to earlier work, so the definitions below are
 readings, each pinned by the tests of this oracle:
@@ -328,20 +329,36 @@ def _wrap(d: np.ndarray) -> np.ndarray:
     return np.where(d > np.pi, d - 2 * np.pi, np.where(d <= -np.pi, d + 2 * np.pi, d))
 
 
+def _plane_vorticity(S: np.ndarray, ua: int, va: int) -> Tuple[np.ndarray, np.ndarray]:
+    """omega = d_u v_v - d_v v_u and the windings of the plaquettes c -> c+u -> c+u+v -> c+v, in the
+    planes spanned by array axes ua (u) and va (v), for a periodic phase field S."""
+    su = lambda f, k: np.roll(f, -k, axis=ua)   # noqa: E731  f(c + k u)
+    sv = lambda f, k: np.roll(f, -k, axis=va)   # noqa: E731  f(c + k v)
+    vu = _wrap(su(S, 1) - su(S, -1)) / 2
+    vv = _wrap(sv(S, 1) - sv(S, -1)) / 2
+    omega = (su(vv, 1) - su(vv, -1) - sv(vu, 1) + sv(vu, -1)) / 2
+    s10, s11, s01 = su(S, 1), su(sv(S, 1), 1), sv(S, 1)
+    circ = _wrap(s10 - S) + _wrap(s11 - s10) + _wrap(s01 - s11) + _wrap(S - s01)
+    return omega, np.rint(circ / (2 * np.pi)).astype(np.int32)
+
+
 def vorticity(psi_m: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """Vorticity of one component on a periodic (Ny, Nx) lattice, Sec. VI: S = arg psi_m (0 where
     psi_m = 0); v_x = (S(x+1) - S(x-1)) / 2 and v_y likewise, each difference wrapped to (-pi, pi];
     omega = (v_y(x+1, y) - v_y(x-1, y) - v_x(x, y+1) + v_x(x, y-1)) / 2, the central-difference curl
     (the printed stencil swaps v_x and v_y in two terms).  Also the winding number of every
     plaquette (x, y) -> (x+1, y) -> (x+1, y+1) -> (x, y+1): the sum of its four wrapped phase
-    differences over 2 pi, an integer, indexed by its corner (x, y)."""
+    differences over 2 pi, an integer, indexed by its corner (x, y).
+
+    On a periodic (Nz, Ny, Nx) lattice (the paper's method in 3D, which it names as future work):
+    the same in each family of lattice planes, the three components of the curl omega = curl v
+    and the windings of the plaquettes normal to x, y and z, circulated y -> z, z -> x and x -> y
+    (right-handed about the normal); both arrays have shape (3, Nz, Ny, Nx), components x, y, z."""
     psi_m = np.asarray(psi_m, dtype=np.complex128)
     S = np.where(psi_m == 0, 0.0, np.angle(psi_m))
-    sx = lambda f, k: np.roll(f, -k, axis=1)   # noqa: E731  f(x + k)
-    sy = lambda f, k: np.roll(f, -k, axis=0)   # noqa: E731  f(y + k)
-    vx = _wrap(sx(S, 1) - sx(S, -1)) / 2
-    vy = _wrap(sy(S, 1) - sy(S, -1)) / 2
-    omega = (sx(vy, 1) - sx(vy, -1) - sy(vx, 1) + sy(vx, -1)) / 2
-    s10, s11, s01 = sx(S, 1), sx(sy(S, 1), 1), sy(S, 1)
-    circ = _wrap(s10 - S) + _wrap(s11 - s10) + _wrap(s01 - s11) + _wrap(S - s01)
-    return omega, np.rint(circ / (2 * np.pi)).astype(np.int32)
+    if S.ndim == 2:
+        return _plane_vorticity(S, 1, 0)          # u = x, v = y
+    planes = [_plane_vorticity(S, 1, 0),          # normal x: u = y, v = z
+              _plane_vorticity(S, 0, 2),          # normal y: u = z, v = x
+              _plane_vorticity(S, 2, 1)]          # normal z: u = x, v = y
+    return np.stack([o for o, _ in planes]), np.stack([w for _, w in planes])

@@ -831,6 +831,51 @@ def test_vorticity_small_lattices():
         assert int(wind.sum()) == 0
 
 
+def test_vorticity_3d_z_uniform_reduces_to_2d():
+    """A field uniform along z: the z components are the 2D vorticity and windings of every plane,
+    the x and y components vanish (no phase changes along z)."""
+    cores = [(20.5, 14.5, 1), (20.5, 45.5, -1)]
+    f2 = _vortex_field(40, 64, cores, kx=2 * np.pi * 3 / 64)
+    om2, w2 = O.vorticity(f2)
+    om3, w3 = O.vorticity(np.repeat(f2[None], 5, axis=0))
+    assert om3.shape == (3, 5, 40, 64) and w3.dtype == np.int32
+    for z in range(5):
+        assert np.array_equal(om3[2, z], om2) and np.array_equal(w3[2, z], w2)
+    assert not om3[:2].any() and not w3[:2].any()
+
+
+def test_vorticity_3d_line_along_x_is_right_handed():
+    """A straight vortex line along x (phase atan2(z - z0, y - y0), which turns from y to z): winding
+    +1 on the x-normal plaquette around the core in every x plane (circulation y -> z, right-handed
+    about +x), none in the interior elsewhere, none on y- or z-normal plaquettes (the field does not
+    change along x), and omega_x sums to 2 pi around the core (discrete Stokes)."""
+    nz, ny, nx, z0, y0 = 40, 48, 6, 20.5, 23.5
+    z, y, _ = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    om, w = O.vorticity(np.exp(1j * np.arctan2(z - z0, y - y0)))
+    for x in range(nx):
+        inner = w[0, :-1, :-1, x]
+        assert {(int(a), int(b)): int(inner[a, b]) for a, b in zip(*np.nonzero(inner))} == {(20, 23): 1}
+        box = om[0, 10:32, 13:35, x]
+        assert abs(box.sum() - 2 * np.pi) < 1e-9, box.sum()
+    assert not w[1:].any() and not om[1:].any()
+
+
+def test_vorticity_3d_cyclic_relabelling_of_axes():
+    """Relabelling the axes cyclically (x, y, z) -> (z, x, y) is a rotation: the components follow
+    the axes, value for value (the same arithmetic on the same phases), which fixes the orientation
+    and sign conventions of all three plane families together."""
+    rng = np.random.default_rng(12)
+    psi = np.exp(1j * rng.uniform(-np.pi, np.pi, size=(5, 6, 7)))
+    om, w = O.vorticity(psi)
+    P = np.transpose(psi, (1, 2, 0))              # P[i, j, k] = psi[k, i, j]: P's x, y, z = psi's z, x, y
+    omP, wP = O.vorticity(P)
+    for cP, c in ((0, 2), (1, 0), (2, 1)):
+        assert np.array_equal(omP[cP], np.transpose(om[c], (1, 2, 0)))
+        assert np.array_equal(wP[cP], np.transpose(w[c], (1, 2, 0)))
+    # and on a periodic lattice every plane family's windings sum to zero
+    assert not w.sum(axis=(1, 2, 3)).any()
+
+
 # ---------------------------------------------------------------------------
 # P12: external potential and chemical potential (Sec. II "Additional terms"; Sec. IV dispersion)
 # ---------------------------------------------------------------------------
