@@ -240,9 +240,10 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
 
 
 def diagnostics(workload, dtype, reps):
-    """Per-site fields (Sec. III) and, in 2D, the vorticity of m = +2 (Sec. VI) on the workload's
-    lattice after 20 steps: average time per launch over `reps` back-to-back launches, from HIP
-    events on the library's stream, against the algorithmic HBM bytes of each kernel."""
+    """Per-site fields (Sec. III) and, in 2D and 3D, the vorticity of m = +2 (Sec. VI; in 3D its
+    three plane families) on the workload's lattice after 20 steps: average time per call over
+    `reps` back-to-back calls, from HIP events on the library's stream, against the algorithmic
+    HBM bytes of each kernel."""
     import torch
     from paper_1907_12834_amd.qlg import lib
 
@@ -252,16 +253,17 @@ def diagnostics(workload, dtype, reps):
     lat.set_psi([torch.from_numpy(w.psi[0])])
     lat.step(20)
     n = lat.sites
-    outs = [torch.empty(n, dtype=torch.float64, device=lat.device) for _ in range(4)]
-    wind = torch.empty(n, dtype=torch.int32, device=lat.device)
+    ncomp = 3 if ndim == 3 else 1
+    outs = [torch.empty(ncomp * n if k == 0 else n, dtype=torch.float64, device=lat.device) for k in range(4)]
+    wind = torch.empty(ncomp * n, dtype=torch.int32, device=lat.device)
     elem = 8 if dtype == "c64" else 16
     L = lib()
     # bytes per site: the 10 qubit amplitudes read and 4 doubles written; a_m, b_m read
-    # and one double and one int32 written
+    # and one double and one int32 written (per plane family in 3D)
     calls = {"k_fields": (lambda: L.qlg_fields(lat.ctx, *[t.data_ptr() for t in outs]), 10 * elem + 32)}
-    if ndim == 2:
+    if ndim >= 2:
         calls["k_vorticity"] = (lambda: L.qlg_vorticity(lat.ctx, 0, outs[0].data_ptr(), wind.data_ptr()),
-                                2 * elem + 12)
+                                ncomp * (2 * elem + 12))
     res = {"lattice_sites": n, "storage": dtype}
     for name, (fn, bsite) in calls.items():
         for _ in range(5):

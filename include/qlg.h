@@ -173,7 +173,7 @@ qlg_status qlg_set_potential(qlg_ctx* ctx, const double* V_dev, double mu);
 qlg_status qlg_fields(qlg_ctx* ctx, double* n_dev, double* f_par_dev, double* f_perp_dev, double* a00_dev);
 
 /* Lattice vorticity of hyperfine component m_index (0..4 for m = 2..-2) of a
- * 2D state (Sec. VI, "Calculating quantum vorticity on a lattice"), periodic:
+ * 2D or 3D state (Sec. VI, "Calculating quantum vorticity on a lattice"), periodic:
  * the phase S = arg psi_m (0 where psi_m is exactly zero) gives velocities by
  * central differences, v_x(x, y) = w(S(x+1, y) - S(x-1, y)) / 2 and v_y
  * likewise, each difference w(.) reduced to (-pi, pi]; then
@@ -183,8 +183,13 @@ qlg_status qlg_fields(qlg_ctx* ctx, double* n_dev, double* f_par_dev, double* f_
  * phase differences over 2 pi: +1 where the phase of psi_m rises by 2 pi
  * counter-clockwise (x right, y up) around the plaquette.
  * Both use the canonical scalar layout of qlg_fields; either may be NULL, not
- * both (QLG_ERR_ARG).  QLG_ERR_SHAPE for a 1D context, QLG_ERR_ARG for
- * m_index outside 0..4.  Asynchronous on the context's stream. */
+ * both (QLG_ERR_ARG).  On a 3D lattice (which the paper names as future work)
+ * the same is done in every family of lattice planes: omega_dev and winding_dev
+ * then hold three such arrays one after the other (3 x the total site count),
+ * for the plaquettes normal to x, y and z, circulated y -> z, z -> x and x -> y
+ * (right-handed about the normal), omega being the curl component along that
+ * normal.  QLG_ERR_SHAPE for a 1D context, QLG_ERR_ARG for m_index outside
+ * 0..4.  Asynchronous on the context's stream. */
 qlg_status qlg_vorticity(qlg_ctx* ctx, int32_t m_index, double* omega_dev, int32_t* winding_dev);
 
 /* Vortex cores of component m_index of a 2D state, for tracking them through a

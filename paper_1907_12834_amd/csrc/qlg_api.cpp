@@ -517,11 +517,12 @@ qlg_status qlg_fields(qlg_ctx* c, double* n, double* f_par, double* f_perp, doub
 qlg_status qlg_vorticity(qlg_ctx* c, int32_t m_index, double* omega, int32_t* winding) {
   qlg_status s = check_ctx(c);
   if (s) return s;
-  if (c->p.ndim != 2) return fail(c, QLG_ERR_SHAPE, "vorticity needs a 2D lattice");
+  if (c->p.ndim < 2) return fail(c, QLG_ERR_SHAPE, "vorticity needs a 2D or 3D lattice");
   if (m_index < 0 || m_index > 4) return fail(c, QLG_ERR_ARG, "m_index must be in 0..4");
   if (!omega && !winding) return fail(c, QLG_ERR_ARG, "omega and winding are both NULL");
   for (const qlg::InstDesc& d : c->L.inst) {
-    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->copy(c->cur), d, m_index, omega, winding, c->stream),
+    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->p.ndim, c->copy(c->cur), d, m_index, omega, winding,
+                                           c->L.psi_elems / 5, c->stream),
                   "vorticity kernel");
     if (s) return s;
   }
@@ -537,7 +538,8 @@ qlg_status qlg_find_vortices(qlg_ctx* c, int32_t m_index, int32_t* winding, int3
   if (!winding || !count) return fail(c, QLG_ERR_ARG, "winding or count is NULL");
   if (capacity < 0 || (capacity > 0 && !cores)) return fail(c, QLG_ERR_ARG, "bad capacity or NULL cores");
   for (const qlg::InstDesc& d : c->L.inst) {
-    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->copy(c->cur), d, m_index, nullptr, winding, c->stream),
+    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, 2, c->copy(c->cur), d, m_index, nullptr, winding,
+                                           c->L.psi_elems / 5, c->stream),
                   "vorticity kernel");
     if (s) return s;
   }

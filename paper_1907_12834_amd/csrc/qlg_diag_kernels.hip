@@ -97,22 +97,25 @@ __device__ __forceinline__ uint32_t wrap_coord(int64_t c, int32_t n) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restrict__ st, InstDesc d, int m,
-                                                           int64_t block0, double* __restrict__ omega_out,
+__global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restrict__ st, InstDesc d,
+                                                           PlaneFamily f, int m, int64_t block0,
+                                                           double* __restrict__ omega_out,
                                                            int32_t* __restrict__ wind_out) {
 #pragma clang fp contract(off)
   __shared__ double S[kVortLH][kVortLW];
-  const int64_t ntx = (d.nx + kVortW - 1) / kVortW, blk = block0 + blockIdx.x;
-  const int64_t x0 = (blk % ntx) * kVortW, y0 = (blk / ntx) * kVortH;
-  const cx<T>* pa = st + d.off + (int64_t)m * d.stride;
-  const cx<T>* pb = st + d.off + (int64_t)(5 + m) * d.stride;
+  // tile (u0, v0) of plane p: the x, y of the comments above are u, v of the family
+  const int64_t ntu = (f.nu + kVortW - 1) / kVortW, ntv = (f.nv + kVortH - 1) / kVortH;
+  const int64_t blk = block0 + blockIdx.x, tq = blk / ntu;
+  const int64_t x0 = (blk % ntu) * kVortW, y0 = (tq % ntv) * kVortH, pofs = (tq / ntv) * f.sp;
+  const cx<T>* pa = st + d.off + (int64_t)m * d.stride + pofs;
+  const cx<T>* pb = st + d.off + (int64_t)(5 + m) * d.stride + pofs;
   cx<T> v[kVortLoads];
 #pragma unroll
   for (int r = 0; r < kVortLoads; ++r) {
     const int i = threadIdx.x + r * kVortThreads;
     if (i < kVortLH * kVortLW) {
       const int ly = i / kVortLW, lx = i - ly * kVortLW;
-      const int64_t s = (int64_t)wrap_coord(y0 - 1 + ly, d.ny) * d.nx + wrap_coord(x0 - 1 + lx, d.nx);
+      const int64_t s = (int64_t)wrap_coord(y0 - 1 + ly, f.nv) * f.sv + (int64_t)wrap_coord(x0 - 1 + lx, f.nu) * f.su;
       v[r] = pa[s] + pb[s];
     }
   }
@@ -124,13 +127,13 @@ __global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restr
   __syncthreads();
   const int lx = threadIdx.x % kVortW;
   const int64_t x = x0 + lx;
-  if (x >= d.nx) return;
-  const int64_t base = d.psi_off / 5;
+  if (x >= f.nu) return;
+  const int64_t base = d.psi_off / 5 + pofs;
   for (int k = threadIdx.x / kVortW; k < kVortH; k += kVortThreads / kVortW) {
     const int64_t y = y0 + k;
-    if (y >= d.ny) break;
+    if (y >= f.nv) break;
     const int j = k + 1, i = lx + 1;
-    const int64_t o = base + y * d.nx + x;
+    const int64_t o = base + y * f.sv + x * f.su;
     if (omega_out) {
       const double vy_p = wrap_pi(S[j + 1][i + 1] - S[j - 1][i + 1]) / 2.0;
       const double vy_m = wrap_pi(S[j + 1][i - 1] - S[j - 1][i - 1]) / 2.0;
@@ -233,24 +236,41 @@ hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, doub
   return hipGetLastError();
 }
 
-static int64_t vorticity_blocks(const InstDesc& d) {
-  return (int64_t)((d.nx + kVortW - 1) / kVortW) * ((d.ny + kVortH - 1) / kVortH);
+static int64_t vorticity_blocks(const PlaneFamily& f) {
+  return (int64_t)((f.nu + kVortW - 1) / kVortW) * ((f.nv + kVortH - 1) / kVortH) * f.np;
 }
 
-hipError_t launch_vorticity(int dtype, const void* state, const InstDesc& d, int m, double* omega,
-                            int32_t* winding, hipStream_t st) {
+static hipError_t launch_family(int dtype, const void* state, const InstDesc& d, const PlaneFamily& f, int m,
+                                double* omega, int32_t* winding, hipStream_t st) {
   // pieces of at most 2^22 workgroups keep every launch far below 2^32 work-items
   constexpr int64_t kPiece = int64_t(1) << 22;
-  const int64_t nb = vorticity_blocks(d);
+  const int64_t nb = vorticity_blocks(f);
   for (int64_t b0 = 0; b0 < nb; b0 += kPiece) {
     const unsigned n = (unsigned)(nb - b0 < kPiece ? nb - b0 : kPiece);
     if (dtype == 0)
-      hipLaunchKernelGGL(k_vorticity<float>, dim3(n), dim3(kVortThreads), 0, st, (const cx<float>*)state, d, m,
-                         b0, omega, winding);
+      hipLaunchKernelGGL(k_vorticity<float>, dim3(n), dim3(kVortThreads), 0, st, (const cx<float>*)state, d, f,
+                         m, b0, omega, winding);
     else
       hipLaunchKernelGGL(k_vorticity<double>, dim3(n), dim3(kVortThreads), 0, st, (const cx<double>*)state, d,
-                         m, b0, omega, winding);
+                         f, m, b0, omega, winding);
     const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_vorticity(int dtype, int ndim, const void* state, const InstDesc& d, int m, double* omega,
+                            int32_t* winding, int64_t component_stride, hipStream_t st) {
+  const int64_t nx = d.nx, nxy = (int64_t)d.nx * d.ny;
+  if (ndim == 2) return launch_family(dtype, state, d, PlaneFamily{d.nx, d.ny, 1, 1, nx, 0}, m, omega, winding, st);
+  // 3D: the plaquettes normal to x (u = y, v = z), to y (u = z, v = x) and to z (u = x, v = y),
+  // one after the other in the outputs
+  const PlaneFamily fam[3] = {PlaneFamily{d.ny, d.nz, d.nx, nx, nxy, 1},
+                              PlaneFamily{d.nz, d.nx, d.ny, nxy, 1, nx},
+                              PlaneFamily{d.nx, d.ny, d.nz, 1, nx, nxy}};
+  for (int c = 0; c < 3; ++c) {
+    const hipError_t e = launch_family(dtype, state, d, fam[c], m, omega ? omega + c * component_stride : nullptr,
+                                       winding ? winding + c * component_stride : nullptr, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -296,16 +296,20 @@ class Lattice:
         return [{w: per[w][i] for w in which} for i in range(self.nbatch)]
 
     def vorticity(self, m_index: int, omega: bool = True, winding: bool = True) -> List[dict]:
-        """Per instance {"omega": FP64 (ny, nx), "winding": int32 (ny, nx)} of component m_index (Sec. VI)."""
-        om = torch.empty(self.sites, dtype=torch.float64, device=self.device) if omega else None
-        wd = torch.empty(self.sites, dtype=torch.int32, device=self.device) if winding else None
+        """Per instance {"omega": FP64, "winding": int32} of component m_index (Sec. VI): shape
+        (ny, nx) in 2D; (3, nz, ny, nx) in 3D, the plaquettes normal to x, y and z."""
+        ncomp = 3 if self.ndim == 3 else 1
+        om = torch.empty(ncomp * self.sites, dtype=torch.float64, device=self.device) if omega else None
+        wd = torch.empty(ncomp * self.sites, dtype=torch.int32, device=self.device) if winding else None
         self._check(lib().qlg_vorticity(self.ctx, int(m_index), om.data_ptr() if om is not None else None,
                                         wd.data_ptr() if wd is not None else None), "qlg_vorticity")
         out = [dict() for _ in range(self.nbatch)]
         for key, buf in (("omega", om), ("winding", wd)):
-            if buf is not None:
-                for i, v in enumerate(self._unflat_scalar(buf)):
-                    out[i][key] = v
+            if buf is None:
+                continue
+            parts = [self._unflat_scalar(b) for b in buf.view(ncomp, self.sites)]
+            for i in range(self.nbatch):
+                out[i][key] = parts[0][i] if ncomp == 1 else torch.stack([p[i] for p in parts])
         return out
 
     def find_vortices(self, m_index: int, capacity: int = 4096) -> torch.Tensor:

@@ -5,8 +5,9 @@ The HIP path through the C ABI against the FP64 oracle's 3D step: FP64 rel-L2
 tiles along x with a tail, bands with a tail along y and z, 1-site extents) in
 several band heights, both splits; batched 3D instances of different sizes;
 observables and the overlap energy; a potential; graph replay; the exact
-reduction of a z-uniform free field to the 2D step; and the 256^3 and 512^3
-vortex-line states at full size on light-cone windows.
+reduction of a z-uniform free field to the 2D step; the 256^3 and 512^3
+vortex-line states at full size on light-cone windows; and the lattice
+vorticity of the three plane families.
 """
 import numpy as np
 import pytest
@@ -200,12 +201,56 @@ def test_3d_vortex_lines_512_light_cone():
     assert abs(o["norm_q"] / (0.5 * w.eps ** 3 * (np.abs(w.psi[0]) ** 2).sum()) - 1) < 1e-5
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_3d_vorticity_random_ragged_batch(dtype):
+    """The three plane families of a 3D state (instances of different shapes, 1- and 2-site
+    extents included) against the oracle on the GPU's own psi: windings exact, omega to rounding
+    (both sides take the same FP64 differences of the same phases in the same order)."""
+    shapes = [(5, 7, 70), (3, 20, 9), (1, 1, 1), (2, 1, 65), (34, 3, 2)]
+    lat = lattice3(shapes, g=(1.0, -0.3, 0.5), eps=0.4, dtype=dtype)
+    lat.set_psi([torch.from_numpy(qi.random_field(sh, seed=80 + i)) for i, sh in enumerate(shapes)])
+    lat.step(2)
+    psi = [p.cpu().numpy() for p in lat.get_psi()]
+    for m in (0, 3):
+        res = lat.vorticity(m)
+        for i, sh in enumerate(shapes):
+            om, wd = O.vorticity(psi[i][m])
+            assert res[i]["omega"].shape == (3,) + sh and res[i]["winding"].shape == (3,) + sh
+            assert np.array_equal(res[i]["winding"].cpu().numpy(), wd), (m, i)
+            assert np.abs(res[i]["omega"].cpu().numpy() - om).max() <= 1e-12, (m, i)
+
+
+def test_3d_vortex_lines_vorticity_full_size():
+    """The 256^3 vortex-line workload after 3 steps (complex64): windings and omega of sampled
+    planes of each family against the oracle's lattice vorticity of that plane."""
+    w = qi.vortex_lines_3d_256(nsteps=3)
+    n = w.nx[0]
+    lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype="c64")
+    lat.set_psi([torch.from_numpy(w.psi[0])])
+    lat.step(3)
+    psi0 = lat.get_psi()[0][0].cpu().numpy()          # m = +2, [z][y][x]
+    r = lat.vorticity(0)[0]
+    om, wd = r["omega"].cpu().numpy(), r["winding"].cpu().numpy()
+    for k in (0, 100, 255):
+        # normal x: the (z, y) plane circulated y -> z; normal y: (x, z) circulated z -> x;
+        # normal z: (y, x) circulated x -> y -- the oracle's 2D rule with u = axis 1, v = axis 0
+        for c, plane, back in ((0, psi0[:, :, k], lambda a: a[:, :, k]),
+                               (1, psi0[:, k, :].T, lambda a: a[:, k, :].T),
+                               (2, psi0[k], lambda a: a[k])):
+            o2, w2 = O.vorticity(plane)
+            assert np.array_equal(back(wd[c]), w2), (c, k)
+            assert np.abs(back(om[c]) - o2).max() <= 1e-12, (c, k)
+    # the +1 line of m = +2 crosses every z plane; the periodic lattice's windings sum to zero
+    for z in (0, 64, 128, 255):
+        assert (wd[2, z] == 1).any() and int(wd[2, z].sum()) == 0
+
+
 def test_3d_calls_that_need_a_lower_dimension():
     from paper_1907_12834_amd.qlg import QLGError
     lat = lattice3([(4, 5, 6)], g=(1.0, -0.3, 0.5), eps=0.4, dtype="c128")
     lat.set_psi([torch.from_numpy(qi.random_field((4, 5, 6), seed=2))])
     with pytest.raises(QLGError, match="QLG_ERR_SHAPE"):
-        lat.vorticity(0)
+        lat.find_vortices(0)
     f = lat.fields(("n",))[0]["n"]
     assert f.shape == (4, 5, 6)
     ref = (np.abs(lat.get_psi()[0].cpu().numpy()) ** 2).sum(0)
