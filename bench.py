@@ -240,10 +240,10 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
 
 
 def diagnostics(workload, dtype, reps):
-    """Per-site fields (Sec. III) and, in 2D and 3D, the vorticity of m = +2 (Sec. VI; in 3D its
-    three plane families) on the workload's lattice after 20 steps: average time per call over
-    `reps` back-to-back calls, from HIP events on the library's stream, against the algorithmic
-    HBM bytes of each kernel."""
+    """Per-site fields (Sec. III) and, in 2D and 3D, the vorticity of m = +2 (Sec. VI; in 3D
+    its three plane families, fused in one kernel) on the workload's lattice after 20 steps:
+    average time per call over `reps` back-to-back calls, from HIP events on the library's
+    stream, against the algorithmic HBM bytes of each kernel."""
     import torch
     from paper_1907_12834_amd.qlg import lib
 
@@ -259,11 +259,11 @@ def diagnostics(workload, dtype, reps):
     elem = 8 if dtype == "c64" else 16
     L = lib()
     # bytes per site: the 10 qubit amplitudes read and 4 doubles written; a_m, b_m read
-    # and one double and one int32 written (per plane family in 3D)
+    # and one double and one int32 written per plane family (three in 3D, from one pass)
     calls = {"k_fields": (lambda: L.qlg_fields(lat.ctx, *[t.data_ptr() for t in outs]), 10 * elem + 32)}
     if ndim >= 2:
         calls["k_vorticity"] = (lambda: L.qlg_vorticity(lat.ctx, 0, outs[0].data_ptr(), wind.data_ptr()),
-                                ncomp * (2 * elem + 12))
+                                2 * elem + 12 * ncomp)
     res = {"lattice_sites": n, "storage": dtype}
     for name, (fn, bsite) in calls.items():
         for _ in range(5):

@@ -12,17 +12,11 @@ namespace qlg {
 hipError_t launch_fields(int dtype, const void* state, const LaunchGeom& g, double* n, double* f_par,
                          double* f_perp, double* a00, hipStream_t st);
 
-// One family of lattice planes of an instance: the u and v axes of the planes (extents
-// and site strides) and the planes along the third axis (count, site stride).
-struct PlaneFamily {
-  int32_t nu, nv, np;
-  int64_t su, sv, sp;
-};
-
 // Vorticity (FP64) and plaquette winding numbers (int32) of component m of one
 // instance, written at the instance's place in the canonical scalar layout; a
 // NULL output is skipped.  2D: one component.  3D: the three plane families,
-// normal to x, y and z, component c at offset c * component_stride.
+// normal to x, y and z, component c at offset c * component_stride, from one
+// fused pass over the lattice.
 hipError_t launch_vorticity(int dtype, int ndim, const void* state, const InstDesc& d, int m, double* omega,
                             int32_t* winding, int64_t component_stride, hipStream_t st);
 

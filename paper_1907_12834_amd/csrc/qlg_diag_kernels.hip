@@ -72,7 +72,14 @@ __global__ __launch_bounds__(kChunk) void k_fields(const cx<T>* __restrict__ st,
 // issuing every load of a thread before the first atan2, then stores the
 // phases in LDS; every thread then reads its neighbours from there.
 // Floating-point contraction is off so that each difference, product and sum
-// rounds once, in the order written.
+// rounds once, in the order written.  The kernel takes its plane as a family
+// (u and v axes with their extents and site strides, planes along a third
+// axis); a 2D lattice is the one family u = x, v = y.
+struct PlaneFamily {
+  int32_t nu, nv, np;
+  int64_t su, sv, sp;
+};
+
 constexpr int kVortW = 64, kVortH = 32, kVortThreads = 256;
 constexpr int kVortLW = kVortW + 2, kVortLH = kVortH + 2;
 constexpr int kVortLoads = (kVortLW * kVortLH + kVortThreads - 1) / kVortThreads;
@@ -94,6 +101,27 @@ __device__ __forceinline__ uint32_t wrap_coord(int64_t c, int32_t n) {
   uint32_t u = (uint32_t)c;
   if (u >= (uint32_t)n) u = u - (uint32_t)n < (uint32_t)n ? u - (uint32_t)n : u % (uint32_t)n;
   return u;
+}
+
+// The curl at (u, v) of a plane from the phases at its four diagonal neighbours
+// pp = S(u+1, v+1), pm = S(u+1, v-1), mp = S(u-1, v+1), mm = S(u-1, v-1): the
+// velocities v_v(u+1), v_v(u-1), v_u(v+1), v_u(v-1) as wrapped half differences,
+// then (v_v(u+1) - v_v(u-1) - v_u(v+1) + v_u(v-1)) / 2 in that order.
+__device__ __forceinline__ double curl_of(double pp, double pm, double mp, double mm) {
+#pragma clang fp contract(off)
+  const double vv_p = wrap_pi(pp - pm) / 2.0;
+  const double vv_m = wrap_pi(mp - mm) / 2.0;
+  const double vu_p = wrap_pi(pp - mp) / 2.0;
+  const double vu_m = wrap_pi(pm - mm) / 2.0;
+  return (((vv_p - vv_m) - vu_p) + vu_m) / 2.0;
+}
+
+// The winding of the plaquette (u, v) -> (u+1, v) -> (u+1, v+1) -> (u, v+1)
+// from the phases at its corners in that order.
+__device__ __forceinline__ int32_t winding_of(double s00, double s10, double s11, double s01) {
+#pragma clang fp contract(off)
+  const double circ = ((wrap_pi(s10 - s00) + wrap_pi(s11 - s10)) + wrap_pi(s01 - s11)) + wrap_pi(s00 - s01);
+  return (int32_t)rint(circ / kTwoPi);
 }
 
 template <typename T>
@@ -134,17 +162,107 @@ __global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restr
     if (y >= f.nv) break;
     const int j = k + 1, i = lx + 1;
     const int64_t o = base + y * f.sv + x * f.su;
-    if (omega_out) {
-      const double vy_p = wrap_pi(S[j + 1][i + 1] - S[j - 1][i + 1]) / 2.0;
-      const double vy_m = wrap_pi(S[j + 1][i - 1] - S[j - 1][i - 1]) / 2.0;
-      const double vx_p = wrap_pi(S[j + 1][i + 1] - S[j + 1][i - 1]) / 2.0;
-      const double vx_m = wrap_pi(S[j - 1][i + 1] - S[j - 1][i - 1]) / 2.0;
-      omega_out[o] = (((vy_p - vy_m) - vx_p) + vx_m) / 2.0;
-    }
-    if (wind_out) {
-      const double s00 = S[j][i], s10 = S[j][i + 1], s11 = S[j + 1][i + 1], s01 = S[j + 1][i];
-      const double circ = ((wrap_pi(s10 - s00) + wrap_pi(s11 - s10)) + wrap_pi(s01 - s11)) + wrap_pi(s00 - s01);
-      wind_out[o] = (int32_t)rint(circ / kTwoPi);
+    if (omega_out) omega_out[o] = curl_of(S[j + 1][i + 1], S[j - 1][i + 1], S[j + 1][i - 1], S[j - 1][i - 1]);
+    if (wind_out) wind_out[o] = winding_of(S[j][i], S[j][i + 1], S[j + 1][i + 1], S[j + 1][i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vorticity and windings of all three plane families of a 3D lattice, fused
+// ---------------------------------------------------------------------------
+// The planes normal to x (u = y, v = z), to y (u = z, v = x) and to z (u = x,
+// v = y) each take the 2D rule above; every output at (x, y, z) needs the phase
+// only at offsets in {-1, 0, 1}^3 with at most two non-zero.  A workgroup owns a
+// 64 x 16 tile of (x, y) columns and marches over kV3Z consecutive z: the phases
+// of the tile and its one-site halo in x and y sit in LDS for four z slices, a
+// ring in which slice z+1 is written while z-1, z and z+1 of the previous step
+// are no longer read, so one barrier per z step suffices.  psi of slice z+2 is
+// loaded into registers before the outputs of slice z are computed, and turned
+// into phases at the start of the next step.  Each site's phase is thus taken
+// once per 1.16 x (1 + 2 / kV3Z) sites instead of three times, psi is read once
+// instead of once per family, and every store runs along x.
+constexpr int kV3W = 64, kV3H = 16, kV3Z = 16, kV3Threads = 256;
+constexpr int kV3LW = kV3W + 2, kV3LH = kV3H + 2, kV3Slots = 4;
+constexpr int kV3Loads = (kV3LW * kV3LH + kV3Threads - 1) / kV3Threads;
+
+template <typename T>
+__global__ __launch_bounds__(kV3Threads) void k_vorticity3d(const cx<T>* __restrict__ st, InstDesc d, int m,
+                                                           int64_t block0, int64_t cstride,
+                                                           double* __restrict__ omega_out,
+                                                           int32_t* __restrict__ wind_out) {
+#pragma clang fp contract(off)
+  __shared__ double P[kV3Slots][kV3LH][kV3LW];
+  const int64_t ntx = (d.nx + kV3W - 1) / kV3W, nty = (d.ny + kV3H - 1) / kV3H;
+  // the workgroups one XCD runs (every eighth in launch order) take consecutive
+  // tiles, so the halo lines shared by x and y neighbours meet in one L2
+  int64_t blk = blockIdx.x;
+  if (gridDim.x % 8 == 0) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  blk += block0;
+  const int64_t x0 = (blk % ntx) * kV3W, y0 = ((blk / ntx) % nty) * kV3H, z0 = (blk / (ntx * nty)) * kV3Z;
+  const int64_t nxy = (int64_t)d.nx * d.ny;
+  const int nzl = (int)((int64_t)d.nz - z0 < kV3Z ? (int64_t)d.nz - z0 : kV3Z);
+  const cx<T>* pa = st + d.off + (int64_t)m * d.stride;
+  const cx<T>* pb = st + d.off + (int64_t)(5 + m) * d.stride;
+  // in-plane offsets of this thread's halo-tile elements, the same for every slice
+  int64_t ofs[kV3Loads];
+#pragma unroll
+  for (int r = 0; r < kV3Loads; ++r) {
+    const int i = threadIdx.x + r * kV3Threads;
+    const int ly = i / kV3LW, lx = i - ly * kV3LW;
+    ofs[r] = i < kV3LW * kV3LH
+                 ? (int64_t)wrap_coord(y0 - 1 + ly, d.ny) * d.nx + (int64_t)wrap_coord(x0 - 1 + lx, d.nx)
+                 : -1;
+  }
+  cx<T> v[kV3Loads];
+  auto load = [&](int64_t z) {
+    const int64_t zo = (int64_t)wrap_coord(z, d.nz) * nxy;
+#pragma unroll
+    for (int r = 0; r < kV3Loads; ++r)
+      if (ofs[r] >= 0) v[r] = pa[zo + ofs[r]] + pb[zo + ofs[r]];
+  };
+  auto store_phases = [&](int slot) {
+#pragma unroll
+    for (int r = 0; r < kV3Loads; ++r)
+      if (ofs[r] >= 0) (&P[slot][0][0])[threadIdx.x + r * kV3Threads] = phase_of((double)v[r].re, (double)v[r].im);
+  };
+  // slot of slice z is (z - z0 + 1) mod 4: z0 - 1 in slot 0, z0 in slot 1
+  load(z0 - 1);
+  store_phases(0);
+  load(z0);
+  store_phases(1);
+  load(z0 + 1);
+  const int lane = threadIdx.x % kV3W;
+  const int64_t x = x0 + lane;
+  const int i = lane + 1;
+  const int64_t base = d.psi_off / 5;
+  for (int k = 0; k < nzl; ++k) {
+    const int sm = k % kV3Slots, s0 = (k + 1) % kV3Slots, sp = (k + 2) % kV3Slots;
+    store_phases(sp);
+    if (k + 1 < nzl) load(z0 + k + 2);
+    __syncthreads();
+    if (x < d.nx) {
+      const int64_t z = z0 + k;
+      for (int r = threadIdx.x / kV3W; r < kV3H; r += kV3Threads / kV3W) {
+        const int64_t y = y0 + r;
+        if (y >= d.ny) break;
+        const int j = r + 1;
+        const int64_t o = base + z * nxy + y * d.nx + x;
+        const double c = P[s0][j][i];
+        if (omega_out) {
+          // normal x: u = y, v = z
+          omega_out[o] = curl_of(P[sp][j + 1][i], P[sm][j + 1][i], P[sp][j - 1][i], P[sm][j - 1][i]);
+          // normal y: u = z, v = x
+          omega_out[cstride + o] = curl_of(P[sp][j][i + 1], P[sp][j][i - 1], P[sm][j][i + 1], P[sm][j][i - 1]);
+          // normal z: u = x, v = y
+          omega_out[2 * cstride + o] =
+              curl_of(P[s0][j + 1][i + 1], P[s0][j - 1][i + 1], P[s0][j + 1][i - 1], P[s0][j - 1][i - 1]);
+        }
+        if (wind_out) {
+          wind_out[o] = winding_of(c, P[s0][j + 1][i], P[sp][j + 1][i], P[sp][j][i]);
+          wind_out[cstride + o] = winding_of(c, P[sp][j][i], P[sp][j][i + 1], P[s0][j][i + 1]);
+          wind_out[2 * cstride + o] = winding_of(c, P[s0][j][i + 1], P[s0][j + 1][i + 1], P[s0][j + 1][i]);
+        }
+      }
     }
   }
 }
@@ -261,16 +379,19 @@ static hipError_t launch_family(int dtype, const void* state, const InstDesc& d,
 
 hipError_t launch_vorticity(int dtype, int ndim, const void* state, const InstDesc& d, int m, double* omega,
                             int32_t* winding, int64_t component_stride, hipStream_t st) {
-  const int64_t nx = d.nx, nxy = (int64_t)d.nx * d.ny;
-  if (ndim == 2) return launch_family(dtype, state, d, PlaneFamily{d.nx, d.ny, 1, 1, nx, 0}, m, omega, winding, st);
-  // 3D: the plaquettes normal to x (u = y, v = z), to y (u = z, v = x) and to z (u = x, v = y),
-  // one after the other in the outputs
-  const PlaneFamily fam[3] = {PlaneFamily{d.ny, d.nz, d.nx, nx, nxy, 1},
-                              PlaneFamily{d.nz, d.nx, d.ny, nxy, 1, nx},
-                              PlaneFamily{d.nx, d.ny, d.nz, 1, nx, nxy}};
-  for (int c = 0; c < 3; ++c) {
-    const hipError_t e = launch_family(dtype, state, d, fam[c], m, omega ? omega + c * component_stride : nullptr,
-                                       winding ? winding + c * component_stride : nullptr, st);
+  if (ndim == 2) return launch_family(dtype, state, d, PlaneFamily{d.nx, d.ny, 1, 1, d.nx, 0}, m, omega, winding, st);
+  // 3D: the families normal to x, y and z, one after the other in the outputs, in one pass
+  constexpr int64_t kPiece = int64_t(1) << 22;
+  const int64_t nb = (int64_t)((d.nx + kV3W - 1) / kV3W) * ((d.ny + kV3H - 1) / kV3H) * ((d.nz + kV3Z - 1) / kV3Z);
+  for (int64_t b0 = 0; b0 < nb; b0 += kPiece) {
+    const unsigned n = (unsigned)(nb - b0 < kPiece ? nb - b0 : kPiece);
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_vorticity3d<float>, dim3(n), dim3(kV3Threads), 0, st, (const cx<float>*)state, d, m, b0,
+                         component_stride, omega, winding);
+    else
+      hipLaunchKernelGGL(k_vorticity3d<double>, dim3(n), dim3(kV3Threads), 0, st, (const cx<double>*)state, d, m,
+                         b0, component_stride, omega, winding);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -205,8 +205,10 @@ def test_3d_vortex_lines_512_light_cone():
 def test_3d_vorticity_random_ragged_batch(dtype):
     """The three plane families of a 3D state (instances of different shapes, 1- and 2-site
     extents included) against the oracle on the GPU's own psi: windings exact, omega to rounding
-    (both sides take the same FP64 differences of the same phases in the same order)."""
-    shapes = [(5, 7, 70), (3, 20, 9), (1, 1, 1), (2, 1, 65), (34, 3, 2)]
+    (both sides take the same FP64 differences of the same phases in the same order).  The
+    shapes put ragged 64-site x tiles, 16-row y tiles and 16-slice z runs at the edges; the
+    17 x 17 x 65 instance has eight workgroups, the case whose tiles are regrouped by XCD."""
+    shapes = [(5, 7, 70), (3, 20, 9), (1, 1, 1), (2, 1, 65), (34, 3, 2), (17, 17, 65)]
     lat = lattice3(shapes, g=(1.0, -0.3, 0.5), eps=0.4, dtype=dtype)
     lat.set_psi([torch.from_numpy(qi.random_field(sh, seed=80 + i)) for i, sh in enumerate(shapes)])
     lat.step(2)
