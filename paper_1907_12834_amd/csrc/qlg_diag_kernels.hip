@@ -117,11 +117,15 @@ __device__ __forceinline__ double curl_of(double pp, double pm, double mp, doubl
 }
 
 // The winding of the plaquette (u, v) -> (u+1, v) -> (u+1, v+1) -> (u, v+1)
-// from the phases at its corners in that order.
+// from the phases at its corners in that order.  The four unwrapped differences
+// sum to zero and each reduction adds a multiple of the double 2 pi, so circ is a
+// multiple of 2 pi to within a few units in the last place: circ / (2 pi) and
+// circ * (1 / (2 pi)) both lie within 1e-14 of the same integer and round to it.
 __device__ __forceinline__ int32_t winding_of(double s00, double s10, double s11, double s01) {
 #pragma clang fp contract(off)
+  constexpr double kInvTwoPi = 0.15915494309189535;
   const double circ = ((wrap_pi(s10 - s00) + wrap_pi(s11 - s10)) + wrap_pi(s01 - s11)) + wrap_pi(s00 - s01);
-  return (int32_t)rint(circ / kTwoPi);
+  return (int32_t)rint(circ * kInvTwoPi);
 }
 
 template <typename T>
@@ -133,7 +137,12 @@ __global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restr
   __shared__ double S[kVortLH][kVortLW];
   // tile (u0, v0) of plane p: the x, y of the comments above are u, v of the family
   const int64_t ntu = (f.nu + kVortW - 1) / kVortW, ntv = (f.nv + kVortH - 1) / kVortH;
-  const int64_t blk = block0 + blockIdx.x, tq = blk / ntu;
+  // the workgroups one XCD runs (every eighth in launch order) take consecutive
+  // tiles, so the halo lines shared by neighbouring tiles meet in one L2
+  int64_t blk = blockIdx.x;
+  if (gridDim.x % 8 == 0) blk = (blk % 8) * (gridDim.x / 8) + blk / 8;
+  blk += block0;
+  const int64_t tq = blk / ntu;
   const int64_t x0 = (blk % ntu) * kVortW, y0 = (tq % ntv) * kVortH, pofs = (tq / ntv) * f.sp;
   const cx<T>* pa = st + d.off + (int64_t)m * d.stride + pofs;
   const cx<T>* pb = st + d.off + (int64_t)(5 + m) * d.stride + pofs;
