@@ -199,6 +199,15 @@ def test_3d_vortex_lines_512_light_cone():
         assert np.abs(g_ - ref).max() <= 1e-5 * np.abs(ref).max(), (cz, cy, cx, g_, ref)
     o = lat.observables()[0]
     assert abs(o["norm_q"] / (0.5 * w.eps ** 3 * (np.abs(w.psi[0]) ** 2).sum()) - 1) < 1e-5
+    # the fused vorticity pass at 8192 workgroups (tiles regrouped by XCD): sampled planes of
+    # each family against the oracle's 2D rule on the GPU's own psi of m = +2, sliced on the device
+    r = lat.vorticity(0)[0]
+    psi0 = got[0]
+    for k in (0, 257, n - 1):
+        for c, sel in ((0, lambda a: a[..., k]), (1, lambda a: a[:, k, :].T), (2, lambda a: a[k])):
+            o2, w2 = O.vorticity(sel(psi0).cpu().numpy())
+            assert np.array_equal(sel(r["winding"][c]).cpu().numpy(), w2), (c, k)
+            assert np.abs(sel(r["omega"][c]).cpu().numpy() - o2).max() <= 1e-12, (c, k)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -222,12 +231,13 @@ def test_3d_vorticity_random_ragged_batch(dtype):
             assert np.abs(res[i]["omega"].cpu().numpy() - om).max() <= 1e-12, (m, i)
 
 
-def test_3d_vortex_lines_vorticity_full_size():
-    """The 256^3 vortex-line workload after 3 steps (complex64): windings and omega of sampled
-    planes of each family against the oracle's lattice vorticity of that plane."""
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_3d_vortex_lines_vorticity_full_size(dtype):
+    """The 256^3 vortex-line workload after 3 steps: windings and omega of sampled planes of each
+    family against the oracle's lattice vorticity of that plane."""
     w = qi.vortex_lines_3d_256(nsteps=3)
     n = w.nx[0]
-    lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype="c64")
+    lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype=dtype)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     lat.step(3)
     psi0 = lat.get_psi()[0][0].cpu().numpy()          # m = +2, [z][y][x]
