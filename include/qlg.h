@@ -196,14 +196,18 @@ qlg_status qlg_vorticity(qlg_ctx* ctx, int32_t m_index, double* omega_dev, int32
  * run (Sec. VI follows every core of every channel over time): the plaquettes
  * whose winding number, as qlg_vorticity defines it, is non-zero, listed in
  * the order (instance, y, x) as cores_dev[k] = {instance, y, x, winding}
- * (int32 x 4; (y, x) is the plaquette's lower-left corner).  At most capacity
- * entries are written; count_dev[0] (device int64) receives the number of
- * cores, which may exceed capacity (call again with a larger buffer).
- * winding_dev (device, nbatch * sites int32, canonical scalar layout) is
- * filled with the winding field on the way.  The order is deterministic (no
- * atomics).  QLG_ERR_SHAPE for a lattice that is not 2D; QLG_ERR_ARG for
- * m_index outside 0..4, NULL winding_dev or count_dev, capacity < 0, or
- * capacity > 0 with NULL cores_dev.  Asynchronous on the context's stream. */
+ * (int32 x 4; (y, x) is the plaquette's lower-left corner).  On a 3D lattice
+ * the plaquettes of the three plane families are listed, in the order (family,
+ * instance, z, y, x), as cores_dev[k] = {instance, family, z, y, x, winding}
+ * (int32 x 6; family 0, 1, 2 = normal to x, y, z as in qlg_vorticity; (z, y, x)
+ * is the plaquette's first corner).  At most capacity entries are written;
+ * count_dev[0] (device int64) receives the number of cores, which may exceed
+ * capacity (call again with a larger buffer).  winding_dev (device, int32 in
+ * the canonical scalar layout: nbatch * sites in 2D, 3 x that in 3D) is filled
+ * with the winding field on the way.  The order is deterministic (no
+ * atomics).  QLG_ERR_SHAPE for a 1D lattice; QLG_ERR_ARG for m_index outside
+ * 0..4, NULL winding_dev or count_dev, capacity < 0, or capacity > 0 with NULL
+ * cores_dev.  Asynchronous on the context's stream. */
 qlg_status qlg_find_vortices(qlg_ctx* ctx, int32_t m_index, int32_t* winding_dev, int32_t* cores_dev,
                              int64_t capacity, int64_t* count_dev);
 

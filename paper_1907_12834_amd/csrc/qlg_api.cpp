@@ -533,18 +533,22 @@ qlg_status qlg_find_vortices(qlg_ctx* c, int32_t m_index, int32_t* winding, int3
                              int64_t* count) {
   qlg_status s = check_ctx(c);
   if (s) return s;
-  if (c->p.ndim != 2) return fail(c, QLG_ERR_SHAPE, "vortex cores need a 2D lattice");
+  if (c->p.ndim < 2) return fail(c, QLG_ERR_SHAPE, "vortex cores need a 2D or 3D lattice");
   if (m_index < 0 || m_index > 4) return fail(c, QLG_ERR_ARG, "m_index must be in 0..4");
   if (!winding || !count) return fail(c, QLG_ERR_ARG, "winding or count is NULL");
   if (capacity < 0 || (capacity > 0 && !cores)) return fail(c, QLG_ERR_ARG, "bad capacity or NULL cores");
   for (const qlg::InstDesc& d : c->L.inst) {
-    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, 2, c->copy(c->cur), d, m_index, nullptr, winding,
+    s = hip_check(c, qlg::launch_vorticity(c->p.dtype, c->p.ndim, c->copy(c->cur), d, m_index, nullptr, winding,
                                            c->L.psi_elems / 5, c->stream),
                   "vorticity kernel");
     if (s) return s;
   }
-  int64_t* counts = reinterpret_cast<int64_t*>(c->sc(c->S.obs_part));   // nchunks int64 fit in the partials
-  return hip_check(c, qlg::launch_vortex_cores(winding, c->geom(), counts, cores, capacity, count, c->stream),
+  // the counts of one chunk per plane family (three in 3D) fit in the kNObs doubles per chunk
+  // of the observables' partials
+  static_assert(qlg::kNObs >= 3, "core counts need three int64 per chunk");
+  int64_t* counts = reinterpret_cast<int64_t*>(c->sc(c->S.obs_part));
+  return hip_check(c, qlg::launch_vortex_cores(winding, c->geom(), c->p.ndim, c->L.psi_elems / 5, counts, cores,
+                                               capacity, count, c->stream),
                    "vortex core kernels");
 }
 

@@ -21,9 +21,12 @@ hipError_t launch_vorticity(int dtype, int ndim, const void* state, const InstDe
                             int32_t* winding, int64_t component_stride, hipStream_t st);
 
 // The non-zero entries of a winding field (canonical scalar layout) as an ordered
-// list out[k] = {instance, y, x, winding}, k < capacity; *total (device) receives
-// the number of cores.  counts: nchunks int64 of workspace.
-hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int64_t* counts, int32_t* out,
-                               int64_t capacity, int64_t* total, hipStream_t st);
+// list, k < capacity: 2D out[k] = {instance, y, x, winding}; 3D, whose winding
+// field holds the three plane families at component_stride from each other,
+// out[k] = {instance, family, z, y, x, winding} in (family, instance, z, y, x)
+// order.  *total (device) receives the number of cores.  counts: nchunks int64
+// of workspace per family.
+hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int ndim, int64_t component_stride,
+                               int64_t* counts, int32_t* out, int64_t capacity, int64_t* total, hipStream_t st);
 
 }  // namespace qlg

@@ -279,19 +279,22 @@ __global__ __launch_bounds__(kV3Threads) void k_vorticity3d(const cx<T>* __restr
 // ---------------------------------------------------------------------------
 // Vortex cores: the plaquettes with a non-zero winding, as an ordered list
 // ---------------------------------------------------------------------------
-// Three launches, no atomics, so the list is in (instance, y, x) order on every
-// run: the non-zero count of every 256-site chunk; one workgroup's exclusive
-// scan of the counts (the chunks of an instance are consecutive, and so are the
-// instances); then every chunk writes its cores at its offset, ranked inside the
-// chunk by wave ballots.
+// Three launches, no atomics, so the list is in (family, instance, z, y, x)
+// order on every run: the non-zero count of every 256-site chunk of every plane
+// family (one family in 2D, three in 3D); one workgroup's exclusive scan of the
+// counts (the chunks of an instance are consecutive, then the instances, then
+// the families); then every chunk writes its cores at its offset, ranked inside
+// the chunk by wave ballots.  Workgroup b takes family b / nchunks and chunk
+// b % nchunks; family c's windings sit at c * cstride.
 __global__ __launch_bounds__(kChunk) void k_core_count(const int32_t* __restrict__ wind, LaunchGeom g,
-                                                      int64_t* __restrict__ counts) {
+                                                      int64_t cstride, int64_t* __restrict__ counts) {
   __shared__ int wsum[kChunk / kLanes];
-  const InstDesc d = g.inst[g.chunk2inst[blockIdx.x]];
-  const int s = (blockIdx.x - d.chunk_begin) * kChunk + threadIdx.x;
-  const bool core = s < d.sites && wind[d.psi_off / 5 + s] != 0;
-  const int c = __popcll(__ballot(core));
-  if ((threadIdx.x & (kLanes - 1)) == 0) wsum[threadIdx.x / kLanes] = c;
+  const int c = blockIdx.x / g.nchunks, b = blockIdx.x - c * g.nchunks;
+  const InstDesc d = g.inst[g.chunk2inst[b]];
+  const int s = (b - d.chunk_begin) * kChunk + threadIdx.x;
+  const bool core = s < d.sites && wind[c * cstride + d.psi_off / 5 + s] != 0;
+  const int n = __popcll(__ballot(core));
+  if ((threadIdx.x & (kLanes - 1)) == 0) wsum[threadIdx.x / kLanes] = n;
   __syncthreads();
   if (threadIdx.x == 0) {
     int t = 0;
@@ -327,13 +330,15 @@ __global__ __launch_bounds__(kScanThreads) void k_core_scan(int64_t* __restrict_
 }
 
 __global__ __launch_bounds__(kChunk) void k_core_scatter(const int32_t* __restrict__ wind, LaunchGeom g,
+                                                        int ndim, int64_t cstride,
                                                         const int64_t* __restrict__ offsets,
                                                         int32_t* __restrict__ out, int64_t capacity) {
   __shared__ int wsum[kChunk / kLanes];
-  const int inst = g.chunk2inst[blockIdx.x];
+  const int c = blockIdx.x / g.nchunks, b = blockIdx.x - c * g.nchunks;
+  const int inst = g.chunk2inst[b];
   const InstDesc d = g.inst[inst];
-  const int s = (blockIdx.x - d.chunk_begin) * kChunk + threadIdx.x;
-  const int32_t w = s < d.sites ? wind[d.psi_off / 5 + s] : 0;
+  const int s = (b - d.chunk_begin) * kChunk + threadIdx.x;
+  const int32_t w = s < d.sites ? wind[c * cstride + d.psi_off / 5 + s] : 0;
   const unsigned long long mask = __ballot(w != 0);
   const int lane = threadIdx.x & (kLanes - 1), wv = threadIdx.x / kLanes;
   if (lane == 0) wsum[wv] = __popcll(mask);
@@ -342,11 +347,22 @@ __global__ __launch_bounds__(kChunk) void k_core_scatter(const int32_t* __restri
   int64_t k = offsets[blockIdx.x] + __popcll(mask & ((1ull << lane) - 1ull));
   for (int j = 0; j < wv; ++j) k += wsum[j];
   if (k >= capacity) return;
-  int32_t* e = out + 4 * k;
-  e[0] = inst;
-  e[1] = s / d.nx;
-  e[2] = s % d.nx;
-  e[3] = w;
+  if (ndim == 3) {
+    const int nxy = d.nx * d.ny;
+    int32_t* e = out + 6 * k;
+    e[0] = inst;
+    e[1] = c;
+    e[2] = s / nxy;
+    e[3] = (s % nxy) / d.nx;
+    e[4] = s % d.nx;
+    e[5] = w;
+  } else {
+    int32_t* e = out + 4 * k;
+    e[0] = inst;
+    e[1] = s / d.nx;
+    e[2] = s % d.nx;
+    e[3] = w;
+  }
 }
 
 }  // namespace
@@ -406,16 +422,18 @@ hipError_t launch_vorticity(int dtype, int ndim, const void* state, const InstDe
   return hipSuccess;
 }
 
-hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int64_t* counts, int32_t* out,
-                               int64_t capacity, int64_t* total, hipStream_t st) {
+hipError_t launch_vortex_cores(const int32_t* winding, const LaunchGeom& g, int ndim, int64_t component_stride,
+                               int64_t* counts, int32_t* out, int64_t capacity, int64_t* total, hipStream_t st) {
   if (g.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_core_count, dim3(g.nchunks), dim3(kChunk), 0, st, winding, g, counts);
+  const int nblocks = (ndim == 3 ? 3 : 1) * g.nchunks;
+  hipLaunchKernelGGL(k_core_count, dim3(nblocks), dim3(kChunk), 0, st, winding, g, component_stride, counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_core_scan, dim3(1), dim3(kScanThreads), 0, st, counts, g.nchunks, total);
+  hipLaunchKernelGGL(k_core_scan, dim3(1), dim3(kScanThreads), 0, st, counts, nblocks, total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_core_scatter, dim3(g.nchunks), dim3(kChunk), 0, st, winding, g, counts, out, capacity);
+  hipLaunchKernelGGL(k_core_scatter, dim3(nblocks), dim3(kChunk), 0, st, winding, g, ndim, component_stride, counts,
+                     out, capacity);
   return hipGetLastError();
 }
 

@@ -313,12 +313,15 @@ class Lattice:
         return out
 
     def find_vortices(self, m_index: int, capacity: int = 4096) -> torch.Tensor:
-        """Vortex cores of component m_index (Sec. VI): an int32 tensor (k, 4) of
-        (instance, y, x, winding) rows in (instance, y, x) order, on the device."""
-        wind = torch.empty(self.sites, dtype=torch.int32, device=self.device)
+        """Vortex cores of component m_index (Sec. VI): an int32 tensor on the device, (k, 4) of
+        (instance, y, x, winding) rows in (instance, y, x) order in 2D; (k, 6) of (instance,
+        family, z, y, x, winding) rows in (family, instance, z, y, x) order in 3D, family 0, 1, 2
+        the plaquettes normal to x, y, z."""
+        ncomp, width = (3, 6) if self.ndim == 3 else (1, 4)
+        wind = torch.empty(ncomp * self.sites, dtype=torch.int32, device=self.device)
         count = torch.zeros(1, dtype=torch.int64, device=self.device)
         while True:
-            cores = torch.empty((max(int(capacity), 1), 4), dtype=torch.int32, device=self.device)
+            cores = torch.empty((max(int(capacity), 1), width), dtype=torch.int32, device=self.device)
             self._check(lib().qlg_find_vortices(self.ctx, int(m_index), wind.data_ptr(), cores.data_ptr(),
                                                 int(capacity), count.data_ptr()), "qlg_find_vortices")
             n = int(count.item())
@@ -328,7 +331,8 @@ class Lattice:
 
     def track_vortices(self, m_index: int, nsteps: int, every: int) -> List[tuple]:
         """Advance nsteps, listing the cores of component m_index every `every` steps (and at the
-        start): [(step, cores (k, 4) on the device), ...], the paper's vortex tracks."""
+        start): [(step, cores on the device as find_vortices returns them), ...], the paper's
+        vortex tracks."""
         out = [(0, self.find_vortices(m_index))]
         done = 0
         while done < nsteps:

@@ -7,7 +7,7 @@ several band heights, both splits; batched 3D instances of different sizes;
 observables and the overlap energy; a potential; graph replay; the exact
 reduction of a z-uniform free field to the 2D step; the 256^3 and 512^3
 vortex-line states at full size on light-cone windows; and the lattice
-vorticity of the three plane families.
+vorticity of the three plane families and their vortex-core lists.
 """
 import numpy as np
 import pytest
@@ -257,12 +257,72 @@ def test_3d_vortex_lines_vorticity_full_size(dtype):
         assert (wd[2, z] == 1).any() and int(wd[2, z].sum()) == 0
 
 
-def test_3d_calls_that_need_a_lower_dimension():
+def oracle_cores3(psis, m_index):
+    """(instance, family, z, y, x, winding) of every non-zero winding of the oracle's three plane
+    families, in (family, instance, z, y, x) order."""
+    per = [O.vorticity(p[m_index])[1] for p in psis]
+    rows = []
+    for c in range(3):
+        for i, wd in enumerate(per):
+            rows += [(i, c, int(z), int(y), int(x), int(wd[c, z, y, x])) for z, y, x in np.argwhere(wd[c])]
+    return np.array(rows, dtype=np.int64).reshape(-1, 6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_3d_find_vortices_ragged_batch(dtype):
+    """Core lists of the three plane families of random fields on ragged 3D instances (1-site
+    extents included) equal the oracle's, entry by entry and in order; a capacity below the count
+    writes the first entries and reports the full count; the winding output holds all three
+    families."""
+    from paper_1907_12834_amd.qlg import lib
+    shapes = [(5, 7, 70), (3, 20, 9), (1, 1, 1), (2, 1, 65), (17, 17, 65)]
+    lat = lattice3(shapes, g=(1.0, -0.3, 0.5), eps=0.4, dtype=dtype)
+    lat.set_psi([torch.from_numpy(qi.random_field(sh, seed=90 + i)) for i, sh in enumerate(shapes)])
+    lat.step(2)
+    psis = [p.cpu().numpy() for p in lat.get_psi()]
+    for m in (0, 3):
+        ref = oracle_cores3(psis, m)
+        assert len(ref) > 1000 and set(ref[:, 1]) == {0, 1, 2}
+        got = lat.find_vortices(m, capacity=64).cpu().numpy()       # grows to the count by itself
+        assert got.shape == ref.shape and np.array_equal(got, ref), (m, got[:5], ref[:5])
+    wind = torch.empty(3 * lat.sites, dtype=torch.int32, device="cuda")
+    cores = torch.full((10, 6), -7, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert lib().qlg_find_vortices(lat.ctx, 0, wind.data_ptr(), cores.data_ptr(), 10, count.data_ptr()) == 0
+    ref = oracle_cores3(psis, 0)
+    assert int(count.item()) == len(ref) and np.array_equal(cores.cpu().numpy(), ref[:10])
+    r = lat.vorticity(0, omega=False)
+    flat = torch.cat([r[i]["winding"].reshape(3, -1) for i in range(len(shapes))], dim=1).reshape(-1)
+    assert torch.equal(wind, flat)
+
+
+def test_3d_vortex_lines_cores_full_size():
+    """The 256^3 vortex-line state after 3 steps (complex64): the core list of m = +2 equals the
+    non-zero windings of the vorticity output, and every z plane holds a core of the line that
+    crosses it, with windings of both signs summing to zero per plane."""
+    w = qi.vortex_lines_3d_256(nsteps=3)
+    n = w.nx[0]
+    lat = lattice3([(n, n, n)], g=w.g, eps=w.eps, dtype="c64")
+    lat.set_psi([torch.from_numpy(w.psi[0])])
+    lat.step(3)
+    wd = lat.vorticity(0, omega=False)[0]["winding"]
+    cores = lat.find_vortices(0).cpu().numpy()
+    nz = torch.nonzero(wd).cpu().numpy()                              # (family, z, y, x), row-major
+    assert np.array_equal(cores[:, 1:5], nz) and (cores[:, 0] == 0).all()
+    assert np.array_equal(cores[:, 5], wd[tuple(torch.from_numpy(nz).T.to(wd.device))].cpu().numpy())
+    zc = cores[cores[:, 1] == 2]
+    assert set(zc[:, 2]) == set(range(n))
+    for z in (0, 128, 255):
+        sel = zc[zc[:, 2] == z]
+        assert (sel[:, 5] == 1).any() and sel[:, 5].sum() == 0
+
+
+def test_3d_fields_and_core_errors():
     from paper_1907_12834_amd.qlg import QLGError
     lat = lattice3([(4, 5, 6)], g=(1.0, -0.3, 0.5), eps=0.4, dtype="c128")
     lat.set_psi([torch.from_numpy(qi.random_field((4, 5, 6), seed=2))])
-    with pytest.raises(QLGError, match="QLG_ERR_SHAPE"):
-        lat.find_vortices(0)
+    with pytest.raises(QLGError, match="QLG_ERR_ARG"):
+        lat.find_vortices(5)
     f = lat.fields(("n",))[0]["n"]
     assert f.shape == (4, 5, 6)
     ref = (np.abs(lat.get_psi()[0].cpu().numpy()) ** 2).sum(0)
