@@ -317,6 +317,23 @@ def test_3d_vortex_lines_cores_full_size():
         assert (sel[:, 5] == 1).any() and sel[:, 5].sum() == 0
 
 
+def test_3d_track_vortices_against_oracle_steps():
+    """Core lists of the three plane families every 2 steps of a 3D run (complex128) equal those
+    of the oracle's own run from the same initial field."""
+    shape = (6, 10, 14)
+    g, eps = (1.0, -0.3, 0.5), 0.4
+    psi0 = qi.random_field(shape, seed=33)
+    lat = lattice3([shape], g=g, eps=eps, dtype="c128")
+    lat.set_psi([torch.from_numpy(psi0)])
+    tracks = lat.track_vortices(3, 6, 2)
+    assert [t for t, _ in tracks] == [0, 2, 4, 6]
+    for t, cores in tracks:
+        A, B = O.run_psi(psi0, t, eps, g)
+        ref = oracle_cores3([(A + B).numpy()], 3)
+        assert len(ref) > 50
+        assert np.array_equal(cores.cpu().numpy(), ref), t
+
+
 def test_3d_fields_and_core_errors():
     from paper_1907_12834_amd.qlg import QLGError
     lat = lattice3([(4, 5, 6)], g=(1.0, -0.3, 0.5), eps=0.4, dtype="c128")
