@@ -259,10 +259,13 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
   block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
 }
 
-// acc[0..2] += sum over chunks of part (single block, fixed order).
+// acc[0..2] += sum over chunks of part (single block, fixed order).  Unrolling
+// issues the loads of eight chunks ahead of their additions; each thread still
+// adds its chunks in increasing order.
 __global__ __launch_bounds__(kChunk) void k_dg_accumulate(const double* __restrict__ part, int nchunks,
                                                          double* __restrict__ acc) {
   double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int c = threadIdx.x; c < nchunks; c += kChunk) {
     v[0] += part[3 * c];
     v[1] += part[3 * c + 1];
