@@ -184,12 +184,13 @@ __global__ __launch_bounds__(kVortThreads) void k_vorticity(const cx<T>* __restr
 // only at offsets in {-1, 0, 1}^3 with at most two non-zero.  A workgroup owns a
 // 64 x 16 tile of (x, y) columns and marches over kV3Z consecutive z: the phases
 // of the tile and its one-site halo in x and y sit in LDS for four z slices, a
-// ring in which slice z+1 is written while z-1, z and z+1 of the previous step
-// are no longer read, so one barrier per z step suffices.  psi of slice z+2 is
-// loaded into registers before the outputs of slice z are computed, and turned
-// into phases at the start of the next step.  Each site's phase is thus taken
-// once per 1.16 x (1 + 2 / kV3Z) sites instead of three times, psi is read once
-// instead of once per family, and every store runs along x.
+// ring in which slice z+1 overwrites slice z-3, last read two steps earlier,
+// before the previous step's barrier, so one barrier per z step suffices.  psi
+// of slice z+2 is loaded into registers before the outputs of slice z are
+// computed, and turned into phases at the start of the next step.  The phases
+// are thus computed 1.16 x (1 + 2 / kV3Z) = 1.31 times per site instead of 3.3
+// times, psi is read once instead of once per family, and every store runs
+// along x.
 constexpr int kV3W = 64, kV3H = 16, kV3Z = 16, kV3Threads = 256;
 constexpr int kV3LW = kV3W + 2, kV3LH = kV3H + 2, kV3Slots = 4;
 constexpr int kV3Loads = (kV3LW * kV3LH + kV3Threads - 1) / kV3Threads;
