@@ -67,8 +67,8 @@ __global__ __launch_bounds__(kChunk) void k_fields(const cx<T>* __restrict__ st,
 // the plaquette with corner (x, y) is the sum of the wrapped differences
 // around (x, y) -> (x+1, y) -> (x+1, y+1) -> (x, y+1), over 2 pi.
 //
-// A workgroup of 256 threads owns a 64 x 32 tile of outputs.  It loads psi_m
-// of the tile and a one-site periodic halo, 66 x 34 sites (1.10 per output),
+// A workgroup of 256 threads owns a 64 x 16 tile of outputs.  It loads psi_m
+// of the tile and a one-site periodic halo, 66 x 18 sites (1.16 per output),
 // issuing every load of a thread before the first atan2, then stores the
 // phases in LDS; every thread then reads its neighbours from there.
 // Floating-point contraction is off so that each difference, product and sum
@@ -80,7 +80,7 @@ struct PlaneFamily {
   int64_t su, sv, sp;
 };
 
-constexpr int kVortW = 64, kVortH = 32, kVortThreads = 256;
+constexpr int kVortW = 64, kVortH = 16, kVortThreads = 256;
 constexpr int kVortLW = kVortW + 2, kVortLH = kVortH + 2;
 constexpr int kVortLoads = (kVortLW * kVortLH + kVortThreads - 1) / kVortThreads;
 
