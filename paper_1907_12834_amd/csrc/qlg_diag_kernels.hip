@@ -21,6 +21,14 @@ constexpr double kTwoPi = 2.0 * kPi;
 // sqrt(6 - m(m+1)) psi*_{m+1} psi_m, F_x = Re F_+ and F_y = Im F_+, so
 // F_perp = sqrt(F_x^2 + F_y^2) = |F_+|; sigma = 2 psi_2 psi_-2 - 2 psi_1 psi_-1
 // + psi_0^2 is the singlet pair amplitude psi^T S psi.
+// One amplitude read once and not again by this kernel: loaded with the
+// non-temporal hint, which keeps the ten qubit planes streaming through the
+// caches without displacing lines still to be read.
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  return cx<T>{__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
+}
+
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_fields(const cx<T>* __restrict__ st, LaunchGeom g,
                                                   double* __restrict__ n_out, double* __restrict__ fpar_out,
@@ -31,7 +39,7 @@ __global__ __launch_bounds__(kChunk) void k_fields(const cx<T>* __restrict__ st,
   cx<double> p[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    const cx<T> v = st[d.off + m * d.stride + s] + st[d.off + (5 + m) * d.stride + s];
+    const cx<T> v = load_stream(st + d.off + m * d.stride + s) + load_stream(st + d.off + (5 + m) * d.stride + s);
     p[m] = cx<double>{(double)v.re, (double)v.im};
   }
   double q[5];
