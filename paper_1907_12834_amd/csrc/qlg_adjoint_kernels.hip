@@ -77,6 +77,34 @@ __device__ __forceinline__ void store_site(cx<T>* __restrict__ st, const InstDes
   }
 }
 
+// The same, with the non-temporal hint: for the recorded self-interaction
+// inputs, written once per segment recompute and read back once, by the
+// reverse sweep, so they need not displace lines the recompute still reads.
+template <typename T>
+__device__ __forceinline__ void store_site_nt(cx<T>* __restrict__ st, const InstDesc& d, int s, const cx<T> (&a)[5],
+                                              const cx<T> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    cx<T>* pa = st + d.off + m * d.stride + s;
+    cx<T>* pb = st + d.off + (5 + m) * d.stride + s;
+    __builtin_nontemporal_store(a[m].re, &pa->re);
+    __builtin_nontemporal_store(a[m].im, &pa->im);
+    __builtin_nontemporal_store(b[m].re, &pb->re);
+    __builtin_nontemporal_store(b[m].im, &pb->im);
+  }
+}
+template <typename T, typename S>
+__device__ __forceinline__ void load_site_nt(const cx<T>* __restrict__ st, const InstDesc& d, int s,
+                                             cx<S> (&a)[5], cx<S> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<T>* pa = st + d.off + m * d.stride + s;
+    const cx<T>* pb = st + d.off + (5 + m) * d.stride + s;
+    a[m] = cx<S>{(S)__builtin_nontemporal_load(&pa->re), (S)__builtin_nontemporal_load(&pa->im)};
+    b[m] = cx<S>{(S)__builtin_nontemporal_load(&pb->re), (S)__builtin_nontemporal_load(&pb->im)};
+  }
+}
+
 // C^H without its factor 1/2:  2 a' = (a + b) + i (a - b),  2 b' = (a + b) - i (a - b)
 __device__ __forceinline__ void collide2_adj(cx<double> (&a)[5], cx<double> (&b)[5]) {
 #pragma unroll
@@ -145,7 +173,7 @@ __global__ __launch_bounds__(kChunk) void k_chain(const cx<T>* __restrict__ in, 
   cx<T> a[5], b[5];
   if (axis >= 0) iprime_site(in, r, axis, qb, a, b);
   else load_site(in, r.d, r.s, a, b);
-  if (rec) store_site(rec, r.d, r.s, a, b);
+  if (rec) store_site_nt(rec, r.d, r.s, a, b);
   if (with_u) {
     // the same per-site angle as the fused forward kernels: T(theta) T(V + mu)
     if (pot || mu != 0.0) potential<T, true>(a, b, ang, T(theta) * T((pot ? pot[r.d.psi_off / 5 + r.s] : 0.0) + mu));
@@ -228,7 +256,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z,
   double dg[3] = {0.0, 0.0, 0.0};
   if (r.ok) {
     cx<double> a[5], b[5], la[5], lb[5];
-    load_site(z, r.d, r.s, a, b);
+    load_site_nt(z, r.d, r.s, a, b);
     load_site(lam, r.d, r.s, la, lb);
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lam, r.d, r.s, la, lb);
@@ -252,7 +280,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
     cx<double> la[5], lb[5];
     iprime_adj_site(lin, r, axis, qb, la, lb);
     cx<double> a[5], b[5];
-    load_site(z, r.d, r.s, a, b);
+    load_site_nt(z, r.d, r.s, a, b);
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lout, r.d, r.s, la, lb);
   }
