@@ -32,6 +32,15 @@ struct Sizes {
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
+int64_t adjoint_chunks(const qlg_params* p) {
+  int64_t n = 0;
+  for (int i = 0; i < p->nbatch; ++i) {
+    const int64_t ny = p->ndim >= 2 ? p->ny[i] : 1, nz = p->ndim == 3 ? p->nz[i] : 1;
+    n += (p->nx[i] * ny * nz + qlg::kChunk - 1) / qlg::kChunk;
+  }
+  return n;
+}
+
 qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   if (nsteps < 0 || K < 1) return QLG_ERR_ARG;
   size_t state_bytes = 0, scratch_bytes = 0;
@@ -43,9 +52,9 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   s->nck = (nsteps + K - 1) / K;
   s->nsub = 4 * p->ndim;
   s->nrec = p->split == QLG_SPLIT_PLAIN ? 1 : s->nsub;
-  // chunk count bound: one chunk per 256 sites per instance
-  int64_t nchunks = 0;
-  for (int i = 0; i < p->nbatch; ++i) nchunks += (p->nx[i] * (p->ndim == 2 ? p->ny[i] : 1) + 255) / 256;
+  // chunks of the per-site kernels: ceil(sites / 256) per instance, as the context's layout
+  // counts them (every extent of the instance, 1D to 3D)
+  const int64_t nchunks = adjoint_chunks(p);
   size_t o = 0;
   // inputs of every self-interaction of one checkpoint segment: [K][nrec] state copies
   s->off_zrec = o;  o += up256((size_t)K * (size_t)s->nrec * s->copy);
@@ -150,6 +159,10 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   if (nsteps == 0) return QLG_OK;
   if (!ckpt_dev || !work_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "checkpoint or work buffer is NULL");
   if (work_bytes < s.work) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "work buffer too small");
+  // every substep kernel writes 3 partials per chunk of the context's layout; the workspace
+  // region between off_part and off_acc must hold all of them
+  if ((size_t)3 * s.nsub * (size_t)std::max(v.geom.nchunks, 1) * sizeof(double) > s.off_acc - s.off_part)
+    return qlg::ctx_fail(ctx, QLG_ERR_ARG, "adjoint partials exceed their workspace region");
   if (((uintptr_t)work_dev & 255) || ((uintptr_t)ckpt_dev & 255))
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
 

@@ -99,3 +99,39 @@ def test_null_context_calls(Q):
     assert lib.qlg_step(None, 1) == 1
     assert lib.qlg_get_tuning(None, None) == 1
     assert lib.qlg_last_error(None).decode() == "NULL context"
+
+
+def _up256(v):
+    return (v + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("ndim,nx,ny,nz", [
+    (1, [100], None, None), (1, [16384, 700], None, None),
+    (2, [64], [64], None), (2, [30, 7, 512], [10, 3, 512], None),
+    (3, [16], [16], [16]), (3, [10], [12], [16]), (3, [64], [64], [64]),
+    (3, [10, 1, 33], [4, 1, 17], [3, 65, 9]),
+])
+@pytest.mark.parametrize("split", [0, 1])
+def test_adjoint_workspace_covers_kernel_partials(Q, ndim, nx, ny, nz, split):
+    """The reverse sweep's substep kernels write 3 FP64 partials per 256-site chunk of every
+    instance for each of the 4 ndim substeps of a step; the workspace qlg_adjoint_query
+    reports must hold them beside the recorded inputs, the forward chain's two state copies,
+    the two complex128 cotangents and the dL/dg accumulator."""
+    lib = Q.lib()
+    nsteps, K = 10, 4
+    p, keep = Q.make_params(ndim, nx, ny, (1, -0.5, 0.5), 0.1, Q.C64, split, nz)
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.qlg_query_sizes(ctypes.byref(p), ctypes.byref(sb), ctypes.byref(cb)) == 0
+    ck, wk = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.qlg_adjoint_query(ctypes.byref(p), nsteps, K, ctypes.byref(ck), ctypes.byref(wk)) == 0
+    copy = sb.value // 2
+    lam = copy // 8 * 16
+    nsub = 4 * ndim
+    nrec = 1 if split == 1 else nsub
+    sites = [x * (y if ndim >= 2 else 1) * (z if ndim == 3 else 1)
+             for x, y, z in zip(nx, ny or [1] * len(nx), nz or [1] * len(nx))]
+    nchunks = sum((s + 255) // 256 for s in sites)
+    need = (_up256(K * nrec * copy) + _up256(2 * copy) + _up256(2 * lam)
+            + _up256(8 * 3 * nsub * nchunks) + _up256(8 * 4))
+    assert wk.value >= need, (wk.value, need)
+    assert ck.value == -(-nsteps // K) * copy

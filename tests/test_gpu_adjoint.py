@@ -286,3 +286,18 @@ def test_vortex_pair_2d_fd_check():
         gm_[k] -= h
         fdg = (Lof(psi0, gp_) - Lof(psi0, gm_)) / (2 * h)
         assert abs(fdg - gg[k]) <= 1e-6 * max(abs(gg[k]), 1e-6), (k, fdg, gg[k])
+
+
+@pytest.mark.parametrize("split", ["interleaved", "plain"])
+def test_3d_gradient_multi_chunk_matches_oracle_autograd(split):
+    """A 3D lattice of several 256-site chunks (16 x 12 x 10 = 1920 sites, 8 chunks; ragged
+    extents): every substep kernel of the reverse sweep writes its dL/dg partials for all
+    chunks, so the workspace must be sized by the whole lattice, not by one x row."""
+    shape = (16, 12, 10)
+    psi0 = qi.random_field(shape, seed=57, scale=0.4)
+    eps, nsteps = 0.35, 5
+    L0, gp0, gg0 = oracle_grad(psi0, G, eps, nsteps, split)
+    L1, gp1, gg1 = gpu_grad(psi0, G, eps, nsteps, K=2, split=split)
+    assert abs(L1 - L0) <= 1e-12 * abs(L0), (L1, L0)
+    assert rel(gp1, gp0) <= 1e-10, rel(gp1, gp0)
+    assert rel(gg1, gg0) <= 1e-10, (gg1, gg0)
