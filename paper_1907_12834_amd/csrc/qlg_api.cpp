@@ -58,31 +58,7 @@ void tiles_z(int64_t nx, int64_t nz, int rows, int* ntx, int* ntz) {
   *ntz = (int)((nz + rows - 1) / rows);
 }
 
-qlg_status validate(const qlg_params* p, std::string* msg) {
-  if (!p) { *msg = "params is NULL"; return QLG_ERR_ARG; }
-  if (p->ndim < 1 || p->ndim > 3) { *msg = "ndim must be 1, 2 or 3"; return QLG_ERR_SHAPE; }
-  if (p->dtype != QLG_C64 && p->dtype != QLG_C128) { *msg = "dtype must be QLG_C64 or QLG_C128"; return QLG_ERR_DTYPE; }
-  if (p->split != QLG_SPLIT_INTERLEAVED && p->split != QLG_SPLIT_PLAIN) { *msg = "unknown split"; return QLG_ERR_ARG; }
-  if (p->nbatch < 1) { *msg = "nbatch must be >= 1"; return QLG_ERR_SHAPE; }
-  if (!p->nx) { *msg = "nx is NULL"; return QLG_ERR_ARG; }
-  if (p->ndim >= 2 && !p->ny) { *msg = "ny is NULL for a 2D or 3D lattice"; return QLG_ERR_ARG; }
-  if (p->ndim == 3 && !p->nz) { *msg = "nz is NULL for a 3D lattice"; return QLG_ERR_ARG; }
-  if (!std::isfinite(p->g0) || !std::isfinite(p->g1) || !std::isfinite(p->g2)) { *msg = "couplings must be finite"; return QLG_ERR_ARG; }
-  if (!std::isfinite(p->eps) || !(p->eps > 0)) { *msg = "eps must be finite and > 0"; return QLG_ERR_ARG; }
-  for (int i = 0; i < p->nbatch; ++i) {
-    const int64_t nx = p->nx[i];
-    const int64_t ny = p->ndim >= 2 ? p->ny[i] : (p->ny ? p->ny[i] : 1);
-    const int64_t nz = p->ndim == 3 ? p->nz[i] : (p->nz ? p->nz[i] : 1);
-    if (nx < 1 || ny < 1 || nz < 1 || nx > kMaxExtent || ny > kMaxExtent || nz > kMaxExtent) {
-      *msg = "extents must be in [1, 2^30]";
-      return QLG_ERR_SHAPE;
-    }
-    if (p->ndim == 1 && ny != 1) { *msg = "ny must be 1 (or NULL) for ndim == 1"; return QLG_ERR_SHAPE; }
-    if (p->ndim < 3 && nz != 1) { *msg = "nz must be 1 (or NULL) for ndim < 3"; return QLG_ERR_SHAPE; }
-    if (nx * ny > kMaxSites || nx * ny * nz > kMaxSites) { *msg = "an instance exceeds 2^31-1 sites"; return QLG_ERR_SHAPE; }
-  }
-  return QLG_OK;
-}
+qlg_status validate(const qlg_params* p, const char** msg) { return qlg::validate_params(p, msg); }
 
 Layout make_layout(const qlg_params* p) {
   Layout L;
@@ -352,7 +328,7 @@ const char* qlg_status_string(qlg_status s) {
 const char* qlg_last_error(const qlg_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
 qlg_status qlg_query_sizes(const qlg_params* p, size_t* state_bytes, size_t* scratch_bytes) {
-  std::string msg;
+  const char* msg = nullptr;
   qlg_status s = validate(p, &msg);
   if (s) return s;
   if (!state_bytes || !scratch_bytes) return QLG_ERR_ARG;
@@ -367,7 +343,7 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
                     size_t scratch_bytes, void* hip_stream, qlg_ctx** out) {
   if (!out) return QLG_ERR_ARG;
   *out = nullptr;
-  std::string msg;
+  const char* msg = nullptr;
   qlg_status s = validate(p, &msg);
   if (s) return s;
   if (!state_dev || !scratch_dev) return QLG_ERR_ARG;
@@ -621,38 +597,7 @@ qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
 // Host decoding of nrec records of nbatch instances; false if any is non-finite
 // or drifted.
 static bool decode_records(const qlg_ctx* c, const double* rec, int64_t nrec, qlg_obs* out) {
-  const int nb = c->p.nbatch;
-  const double meas = std::pow(c->p.eps, c->p.ndim);
-  const double tol = c->p.dtype == QLG_C64 ? 1e-4 : 1e-10;
-  bool bad = false;
-  for (int64_t k = 0; k < nrec * nb; ++k) {
-    const double* r = rec + (size_t)k * qlg::kRecord;
-    qlg_obs& o = out[k];
-    std::memset(&o, 0, sizeof o);
-    o.norm_q = meas * r[0];
-    o.norm_psi = meas * r[1];
-    for (int m = 0; m < 5; ++m) o.pop[m] = meas * r[2 + m];
-    o.energy = meas * (r[7] / (c->p.eps * c->p.eps) + r[8]);
-    o.step = (int64_t)r[qlg::kNObs + 3];
-    const int flags = (int)r[qlg::kNObs + 4];
-    o.has_overlap = (flags & 1) ? 1 : 0;
-    if (o.has_overlap) {
-      o.overlap_re = meas * r[qlg::kNObs];
-      o.overlap_im = meas * r[qlg::kNObs + 1];
-      const double nn = o.norm_psi;
-      if (nn > 0) {   // i (nn - ov) / nn
-        o.e_overlap_re = o.overlap_im / nn;
-        o.e_overlap_im = (nn - o.overlap_re) / nn;
-      }
-    }
-    for (int j = 0; j < qlg::kNObs; ++j) bad |= !std::isfinite(r[j]);
-    const double ref = r[qlg::kNObs + 2];
-    if ((flags & 2) && ref > 0) {
-      const double drift = r[0] / ref - 1.0;
-      bad |= !(std::fabs(drift) <= tol);
-    }
-  }
-  return !bad;
+  return qlg::decode_record_values(c->p, rec, nrec, out);
 }
 
 qlg_status qlg_observables(qlg_ctx* c, qlg_obs* out) {
@@ -807,6 +752,75 @@ qlg_status qlg_last_kernel_ms(qlg_ctx* c, double* ms, int64_t* launches) {
 }
 
 }  // extern "C"
+
+namespace qlg {
+
+// Host checks of a parameter block (no device call, no allocation); *msg names the failure.
+qlg_status validate_params(const qlg_params* p, const char** msg) {
+  if (!p) { *msg = "params is NULL"; return QLG_ERR_ARG; }
+  if (p->ndim < 1 || p->ndim > 3) { *msg = "ndim must be 1, 2 or 3"; return QLG_ERR_SHAPE; }
+  if (p->dtype != QLG_C64 && p->dtype != QLG_C128) { *msg = "dtype must be QLG_C64 or QLG_C128"; return QLG_ERR_DTYPE; }
+  if (p->split != QLG_SPLIT_INTERLEAVED && p->split != QLG_SPLIT_PLAIN) { *msg = "unknown split"; return QLG_ERR_ARG; }
+  if (p->nbatch < 1) { *msg = "nbatch must be >= 1"; return QLG_ERR_SHAPE; }
+  if (!p->nx) { *msg = "nx is NULL"; return QLG_ERR_ARG; }
+  if (p->ndim >= 2 && !p->ny) { *msg = "ny is NULL for a 2D or 3D lattice"; return QLG_ERR_ARG; }
+  if (p->ndim == 3 && !p->nz) { *msg = "nz is NULL for a 3D lattice"; return QLG_ERR_ARG; }
+  if (!std::isfinite(p->g0) || !std::isfinite(p->g1) || !std::isfinite(p->g2)) { *msg = "couplings must be finite"; return QLG_ERR_ARG; }
+  if (!std::isfinite(p->eps) || !(p->eps > 0)) { *msg = "eps must be finite and > 0"; return QLG_ERR_ARG; }
+  for (int i = 0; i < p->nbatch; ++i) {
+    const int64_t nx = p->nx[i];
+    const int64_t ny = p->ndim >= 2 ? p->ny[i] : (p->ny ? p->ny[i] : 1);
+    const int64_t nz = p->ndim == 3 ? p->nz[i] : (p->nz ? p->nz[i] : 1);
+    if (nx < 1 || ny < 1 || nz < 1 || nx > kMaxExtent || ny > kMaxExtent || nz > kMaxExtent) {
+      *msg = "extents must be in [1, 2^30]";
+      return QLG_ERR_SHAPE;
+    }
+    if (p->ndim == 1 && ny != 1) { *msg = "ny must be 1 (or NULL) for ndim == 1"; return QLG_ERR_SHAPE; }
+    if (p->ndim < 3 && nz != 1) { *msg = "nz must be 1 (or NULL) for ndim < 3"; return QLG_ERR_SHAPE; }
+    if (nx * ny > kMaxSites || nx * ny * nz > kMaxSites) { *msg = "an instance exceeds 2^31-1 sites"; return QLG_ERR_SHAPE; }
+  }
+  return QLG_OK;
+}
+
+// Decoding of nrec observables records of the p->nbatch instances into out[nrec][nbatch];
+// false if any is non-finite or, where the record holds a reference norm, drifted beyond the
+// dtype's threshold.  No allocation.
+bool decode_record_values(const qlg_params& p, const double* rec, int64_t nrec, qlg_obs* out) {
+  const int nb = p.nbatch;
+  const double meas = std::pow(p.eps, p.ndim);
+  const double tol = p.dtype == QLG_C64 ? 1e-4 : 1e-10;
+  bool bad = false;
+  for (int64_t k = 0; k < nrec * nb; ++k) {
+    const double* r = rec + (size_t)k * qlg::kRecord;
+    qlg_obs& o = out[k];
+    std::memset(&o, 0, sizeof o);
+    o.norm_q = meas * r[0];
+    o.norm_psi = meas * r[1];
+    for (int m = 0; m < 5; ++m) o.pop[m] = meas * r[2 + m];
+    o.energy = meas * (r[7] / (p.eps * p.eps) + r[8]);
+    o.step = (int64_t)r[qlg::kNObs + 3];
+    const int flags = (int)r[qlg::kNObs + 4];
+    o.has_overlap = (flags & 1) ? 1 : 0;
+    if (o.has_overlap) {
+      o.overlap_re = meas * r[qlg::kNObs];
+      o.overlap_im = meas * r[qlg::kNObs + 1];
+      const double nn = o.norm_psi;
+      if (nn > 0) {   // i (nn - ov) / nn
+        o.e_overlap_re = o.overlap_im / nn;
+        o.e_overlap_im = (nn - o.overlap_re) / nn;
+      }
+    }
+    for (int j = 0; j < qlg::kNObs; ++j) bad |= !std::isfinite(r[j]);
+    const double ref = r[qlg::kNObs + 2];
+    if ((flags & 2) && ref > 0) {
+      const double drift = r[0] / ref - 1.0;
+      bad |= !(std::fabs(drift) <= tol);
+    }
+  }
+  return !bad;
+}
+
+}  // namespace qlg
 
 // Accessors used by the adjoint implementation (qlg_adjoint.cpp).
 namespace qlg {

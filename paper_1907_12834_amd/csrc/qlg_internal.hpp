@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/qlg.h"
+
 namespace qlg {
 
 // One lattice instance inside a batch.  Offsets are in complex elements.
@@ -80,5 +82,12 @@ hipError_t launch_observables(int dtype, int ndim, const void* state, const Laun
 // overlap partials (ovpart may be null) and a reference record (ref may be null).
 hipError_t launch_record(const LaunchGeom& g, const double* part, const double* ovpart, const double* ref,
                          double* rec, int64_t step, hipStream_t st);
+
+// Host checks of a parameter block shared by every entry point that takes one (no
+// device call, no allocation); *msg receives a static description of the failure.
+qlg_status validate_params(const qlg_params* p, const char** msg);
+// Observables records (kRecord doubles per instance, written by k_reduce_record) to
+// qlg_obs values; false if a record is non-finite or drifted (no allocation).
+bool decode_record_values(const qlg_params& p, const double* rec, int64_t nrec, qlg_obs* out);
 
 }  // namespace qlg
