@@ -287,6 +287,20 @@ def adjoint_vortex_pair_2d_512(n: int = 512, sep: float = 128.0, eps: float = 0.
                     nsteps, {"sep": sep, "seed": seed, "checkpoint_every": checkpoint_every})
 
 
+def adjoint_vortex_pair_2d_64(n: int = 64, sep: float = 16.0, eps: float = 0.4, seed: int = 2019) -> np.ndarray:
+    """The vortex-pair construction on the 64^2 lattice of the adjoint's finite-difference and
+    reference-gradient checks: separation 16 sites and eps = 0.4, so the cores fit the box."""
+    return vortex_pair_2d(n, n, sep, eps, np.random.default_rng(seed))
+
+
+def adjoint_spin_texture_2d_64(n: int = 64, sep: float = 16.0, eps: float = 0.4, seed: int = 2019,
+                               noise_seed: int = 77, noise: float = 0.05) -> np.ndarray:
+    """adjoint_vortex_pair_2d_64 plus a seeded complex Gaussian spinor of amplitude `noise` in
+    every component: m = +-1 are populated and F != 0 at every site, so the spin factor of
+    the self-interaction (and its derivative) acts everywhere."""
+    return adjoint_vortex_pair_2d_64(n, sep, eps, seed) + random_field((n, n), noise_seed, noise)
+
+
 def vortex_lines_3d(n: int, sep: float, eps: float, rng: np.random.Generator, amp: float = 4.0,
                     coeffs=(0.3, 0.05, 0.4), jitter: float = 0.05) -> np.ndarray:
     """The 2D vortex pair of vortex_pair_2d extruded along z into two vortex lines on an n^3

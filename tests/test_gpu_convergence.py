@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import qlg_inputs as qi
 from oracle import qlg_oracle as O
 
 pytestmark = pytest.mark.gpu
@@ -23,11 +24,28 @@ def conv():
     return convergence
 
 
+def stationary_state(kind, w):
+    """Table I row 14 at E = -2 as the bright sech state, at E = +2 as the dark two-kink product
+    (Sec. IV), K = 1, eps = 1/w, L = 40 w sites, from the shared input generators."""
+    eps, L = 1.0 / w, 40 * w
+    if kind == "bright":
+        g = (-1.0, 0.2, 1.0)
+        c = qi.table1_coeffs(14, -2.0, *g).real
+        X = (np.arange(L) - L / 2) * eps
+        return c[:, None] * (1.0 / np.cosh(X))[None, :], eps, g
+    g = (1.0, 0.1, 0.7)
+    c = qi.table1_coeffs(14, 2.0, *g).real
+    return qi.dark_pair_1d(L, eps, c, K=1.0), eps, g
+
+
 def oracle_error(kind, split, w, nsteps):
-    C = conv()
-    psi0, eps, g = C.initial_state(kind, w)
+    """The oracle's run and its own density L2 error (Sec. VII) from the stationary state."""
+    psi0, eps, g = stationary_state(kind, w)
+    # the GPU study starts from the same state
+    p0, e0, g0 = conv().initial_state(kind, w)
+    assert np.array_equal(p0, psi0) and e0 == eps and tuple(g0) == g
     A, B = O.run_psi(psi0, nsteps, eps, g, split)
-    return C.density_error(psi0, (A + B).numpy())
+    return O.density_l2_error(torch.from_numpy(psi0), A + B)
 
 
 @pytest.mark.parametrize("kind", ["bright", "dark"])
