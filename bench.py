@@ -49,6 +49,7 @@ BYTES_PER_SITE_PASS = {"c64": 2 * 10 * 8, "c128": 2 * 10 * 16}
 PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # fp32 vector (packed), fp64 vector
 PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
+PREROLL_S = 0.2        # untimed steps right before each clock start, at least this long
 
 # HBM traffic of one launch of the fused step (complex64, interleaved split), by workload, kernel and
 # plan (steps per pass in 1D, band height in 2D and 3D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
@@ -197,9 +198,10 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
 
     # observables every OBS_EVERY steps are recorded on the device (no host round trip)
     # and decoded once at the end of the run, inside the timed region
-    rec = lat.new_records(max(steps, warmup) // OBS_EVERY + 1)
+    recs = {"buf": lat.new_records(max(steps, warmup) // OBS_EVERY + 1)}
 
     def run(nsteps):
+        rec = recs["buf"]
         done, k = 0, 0
         while done < nsteps:
             n = min(OBS_EVERY, nsteps - done)
@@ -211,15 +213,29 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
         return lat.decode_records(rec[:k])
 
     run(warmup)
-    # Capture, before the clock starts, every graph the timed runs replay: graphs are keyed by
-    # (steps, starting copy), and the timed runs advance in chunks of OBS_EVERY steps (even, so
-    # each chunk starts from the same copy) plus one remainder.  Each chunk size runs twice,
-    # which captures both starting copies and returns to the first.
-    for n in sorted({OBS_EVERY, steps % OBS_EVERY, warmup % OBS_EVERY} - {0}):
+    # Capture, before the clock starts, every graph the warm-up and timed runs replay: graphs
+    # are keyed by (steps, starting copy), and those runs advance in chunks of OBS_EVERY steps
+    # plus one remainder.  Each chunk size runs, then one single step (which moves to the other
+    # copy wherever a step changes copies), then the chunk size again: both starting copies.
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    sizes = sorted({OBS_EVERY, steps % OBS_EVERY, warmup % OBS_EVERY} - {0})
+    for n in sizes:
         lat.step(n)
+        lat.step(1)
         lat.step(n)
+    torch.cuda.synchronize()
+    per_step = (time.perf_counter() - c0) / sum(2 * n + 1 for n in sizes)   # upper bound (captures)
     lat.set_psi([torch.from_numpy(w.psi[0])])
     obs0 = lat.observables()[0]
+    # The warm-up again, on the state the timed run continues, so that the GPU is busy up to the
+    # start of the clock: after the host-side work above its clock has dropped, and it takes a
+    # few tens of milliseconds of work to return to the steady state.  W steps, and at least
+    # PREROLL_S seconds of them.
+    preroll = max(warmup, int(math.ceil(PREROLL_S / per_step)) if per_step > 0 else 0)
+    if preroll // OBS_EVERY + 1 > recs["buf"].shape[0]:
+        recs["buf"] = lat.new_records(preroll // OBS_EVERY + 1)
+    run(preroll)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     trace = run(steps)
@@ -244,12 +260,14 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
     # Those events add ~9 us of dispatch gap per launch, so they stay out of the
     # throughput region above.
     lat.set_psi([torch.from_numpy(w.psi[0])])
+    run(preroll)
     lat.set_timing(True)
     run(min(steps, 4000))
     kern_ms, launches = lat.last_kernel_ms()
     lat.set_timing(False)
     return {"w": w, "L": L, "value": L * steps / wall, "wall": wall, "kern_ms": kern_ms, "launches": launches,
-            "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0, "repeats": repeats}
+            "tuning": tuning, "drift": obs1["norm_q"] / obs0["norm_q"] - 1.0, "repeats": repeats,
+            "preroll": preroll}
 
 
 def diagnostics(workload, dtype, reps):
@@ -479,6 +497,7 @@ def main():
             "observables_every": OBS_EVERY,
             "plan": m["tuning"],
             "plan_source": "fixed by --plan" if args.plan else "autotuned",
+            "preroll_steps": m["preroll"],
         },
         "roofline": {
             "bound": bound,

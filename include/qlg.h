@@ -57,7 +57,7 @@ typedef enum {
   QLG_ERR_SHAPE = 2,    /* ndim not 1..3, extent < 1, lattice too large, call not for this ndim */
   QLG_ERR_DTYPE = 3,    /* dtype not QLG_C64 / QLG_C128 */
   QLG_ERR_DEVICE = 4,   /* a HIP call failed; message in qlg_last_error */
-  QLG_ERR_OOM = 5,      /* the library's own small metadata allocation failed */
+  QLG_ERR_OOM = 5,      /* the library's host-side context allocation failed */
   QLG_ERR_STATE = 6,    /* context is in an error state, or call out of order */
   QLG_ERR_NUMERIC = 7   /* non-finite values, or qubit norm drift above threshold */
 } qlg_status;
@@ -123,15 +123,18 @@ int32_t qlg_version(void);
 
 /* Bytes the caller must provide for a lattice described by *params:
  *   state_bytes:   two copies (ping-pong) of all qubit planes, padded;
- *   scratch_bytes: reduction partials for observables and overlaps.
+ *   scratch_bytes: reduction partials for observables and overlaps, and the
+ *                  device tables of the launch geometry (instance descriptors,
+ *                  tile and chunk maps).
  * Errors: QLG_ERR_ARG / SHAPE / DTYPE as for qlg_init. */
 qlg_status qlg_query_sizes(const qlg_params* params, size_t* state_bytes, size_t* scratch_bytes);
 
 /* Create a context over caller-owned device buffers.  state_dev and
  * scratch_dev must be 256-byte aligned and at least the sizes reported by
  * qlg_query_sizes.  hip_stream is a hipStream_t (or NULL).  The state is
- * undefined until qlg_set_psi or qlg_set_qubits.  The library allocates only
- * a small device table of per-instance descriptors (freed by qlg_destroy). */
+ * undefined until qlg_set_psi or qlg_set_qubits.  The library allocates no
+ * device memory: its tables live in scratch_dev.  It owns only the host
+ * context and, once used, its captured graphs and timing events. */
 qlg_status qlg_init(const qlg_params* params, void* state_dev, size_t state_bytes,
                     void* scratch_dev, size_t scratch_bytes, void* hip_stream, qlg_ctx** out);
 
@@ -239,7 +242,12 @@ qlg_status qlg_decode_records(qlg_ctx* ctx, const double* rec_host, int64_t nrec
  * above (the context keeps its plan).  qlg_autotune times the candidate plans on the
  * context's own lattice without changing its state and keeps the fastest; among plans
  * within 2 % of the fastest it prefers fewer launches, then qubit_split 0, 1, 2, then
- * taller bands. */
+ * taller bands.  Chosen plans are kept for the process, keyed by device, dtype, ndim,
+ * split, batched or not and the total site count rounded up to a power of two; a new
+ * context with the same key starts from that plan.  When the environment variable
+ * QLG_TUNE_CACHE names a file, qlg_autotune also appends the plan to it as a text line
+ * "key steps_per_pass tile_rows use_graph qubit_split", and qlg_init takes the last
+ * in-range line with its key from the file before the process's own record. */
 qlg_status qlg_set_tuning(qlg_ctx* ctx, const qlg_tuning* tuning);
 qlg_status qlg_get_tuning(const qlg_ctx* ctx, qlg_tuning* tuning);
 qlg_status qlg_autotune(qlg_ctx* ctx);
@@ -295,6 +303,15 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
 qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every,
                             const void* ckpt_dev, void* lambda_dev, void* work_dev,
                             size_t work_bytes, double* dg_host);
+
+/* Adjoint of qlg_set_psi, the encoding a = b = psi / 2 (Sec. III, two qubits
+ * per m_f level): from the cotangent of both qubits lambda_dev (complex128,
+ * canonical qubits layout, as qlg_adjoint_step leaves it) writes the cotangent
+ * of psi, dpsi_dev = (lambda_a + lambda_b) / 2 (complex128, canonical psi
+ * layout, the same convention).  Device buffers owned by the caller, 16-byte
+ * aligned, not overlapping; QLG_ERR_ARG for NULL or misaligned pointers.
+ * Asynchronous on the context's stream. */
+qlg_status qlg_set_psi_adjoint(qlg_ctx* ctx, const void* lambda_dev, void* dpsi_dev);
 
 /* Human-readable status name, and the last error message of a context. */
 const char* qlg_status_string(qlg_status status);

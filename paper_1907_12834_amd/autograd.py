@@ -42,9 +42,8 @@ class QLGObjective(torch.autograd.Function):
     def backward(ctx, grad_out):
         lat = ctx.lat
         dg = lat.adjoint_step(ctx.nsteps, ctx.K, ctx.ckpt, ctx.lam)
-        lam = ctx.lam.reshape((2,) + tuple(ctx.psi_shape))
-        # psi0 enters as a = b = psi0 / 2
-        dpsi = 0.5 * (lam[0] + lam[1])
+        # psi0 enters as a = b = psi0 / 2: the library's adjoint of that encoding
+        dpsi = lat.set_psi_adjoint(ctx.lam)[0]
         dgt = torch.tensor([a + b for a, b in zip(dg, ctx.dg_explicit)], dtype=ctx.g_dtype, device=ctx.g_device)
         go = grad_out.to(torch.float64)
         dpsi = (go.to(dpsi.device) * dpsi).to(ctx.psi_dtype).to(ctx.psi_device)

@@ -244,4 +244,14 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   return QLG_OK;
 }
 
+qlg_status qlg_set_psi_adjoint(qlg_ctx* ctx, const void* lambda_dev, void* dpsi_dev) {
+  if (!ctx) return QLG_ERR_ARG;
+  if (qlg::ctx_broken(ctx)) return QLG_ERR_STATE;
+  if (!lambda_dev || !dpsi_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda or dpsi is NULL");
+  if (((uintptr_t)lambda_dev & 15) || ((uintptr_t)dpsi_dev & 15))
+    return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda and dpsi must be 16-byte aligned");
+  const qlg::CtxView v = qlg::ctx_view(ctx);
+  return qlg::ctx_hip(ctx, qlg::launch_encode_adj(lambda_dev, dpsi_dev, v.geom, v.stream), "encode adjoint kernel");
+}
+
 }  // extern "C"

@@ -546,6 +546,26 @@ __global__ __launch_bounds__(kChunk) void k_lam_out(const cx<double>* __restrict
   for (int p = 0; p < 10; ++p) qb[r.d.qb_off + (int64_t)p * r.d.sites + r.s] = st[r.d.off + p * r.d.stride + r.s];
 }
 
+// Adjoint of the encoding a = b = psi / 2 (Sec. III, two qubits per m_f level): psi enters
+// both qubits with weight 1/2, so dL/dpsi_m = (lambda_a,m + lambda_b,m) / 2.  Canonical
+// qubits layout in, canonical psi layout out, both complex128.
+__global__ __launch_bounds__(kChunk) void k_encode_adj(const cx<double>* __restrict__ qb,
+                                                      cx<double>* __restrict__ dpsi, LaunchGeom g) {
+  const Site r = site_here(g);
+  if (!r.ok) return;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const cx<double> la = qb[r.d.qb_off + (int64_t)m * r.d.sites + r.s];
+    const cx<double> lb = qb[r.d.qb_off + (int64_t)(5 + m) * r.d.sites + r.s];
+    dpsi[r.d.psi_off + (int64_t)m * r.d.sites + r.s] = 0.5 * (la + lb);
+  }
+}
+
+hipError_t launch_encode_adj(const void* lam, void* dpsi, const LaunchGeom& g, hipStream_t st) {
+  hipLaunchKernelGGL(k_encode_adj, QLG_GRID, (const cx<double>*)lam, (cx<double>*)dpsi, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_lam_layout(bool to_planes, const void* src, void* dst, const LaunchGeom& g, hipStream_t st) {
   if (to_planes)
     hipLaunchKernelGGL(k_lam_in, QLG_GRID, (const cx<double>*)src, (cx<double>*)dst, g);

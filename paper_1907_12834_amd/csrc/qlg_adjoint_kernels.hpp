@@ -29,6 +29,8 @@ hipError_t launch_energy_grad(int dtype, int ndim, const void* state, void* lam,
 hipError_t launch_fidelity_grad(int dtype, const void* state, const void* target, void* lam, const LaunchGeom& g,
                                 double meas, double* part, double* ov, hipStream_t st);
 hipError_t launch_lam_layout(bool to_planes, const void* src, void* dst, const LaunchGeom& g, hipStream_t st);
+// dpsi = (lambda_a + lambda_b) / 2: adjoint of the encoding, complex128 canonical layouts
+hipError_t launch_encode_adj(const void* lam, void* dpsi, const LaunchGeom& g, hipStream_t st);
 hipError_t launch_zero(double* p, int n, hipStream_t st);
 
 }  // namespace qlg

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -92,8 +93,13 @@ Layout make_layout(const qlg_params* p) {
   return L;
 }
 
+// The caller's scratch buffer: reduction partials and records, then the device tables of
+// the launch geometry (instance descriptors, tile and chunk maps), so that the library
+// allocates no device memory of its own.
 struct ScratchLayout {
-  size_t obs_part, obs_res, norm0, ov_part, total;  // byte offsets
+  size_t obs_part, obs_res, norm0, ov_part;          // byte offsets of the reductions
+  size_t inst, tile2inst, chunk2inst, tile2inst_z;   // byte offsets of the tables
+  size_t total;
 };
 
 ScratchLayout scratch_layout(const Layout& L, int nbatch) {
@@ -104,6 +110,10 @@ ScratchLayout scratch_layout(const Layout& L, int nbatch) {
   s.obs_res = take(sizeof(double) * qlg::kRecord * nbatch);   // one observables record
   s.norm0 = take(sizeof(double) * qlg::kRecord * nbatch);     // record of the state at set time
   s.ov_part = take(sizeof(double) * 2 * (size_t)std::max(L.max_tiles, 1));
+  s.inst = take(sizeof(InstDesc) * (size_t)nbatch);
+  s.tile2inst = take(sizeof(int32_t) * (size_t)std::max(L.max_tiles, 1));
+  s.chunk2inst = take(sizeof(int32_t) * (size_t)std::max(L.nchunks, 1));
+  s.tile2inst_z = take(sizeof(int32_t) * (size_t)std::max(L.max_tiles_z, 1));
   s.total = o;
   return s;
 }
@@ -126,7 +136,7 @@ struct qlg_ctx {
   hipStream_t stream = nullptr;
   int cur = 0;
   size_t elem_bytes = 8;
-  // device tables
+  // device tables (inside the scratch buffer)
   InstDesc* d_inst = nullptr;
   int32_t* d_tile2inst = nullptr;
   int32_t* d_chunk2inst = nullptr;
@@ -305,6 +315,50 @@ std::string tune_key(const qlg_ctx* c) {
   return buf;
 }
 
+// A launch plan's range checks for this context (those of qlg_set_tuning): nullptr when valid.
+const char* tuning_error(const qlg_ctx* c, const qlg_tuning& n) {
+  if (c->p.ndim == 1) {
+    if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return "steps_per_pass must be 1..7 in 1D";
+    if (n.qubit_split < 0 || n.qubit_split > 2) return "qubit_split must be 0, 1 or 2";
+    if (n.qubit_split == 2 && n.steps_per_pass > kMaxStepsLanes) return "steps_per_pass must be 1..3 with qubit_split 2";
+  } else {
+    if (n.steps_per_pass != 1) return "steps_per_pass must be 1 in 2D and 3D";
+    if (n.qubit_split != 0) return "qubit_split must be 0 in 2D and 3D";
+    if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return "tile_rows must be 8..256";
+  }
+  return nullptr;
+}
+
+// Autotune results that outlive the process: when the environment variable QLG_TUNE_CACHE
+// names a file, qlg_autotune appends "key steps_per_pass tile_rows use_graph qubit_split" to
+// it, and a new context takes the plan of the last line with its key (a line with a plan
+// that is out of range for the context is ignored).  Read before the process-wide cache.
+bool tune_file_lookup(const qlg_ctx* c, const std::string& key, qlg_tuning* out) {
+  const char* path = std::getenv("QLG_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char k[200];
+  qlg_tuning t{};
+  while (std::fscanf(f, "%199s %d %d %d %d", k, &t.steps_per_pass, &t.tile_rows, &t.use_graph,
+                     &t.qubit_split) == 5)
+    if (key == k && !tuning_error(c, t)) { *out = t; found = true; }
+  std::fclose(f);
+  if (found && c->p.ndim == 1) out->tile_rows = 0;
+  if (found) out->use_graph = out->use_graph ? 1 : 0;
+  return found;
+}
+
+void tune_file_store(const std::string& key, const qlg_tuning& t) {
+  const char* path = std::getenv("QLG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.steps_per_pass, t.tile_rows, t.use_graph, t.qubit_split);
+  std::fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -374,27 +428,29 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
   if (p->ndim >= 2) c->tuning = qlg_tuning{1, 32, 0, 0};
   else c->tuning = qlg_tuning{1, 0, 0, 0};
 
-  hipError_t e = hipMalloc(&c->d_inst, sizeof(InstDesc) * p->nbatch);
-  if (e == hipSuccess) e = hipMalloc(&c->d_tile2inst, sizeof(int32_t) * std::max(c->L.max_tiles, 1));
-  if (e == hipSuccess) e = hipMalloc(&c->d_chunk2inst, sizeof(int32_t) * std::max(c->L.nchunks, 1));
-  if (e == hipSuccess && p->ndim == 3)
-    e = hipMalloc(&c->d_tile2inst_z, sizeof(int32_t) * std::max(c->L.max_tiles_z, 1));
-  if (e != hipSuccess) {
-    qlg_destroy(c);
-    return e == hipErrorOutOfMemory ? QLG_ERR_OOM : QLG_ERR_DEVICE;
-  }
+  c->d_inst = reinterpret_cast<InstDesc*>(c->scratch + c->S.inst);
+  c->d_tile2inst = reinterpret_cast<int32_t*>(c->scratch + c->S.tile2inst);
+  c->d_chunk2inst = reinterpret_cast<int32_t*>(c->scratch + c->S.chunk2inst);
+  if (p->ndim == 3) c->d_tile2inst_z = reinterpret_cast<int32_t*>(c->scratch + c->S.tile2inst_z);
   std::vector<int32_t> c2i;
   for (int i = 0; i < p->nbatch; ++i)
     for (int k = 0; k < c->L.inst[i].nchunks; ++k) c2i.push_back(i);
-  e = hipMemcpy(c->d_chunk2inst, c2i.data(), sizeof(int32_t) * c2i.size(), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(c->d_chunk2inst, c2i.data(), sizeof(int32_t) * c2i.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     qlg_destroy(c);
     return QLG_ERR_DEVICE;
   }
   {
+    const std::string key = tune_key(c);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(tune_key(c));
-    if (it != g_tune_cache.end()) { c->tuning = it->second; c->tuned = true; }
+    qlg_tuning t{};
+    if (tune_file_lookup(c, key, &t)) {
+      c->tuning = t;
+      c->tuned = true;
+    } else {
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) { c->tuning = it->second; c->tuned = true; }
+    }
   }
   s = build_tiles(c);
   if (s) {
@@ -409,10 +465,6 @@ void qlg_destroy(qlg_ctx* c) {
   if (!c) return;
   drop_graphs(c);
   for (auto ev : c->ev) (void)hipEventDestroy(ev);
-  if (c->d_inst) (void)hipFree(c->d_inst);
-  if (c->d_tile2inst) (void)hipFree(c->d_tile2inst);
-  if (c->d_chunk2inst) (void)hipFree(c->d_chunk2inst);
-  if (c->d_tile2inst_z) (void)hipFree(c->d_tile2inst_z);
   delete c;
 }
 
@@ -637,17 +689,8 @@ qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
   if (s) return s;
   if (!t) return fail(c, QLG_ERR_ARG, "tuning is NULL");
   qlg_tuning n = *t;
-  if (c->p.ndim == 1) {
-    if (n.steps_per_pass < 1 || n.steps_per_pass > kMaxSteps1D) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..7 in 1D");
-    if (n.qubit_split < 0 || n.qubit_split > 2) return fail(c, QLG_ERR_ARG, "qubit_split must be 0, 1 or 2");
-    if (n.qubit_split == 2 && n.steps_per_pass > kMaxStepsLanes)
-      return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1..3 with qubit_split 2");
-    n.tile_rows = 0;
-  } else {
-    if (n.steps_per_pass != 1) return fail(c, QLG_ERR_ARG, "steps_per_pass must be 1 in 2D and 3D");
-    if (n.qubit_split != 0) return fail(c, QLG_ERR_ARG, "qubit_split must be 0 in 2D and 3D");
-    if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return fail(c, QLG_ERR_ARG, "tile_rows must be 8..256");
-  }
+  if (const char* why = tuning_error(c, n)) return fail(c, QLG_ERR_ARG, why);
+  if (c->p.ndim == 1) n.tile_rows = 0;
   n.use_graph = n.use_graph ? 1 : 0;
   c->tuning = n;
   return build_tiles(c);
@@ -729,8 +772,10 @@ qlg_status qlg_autotune(qlg_ctx* c) {
   c->tuning = best_t;
   c->tuned = true;
   {
+    const std::string key = tune_key(c);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(c)] = best_t;
+    g_tune_cache[key] = best_t;
+    tune_file_store(key, best_t);
   }
   return build_tiles(c);
 }

@@ -574,13 +574,17 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
 
   double ore = 0.0, oim = 0.0;
   const int nrows = A.tile_rows + 8;
-  // complex64 rows are loaded one iteration ahead, so that a row's HBM latency overlaps
-  // the arithmetic of the row before it (complex128 has no registers to spare for it:
-  // the extra row would halve its occupancy)
-  constexpr bool kAhead = sizeof(T) == 4;
+  // Rows are loaded one iteration ahead, so that a row's HBM latency overlaps the
+  // arithmetic of the row before it.  (complex128 holds the extra row in accumulation
+  // registers: its occupancy, one wave per SIMD, is set by the pipeline's LDS.)
+  constexpr bool kAhead = true;
+  // lattice row of the next load (row y0 - 4 + r of the band, periodic), advanced by one
+  // per load instead of a division per row
+  int yl = (int)wrap64(y0 - 4, nrow);
   // with kExt, e is the (V + mu) angle of the row's site in this lane
-  auto load_row = [&](int r, cx<T>(&a)[5], cx<T>(&b)[5], T& e) {
-    const int64_t s = pbase + wrap64(y0 - 4 + r, nrow) * rstride + xw;
+  auto load_row = [&](cx<T>(&a)[5], cx<T>(&b)[5], T& e) {
+    const int64_t s = pbase + (int64_t)yl * rstride + xw;
+    yl = yl + 1 == nrow ? 0 : yl + 1;
     const cx<T>* src = A.in + d.off + s;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
@@ -594,7 +598,7 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   // loaded four iterations ago
   T e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0), e4 = T(0), ne = T(0);
   cx<T> na[5], nb[5];
-  if (kAhead) load_row(0, na, nb, ne);
+  if (kAhead) load_row(na, nb, ne);
 #pragma unroll 1
   for (int r = 0; r < nrows; ++r) {
     cx<T> a[5], b[5];
@@ -606,9 +610,9 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
         b[m] = nb[m];
       }
       en = ne;
-      if (r + 1 < nrows) load_row(r + 1, na, nb, ne);
+      if (r + 1 < nrows) load_row(na, nb, ne);
     } else {
-      load_row(r, a, b, en);
+      load_row(a, b, en);
     }
     if constexpr (kExt) {
       e4 = e3;

@@ -47,9 +47,15 @@ template <typename T> QLG_HD cx<T> rfma(T s, cx<T> a, cx<T> acc) {
 // time step), so |x| <= pi/4 is evaluated by the Taylor series itself, with
 // enough terms that the truncation (|x|^11/11! ~ 2e-9 in FP32, |x|^19/19! ~ 1e-19
 // in FP64 at |x| = pi/4) stays below the format's rounding; larger angles take
-// the library routine.
+// the library routine.  Below |x| = 1/16, where the angles of a typical step lie,
+// fewer terms reach the same bound: the first omitted terms are |x|^7/7! and
+// |x|^8/8! (FP32; < 1e-12 |x|) and |x|^11/11! and |x|^10/10! (FP64; < 1e-19 |x|).
 QLG_HD void sincos_t(float x, float* s, float* c) {
-  if (fabsf(x) <= 0.78539816f) {
+  if (fabsf(x) <= 0.0625f) {
+    const float x2 = x * x;
+    *s = x * (1.0f + x2 * (-1.0f / 6 + x2 * (1.0f / 120)));
+    *c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24 + x2 * (-1.0f / 720)));
+  } else if (fabsf(x) <= 0.78539816f) {
     const float x2 = x * x;
     *s = x * (1.0f + x2 * (-1.0f / 6 + x2 * (1.0f / 120 + x2 * (-1.0f / 5040 + x2 * (1.0f / 362880)))));
     *c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24 + x2 * (-1.0f / 720 + x2 * (1.0f / 40320 + x2 * (-1.0f / 3628800)))));
@@ -58,7 +64,18 @@ QLG_HD void sincos_t(float x, float* s, float* c) {
   }
 }
 QLG_HD void sincos_t(double x, double* s, double* c) {
-  if (fabs(x) <= 0.7853981633974483) {
+  if (fabs(x) <= 0.0625) {
+    const double x2 = x * x;
+    double ps = 1.0 / 362880.0, pc = 1.0 / 40320.0;   // 1/9!, 1/8!
+    ps = fma(x2, ps, -1.0 / 5040.0);
+    pc = fma(x2, pc, -1.0 / 720.0);
+    ps = fma(x2, ps, 1.0 / 120.0);
+    pc = fma(x2, pc, 1.0 / 24.0);
+    ps = fma(x2, ps, -1.0 / 6.0);
+    pc = fma(x2, pc, -0.5);
+    *s = fma(x * x2, ps, x);
+    *c = fma(x2, pc, 1.0);
+  } else if (fabs(x) <= 0.7853981633974483) {
     const double x2 = x * x;
     double ps = 1.0 / 355687428096000.0, pc = 1.0 / 20922789888000.0;   // 1/17!, 1/16!
     ps = fma(x2, ps, -1.0 / 1307674368000.0);    // 1/15!
@@ -84,8 +101,11 @@ QLG_HD void sincos_t(double x, double* s, double* c) {
 QLG_HD float sqrt_t(float x) { return sqrtf(x); }
 QLG_HD double sqrt_t(double x) { return sqrt(x); }
 
-// 1/sqrt(x) and 1/x for x > 0 (normal): the hardware approximations (about one
-// ulp) in FP32; exact operations in FP64.
+// 1/sqrt(x) for x > 0 and 1/x for x != 0 (normal): the hardware approximations
+// (about one ulp) in FP32; in FP64 the hardware estimate refined by two Newton
+// steps, each of which squares its relative error (y <- y + y (1 - x y^2) / 2 and
+// y <- y + y (1 - x y)), to within a few ulp of the exact value (the host build
+// divides).
 QLG_HD float rsqrt_t(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rsqf(x);
@@ -93,7 +113,19 @@ QLG_HD float rsqrt_t(float x) {
   return 1.0f / sqrtf(x);
 #endif
 }
-QLG_HD double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+QLG_HD double rsqrt_t(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double r = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
 QLG_HD float rcp_t(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcpf(x);
@@ -101,7 +133,16 @@ QLG_HD float rcp_t(float x) {
   return 1.0f / x;
 #endif
 }
-QLG_HD double rcp_t(double x) { return 1.0 / x; }
+QLG_HD double rcp_t(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+#else
+  return 1.0 / x;
+#endif
+}
 
 // Angles of one application of U(theta): theta*g0, theta*g1, theta*g2/5.
 template <typename T>

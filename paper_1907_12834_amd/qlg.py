@@ -29,7 +29,7 @@ EXPORTED = [
     "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_find_vortices", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
-    "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_status_string",
+    "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_set_psi_adjoint", "qlg_status_string",
     "qlg_last_error", "qlg_destroy",
 ]
 
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_forward_record": (i32, [vp, i64, i32, vp, sz]),
         "qlg_objective_grad": (i32, [vp, i32, vp, vp, P(dbl), P(dbl)]),
         "qlg_adjoint_step": (i32, [vp, i64, i32, vp, vp, vp, sz, P(dbl)]),
+        "qlg_set_psi_adjoint": (i32, [vp, vp, vp]),
         "qlg_status_string": (ctypes.c_char_p, [i32]),
         "qlg_last_error": (ctypes.c_char_p, [vp]),
         "qlg_destroy": (None, [vp]),
@@ -459,6 +460,21 @@ class Lattice:
         self._check(lib().qlg_adjoint_step(self.ctx, int(nsteps), int(checkpoint_every), ckpt.data_ptr(),
                                            lam.data_ptr(), work.data_ptr(), wk, dg), "qlg_adjoint_step")
         return list(dg)
+
+    def set_psi_adjoint(self, lam: torch.Tensor) -> List[torch.Tensor]:
+        """Cotangent of psi from that of both qubits (adjoint of set_psi's a = b = psi / 2):
+        lam complex128 in the canonical qubits layout; per instance a complex128 (5, ...) tensor."""
+        lam = lam.contiguous()
+        if not (lam.is_cuda and lam.dtype == torch.complex128 and lam.numel() == 10 * self.sites):
+            raise ValueError("lam must be a complex128 device tensor of %d elements" % (10 * self.sites))
+        dpsi = torch.empty(5 * self.sites, dtype=torch.complex128, device=self.device)
+        self._check(lib().qlg_set_psi_adjoint(self.ctx, lam.data_ptr(), dpsi.data_ptr()), "qlg_set_psi_adjoint")
+        out, o = [], 0
+        for i in range(self.nbatch):
+            n = 5 * self.nx[i] * self.ny[i] * self.nz[i]
+            out.append(dpsi[o:o + n].reshape(self._shape(i)))
+            o += n
+        return out
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -4,6 +4,8 @@ References: the FP64 oracle differentiated by torch autograd (tolerance 1e-10
 relative), central finite differences of the GPU forward (1e-6), and exact
 adjointness of the linear (g = 0) step.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -265,10 +267,17 @@ def test_adjoint_vortex_pair_512_full_size():
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
 
 
-def test_vortex_pair_2d_fd_check():
-    """The 2D vortex-pair construction on 64^2 (eps = 0.4, separation 16) in FP64: FD vs adjoint."""
-    rng = np.random.default_rng(2019)
-    psi0 = qi.vortex_pair_2d(64, 64, 16.0, 0.4, rng)
+@pytest.mark.parametrize("case", ["vortex_pair", "spin_texture"])
+def test_64x64_finite_differences(case):
+    """The 64^2 adjoint checks in FP64 over 40 steps (checkpoint every 16): central differences of
+    the GPU forward against the adjoint, to 1e-6 for a seeded random direction and each coupling
+    (h = 1e-6) and to 1e-5 for 16 seeded sites, each perturbed in the real and in the imaginary
+    part of one component (h = 1e-4).
+    The vortex pair has F = 0 at every site (m = +-1 empty); the spin texture adds a seeded random
+    spinor, so F != 0 everywhere and the spin factor's derivative is exercised.  40 steps keep a
+    perturbation in the linear regime: with g1 < 0 the pair's m = +-2 symmetry is unstable and an
+    asymmetry grows about 1e5-fold per 100 steps at eps = 0.4."""
+    psi0 = qi.adjoint_vortex_pair_2d_64() if case == "vortex_pair" else qi.adjoint_spin_texture_2d_64()
     g, eps, nsteps, K, h = (1.0, -0.3, 0.2), 0.4, 40, 16, 1e-6
     L, gp, gg = gpu_grad(psi0, g, eps, nsteps, K=K)
 
@@ -276,16 +285,89 @@ def test_vortex_pair_2d_fd_check():
         with torch.no_grad():
             return float(objective(torch.from_numpy(p).cuda(), torch.tensor(gv, dtype=torch.float64), eps=eps,
                                    nsteps=nsteps, checkpoint_every=K))
+
+    def fd_dir(d, step=h):
+        return (Lof(psi0 + step * d, g) - Lof(psi0 - step * d, g)) / (2 * step)
+
     d = qi.random_field((64, 64), seed=53, scale=1.0)
-    fd = (Lof(psi0 + h * d, g) - Lof(psi0 - h * d, g)) / (2 * h)
     an = float(np.real(np.sum(np.conj(gp) * d)))
+    fd = fd_dir(d)
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    # single entries: a derivative ~1e-2 against L ~ 1e3 is below what a central difference resolves
+    # to 1e-6: at h = 1e-6 its rounding floor |L| 1e-16 / h is ~1e-7 (1e-5 relative), at h = 1e-4
+    # the O(h^2) truncation is ~1e-8 (1e-6 relative); the entries are checked at h = 1e-4 to 1e-5
+    rng = np.random.default_rng(55)
+    scale = np.abs(gp).max()
+    for _ in range(16):
+        m, y, x = int(rng.integers(5)), int(rng.integers(64)), int(rng.integers(64))
+        for unit in (1.0, 1j):
+            e = np.zeros_like(psi0)
+            e[m, y, x] = unit
+            an = float(np.real(np.conj(gp[m, y, x]) * unit))   # dL/dRe or dL/dIm at that entry
+            fd = fd_dir(e, 1e-4)
+            assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * scale), (m, y, x, unit, fd, an)
     for k in range(3):
         gp_, gm_ = list(g), list(g)
         gp_[k] += h
         gm_[k] -= h
         fdg = (Lof(psi0, gp_) - Lof(psi0, gm_)) / (2 * h)
         assert abs(fdg - gg[k]) <= 1e-6 * max(abs(gg[k]), 1e-6), (k, fdg, gg[k])
+    if case == "spin_texture":
+        assert abs(gg[1]) > 1e-3 * abs(gg[0])   # the spin coupling acts
+
+
+ADJOINT_REFERENCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                 "adjoint_64x64_oracle_grad.npz")
+
+
+@pytest.mark.parametrize("case", ["vortex_pair_T40", "vortex_pair_T125", "spin_texture_T40", "spin_texture_T125"])
+def test_64x64_gradient_matches_oracle_reference(case):
+    """The GPU FP64 gradient of the final energy on the 64^2 lattices (checkpoint every 64) against
+    the oracle's autograd gradient, stored by tests/golden/make_adjoint_reference.py (the oracle
+    alone): the vortex pair and the spin texture (F != 0 at every site) over 40 steps and over
+    125 steps, the physical time of the adjoint workload's 2000 steps at eps = 0.1.  The bound is
+    1e-10 relative, or ten times the gradient's own conditioning where that is larger: the
+    change the oracle's gradient shows when its input moves by one part in 1e15 (stored with it).
+    With g1 < 0 the pair's m = +2 / m = -2 symmetry is unstable, so over 125 steps rounding
+    already moves dL/dpsi0 of the vortex pair by ~1e-3 while dL/dg stays determined to ~1e-14."""
+    ref = np.load(ADJOINT_REFERENCE)
+    psi0 = qi.adjoint_vortex_pair_2d_64() if case.startswith("vortex_pair") else qi.adjoint_spin_texture_2d_64()
+    g, eps = tuple(float(v) for v in ref["g"]), float(ref["eps"])
+    nsteps = int(ref[case + "_steps"])
+    L, gp, gg = gpu_grad(psi0, g, eps, nsteps, K=64)
+    L0, gp0, gg0 = float(ref[case + "_L"]), ref[case + "_dpsi"], ref[case + "_dg"]
+    cond_p = rel(ref[case + "_perturbed_dpsi"], gp0)
+    cond_g = rel(ref[case + "_perturbed_dg"], gg0)
+    tol_p, tol_g = max(1e-10, 10 * cond_p), max(1e-10, 10 * cond_g)
+    print("%s: L %.17g vs %.17g; dpsi rel %.3e (bound %.1e), dg rel %.3e (bound %.1e); dg %s vs %s" %
+          (case, L, L0, rel(gp, gp0), tol_p, rel(gg, gg0), tol_g, gg, gg0))
+    assert abs(L - L0) <= 1e-12 * abs(L0), (L, L0)
+    assert rel(gp, gp0) <= tol_p, (rel(gp, gp0), tol_p)
+    assert rel(gg, gg0) <= tol_g, (gg, gg0, tol_g)
+    # over 40 steps the whole gradient is determined to ~1e-14 by FP64; over 125 steps the
+    # vortex pair's dL/dpsi0 is not (its unstable m = +-2 asymmetry amplifies rounding), dL/dg is
+    if case.endswith("T40"):
+        assert tol_p == 1e-10
+    assert tol_g == 1e-10
+    if case.startswith("spin"):
+        assert abs(gg0[1]) > 1e-3 * abs(gg0[0])
+
+
+def test_set_psi_adjoint_matches_oracle_encoding():
+    """The library's adjoint of the encoding a = b = psi / 2 against torch autograd of the oracle's
+    encoding, on a ragged two-instance batch: bit-identical (both halve a sum of two cotangents)."""
+    from paper_1907_12834_amd.qlg import Lattice
+    shapes = [(7, 9), (5, 13)]
+    lat = Lattice(2, [s[1] for s in shapes], [s[0] for s in shapes], g=G, eps=0.3, dtype="c64")
+    lams = [np.stack(qi.random_qubits(s, seed=60 + i, scale=1.0)) for i, s in enumerate(shapes)]
+    flat = torch.from_numpy(np.concatenate([l.reshape(-1) for l in lams])).cuda()
+    got = lat.set_psi_adjoint(flat)
+    for i, s in enumerate(shapes):
+        p = torch.zeros((5,) + s, dtype=torch.complex128, requires_grad=True)
+        a, b = O.encode(p)
+        (ref,) = torch.autograd.grad((a, b), (p,), grad_outputs=(torch.from_numpy(lams[i][0]),
+                                                                  torch.from_numpy(lams[i][1])))
+        assert np.array_equal(got[i].cpu().numpy(), ref.numpy())
 
 
 @pytest.mark.parametrize("split", ["interleaved", "plain"])

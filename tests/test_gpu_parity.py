@@ -118,16 +118,20 @@ def test_two_solitons_reduced(dtype):
     assert drift <= (1e-12 if dtype == "c128" else 1e-5)
 
 
-TWO_SOLITONS_REFERENCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                                      "two_solitons_L16384_oracle_psi.npz")
+TWO_SOLITONS_REFERENCE = {
+    -0.5: os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_solitons_L16384_oracle_psi.npz"),
+    0.5: os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "two_solitons_L16384_c1_plus05_oracle_psi.npz")}
 
 
+@pytest.mark.parametrize("c1", [-0.5, 0.5])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_two_solitons_L16384_parity_at_stated_lengths(dtype):
-    """The two-soliton workload in the autotuned launch plan, against the oracle's own states after
-    2000 and 20000 steps (written by tests/golden/make_two_solitons_reference.py from the oracle alone)."""
-    ref = np.load(TWO_SOLITONS_REFERENCE)
-    w = qi.two_solitons_1d_L16384()
+def test_two_solitons_L16384_parity_at_stated_lengths(dtype, c1):
+    """The two-soliton workload in the autotuned launch plan, for both spin couplings c1 = -0.5
+    and +0.5, against the oracle's own states after 2000 and 20000 steps (written by
+    tests/golden/make_two_solitons_reference.py from the oracle alone)."""
+    ref = np.load(TWO_SOLITONS_REFERENCE[c1])
+    w = qi.two_solitons_1d_L16384(c1=c1)
     assert int(ref["L"]) == w.nx[0] and float(ref["eps"]) == w.eps and tuple(ref["g"]) == tuple(w.g)
     lat = lattice(1, [w.nx[0]], g=w.g, eps=w.eps, dtype=dtype)
     lat.autotune()
