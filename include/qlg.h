@@ -138,6 +138,24 @@ qlg_status qlg_query_sizes(const qlg_params* params, size_t* state_bytes, size_t
 qlg_status qlg_init(const qlg_params* params, void* state_dev, size_t state_bytes,
                     void* scratch_dev, size_t scratch_bytes, void* hip_stream, qlg_ctx** out);
 
+/* qlg_init for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the caller
+ * passes no scratch buffer.  The context's scratch (the scratch_bytes of
+ * qlg_query_sizes: reduction partials and device tables) is a fixed array of
+ * QLG_STATIC_SCRATCH_BYTES in the library's own device memory, one per GPU,
+ * held until the process ends; this call allocates no device memory.  The
+ * caller still provides state_dev (as for qlg_init).  One such context per GPU
+ * at a time: QLG_ERR_STATE while another context made by this call lives on
+ * the current device (qlg_destroy releases the array after synchronising the
+ * context's stream); QLG_ERR_ARG when the lattice's scratch_bytes exceed
+ * QLG_STATIC_SCRATCH_BYTES, or as for qlg_init.  The array keeps what the
+ * previous context left in it; no kernel reads a value of it that the same
+ * context has not written first.  Every other call behaves as on a context
+ * made by qlg_init. */
+#define QLG_STATIC_SCRATCH_BYTES (16u << 20)
+qlg_status qlg_init_static(const qlg_params* params, void* state_dev, size_t state_bytes,
+                           void* hip_stream, qlg_ctx** out);
+
 /* Load psi (canonical layout) and encode a = b = psi / 2.  Resets the step counter. */
 qlg_status qlg_set_psi(qlg_ctx* ctx, const void* psi_dev);
 /* Decode psi = a + b into psi_dev (canonical layout). */

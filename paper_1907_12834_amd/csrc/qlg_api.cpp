@@ -124,6 +124,25 @@ std::map<std::string, qlg_tuning> g_tune_cache;
 
 }  // namespace
 
+// Scratch of the contexts that qlg_init_static creates: their reduction partials and device
+// tables (the scratch layout above), in one array per GPU that the process holds until it
+// ends.  In host code `scratch` names a host-side stand-in, not device memory: host code
+// uses only the address hipGetSymbolAddress returns for it, taken once per device with that
+// device current.
+static __device__ __align__(256) unsigned char scratch[QLG_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// Per device: the device address of `scratch`, and whether a live context uses it.
+struct StaticScratch {
+  char* ptr = nullptr;
+  bool in_use = false;
+};
+std::mutex g_static_mu;
+std::map<int, StaticScratch> g_static;
+
+}  // namespace
+
 struct qlg_ctx {
   qlg_params p{};
   std::vector<int64_t> nx, ny, nz;
@@ -145,6 +164,7 @@ struct qlg_ctx {
   qlg_tuning tuning{1, 32, 0, 0};
   qlg::ExtPot ext;               // external potential (caller's device array) and mu
   bool tuned = false;
+  int static_dev = -1;            // device whose static scratch this context uses, or -1
   // bookkeeping
   int64_t step_count = 0;
   bool has_overlap = false;
@@ -393,8 +413,8 @@ qlg_status qlg_query_sizes(const qlg_params* p, size_t* state_bytes, size_t* scr
   return QLG_OK;
 }
 
-qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, void* scratch_dev,
-                    size_t scratch_bytes, void* hip_stream, qlg_ctx** out) {
+static qlg_status init_ctx(const qlg_params* p, void* state_dev, size_t state_bytes, void* scratch_dev,
+                           size_t scratch_bytes, void* hip_stream, int static_dev, qlg_ctx** out) {
   if (!out) return QLG_ERR_ARG;
   *out = nullptr;
   const char* msg = nullptr;
@@ -408,6 +428,7 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
 
   qlg_ctx* c = new (std::nothrow) qlg_ctx();
   if (!c) return QLG_ERR_OOM;
+  c->static_dev = static_dev;
   c->p = *p;
   c->nx.assign(p->nx, p->nx + p->nbatch);
   if (p->ndim >= 2) c->ny.assign(p->ny, p->ny + p->nbatch);
@@ -461,10 +482,52 @@ qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, vo
   return QLG_OK;
 }
 
+qlg_status qlg_init(const qlg_params* p, void* state_dev, size_t state_bytes, void* scratch_dev,
+                    size_t scratch_bytes, void* hip_stream, qlg_ctx** out) {
+  return init_ctx(p, state_dev, state_bytes, scratch_dev, scratch_bytes, hip_stream, -1, out);
+}
+
+qlg_status qlg_init_static(const qlg_params* p, void* state_dev, size_t state_bytes, void* hip_stream,
+                           qlg_ctx** out) {
+  if (!out) return QLG_ERR_ARG;
+  *out = nullptr;
+  size_t need_state = 0, need_scratch = 0;
+  qlg_status s = qlg_query_sizes(p, &need_state, &need_scratch);
+  if (s) return s;
+  if (need_scratch > (size_t)QLG_STATIC_SCRATCH_BYTES) return QLG_ERR_ARG;   // lattice too large for it
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return QLG_ERR_DEVICE;
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticScratch& slot = g_static[dev];
+    if (slot.in_use) return QLG_ERR_STATE;   // one such context per device at a time
+    if (!slot.ptr) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return QLG_ERR_DEVICE;
+      slot.ptr = static_cast<char*>(ptr);
+    }
+    slot.in_use = true;
+    base = slot.ptr;
+  }
+  s = init_ctx(p, state_dev, state_bytes, base, (size_t)QLG_STATIC_SCRATCH_BYTES, hip_stream, dev, out);
+  if (s) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static[dev].in_use = false;
+  }
+  return s;
+}
+
 void qlg_destroy(qlg_ctx* c) {
   if (!c) return;
   drop_graphs(c);
   for (auto ev : c->ev) (void)hipEventDestroy(ev);
+  if (c->static_dev >= 0) {
+    // work still queued on the context's stream may use the array: let it finish first
+    (void)hipStreamSynchronize(c->stream);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static[c->static_dev].in_use = false;
+  }
   delete c;
 }
 

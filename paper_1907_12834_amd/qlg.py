@@ -22,10 +22,11 @@ STATUS_NAMES = {0: "QLG_OK", 1: "QLG_ERR_ARG", 2: "QLG_ERR_SHAPE", 3: "QLG_ERR_D
 C64, C128 = 0, 1
 INTERLEAVED, PLAIN = 0, 1
 RECORD_DOUBLES = 16   # QLG_RECORD_DOUBLES
+STATIC_SCRATCH_BYTES = 16 << 20   # QLG_STATIC_SCRATCH_BYTES
 
 # every symbol declared in include/qlg.h
 EXPORTED = [
-    "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
+    "qlg_version", "qlg_query_sizes", "qlg_init", "qlg_init_static", "qlg_set_psi", "qlg_get_psi", "qlg_set_qubits",
     "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_find_vortices", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_version": (i32, []),
         "qlg_query_sizes": (i32, [P(Params), P(sz), P(sz)]),
         "qlg_init": (i32, [P(Params), vp, sz, vp, sz, vp, P(vp)]),
+        "qlg_init_static": (i32, [P(Params), vp, sz, vp, P(vp)]),
         "qlg_set_psi": (i32, [vp, vp]),
         "qlg_get_psi": (i32, [vp, vp]),
         "qlg_set_qubits": (i32, [vp, vp]),
@@ -165,7 +167,8 @@ class Lattice:
     def __init__(self, ndim: int, nx: Sequence[int], ny: Optional[Sequence[int]] = None,
                  nz: Optional[Sequence[int]] = None,
                  g=(1.0, -0.5, 0.5), eps: float = 0.1, dtype: str = "c128",
-                 split: str = "interleaved", device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
+                 split: str = "interleaved", device="cuda:0", stream: Optional[torch.cuda.Stream] = None,
+                 static_scratch: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libqlg needs a HIP device; none is visible")
         self.ndim = ndim
@@ -184,14 +187,23 @@ class Lattice:
                                               nz if ndim == 3 else None)
         sb, cb = query_sizes(self.params)
         self.state_buf = _device_bytes(sb, self.device)
-        self.scratch_buf = _device_bytes(cb, self.device)
         self._pot = None   # device copy of the external potential while one is set
         ctx = ctypes.c_void_p()
-        st = lib().qlg_init(ctypes.byref(self.params), self.state_buf.data_ptr(), sb,
-                            self.scratch_buf.data_ptr(), cb, ctypes.c_void_p(self.stream.cuda_stream),
-                            ctypes.byref(ctx))
-        if st != QLG_OK:
-            raise QLGError(st, "qlg_init")
+        if static_scratch:
+            # the library's per-GPU scratch array (qlg_init_static): no scratch buffer here
+            self.scratch_buf = None
+            with torch.cuda.device(self.device):
+                st = lib().qlg_init_static(ctypes.byref(self.params), self.state_buf.data_ptr(), sb,
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+            if st != QLG_OK:
+                raise QLGError(st, "qlg_init_static")
+        else:
+            self.scratch_buf = _device_bytes(cb, self.device)
+            st = lib().qlg_init(ctypes.byref(self.params), self.state_buf.data_ptr(), sb,
+                                self.scratch_buf.data_ptr(), cb, ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(ctx))
+            if st != QLG_OK:
+                raise QLGError(st, "qlg_init")
         self.ctx = ctx
 
     # -- helpers -------------------------------------------------------------
