@@ -41,6 +41,9 @@ struct UFrame {
   cx<double> cs;       // c(n)
   cx<double> E[5];     // e^{-i (phi0 + m phi)}, m = 2..-2
   cx<double> u;        // e^{i alpha}
+  cx<double> e0, eh;   // e^{-i phi0}, e^{-i phi/2}
+  double sh_phi;       // sin(phi/2)
+  cx<double> ekn;      // e^{-i kappa n}, kappa = theta g2 / 5
   double ca, sa, cb, sb;
   // d^2(beta) entries d_{m'm} for m' >= |m|; the rest by d_{m'm} = (-1)^{m-m'} d_{mm'} = d_{-m,-m'}
   double d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;
@@ -77,32 +80,47 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
   f.Fx = 2.0 * f1.re + r6 * f2.re;
   f.Fy = 2.0 * f1.im + r6 * f2.im;
   const double Fp2 = f.Fx * f.Fx + f.Fy * f.Fy;
-  f.Fperp = sqrt(Fp2);
-  f.Fn = sqrt(Fp2 + f.Fz * f.Fz);
+  const double Fn2 = Fp2 + f.Fz * f.Fz;
+  // |F|, F_perp and their reciprocals (below the normal range the frame is immaterial: phi ~ 0)
+  const double tiny2 = 1e-300;
+  const double iP = Fp2 > tiny2 ? rsqrt_t(Fp2) : 0.0, iF = Fn2 > tiny2 ? rsqrt_t(Fn2) : 0.0;
+  f.Fperp = Fp2 * iP;
+  f.Fn = Fn2 * iF;
   f.phi0 = theta * g0 * f.n + ext;
   f.phi = theta * g1 * f.Fn;
-  for (int i = 0; i < 5; ++i) {
-    const double m = 2 - i;
-    double s, c;
-    sincos(f.phi0 + m * f.phi, &s, &c);
-    f.E[i] = cx<double>{c, -s};
+  // E_m = e^{-i phi0} (e^{-i phi})^m from two phases: e^{-i phi0} and eh = e^{-i phi/2}
+  {
+    double s0, c0, s1, c1;
+    sincos_t(f.phi0, &s0, &c0);
+    sincos_t(0.5 * f.phi, &s1, &c1);
+    const cx<double> e0{c0, -s0}, eh{c1, -s1}, e1 = eh * eh;
+    f.E[2] = e0;
+    f.E[1] = e0 * e1;
+    f.E[0] = f.E[1] * e1;
+    f.E[3] = e0 * conj(e1);
+    f.E[4] = f.E[3] * conj(e1);
+    f.e0 = e0;
+    f.eh = eh;
+    f.sh_phi = s1;
   }
   // c(n) = (e^{-i kappa n} - 1)/n = kappa sinc(h) (-sin h - i cos h), h = kappa n / 2
   const double kappa = theta * g2 / 5.0, h = 0.5 * kappa * f.n;
   double sh, ch;
-  sincos(h, &sh, &ch);
-  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h / 6.0 : sh / h;
+  sincos_t(h, &sh, &ch);
+  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h / 6.0 : sh * rcp_t(h);
   f.cs = cx<double>{-kappa * sinc * sh, -kappa * sinc * ch};
+  f.ekn = cx<double>{ch, -sh} * cx<double>{ch, -sh};   // e^{-i kappa n}
   // frame
-  const double tiny = 1e-280;
   f.ca = 1.0; f.sa = 0.0; f.cb = 1.0; f.sb = 0.0;
   double opc = 2.0, omc = 0.0;
-  if (f.Fperp > tiny) { f.ca = f.Fx / f.Fperp; f.sa = f.Fy / f.Fperp; }
-  if (f.Fn > tiny) {
-    f.cb = f.Fz / f.Fn;
-    f.sb = f.Fperp / f.Fn;
-    if (f.Fz >= 0) { const double A = f.Fn + f.Fz; opc = A / f.Fn; omc = Fp2 / A / f.Fn; }
-    else { const double B = f.Fn - f.Fz; omc = B / f.Fn; opc = Fp2 / B / f.Fn; }
+  if (Fp2 > tiny2) { f.ca = f.Fx * iP; f.sa = f.Fy * iP; }
+  if (Fn2 > tiny2) {
+    f.cb = f.Fz * iF;
+    f.sb = f.Fperp * iF;
+    // |F| (1 +- cos beta) without cancellation: the larger of |F| +- F_z directly, the other from it
+    const double big = f.Fn + fabs(f.Fz), other = Fp2 * rcp_t(big);
+    opc = (f.Fz >= 0 ? big : other) * iF;
+    omc = (f.Fz >= 0 ? other : big) * iF;
   }
   f.u = cx<double>{f.ca, f.sa};
   const double cb = f.cb, sb = f.sb;
@@ -155,31 +173,26 @@ QLG_HD void apply_S(const cx<double> (&z)[5], cx<double> (&out)[5]) {
   out[4] = z[0];
 }
 
-QLG_HD double sinc_d(double x) { return fabs(x) < 1e-4 ? 1.0 - x * x / 6.0 : sin(x) / x; }
-
-// c'(n) for c(n) = (e^{-i k n} - 1)/n
-QLG_HD cx<double> dc_dn(double kappa, double n) {
+// c'(n) for c(n) = (e^{-i k n} - 1)/n; e = e^{-i k n}.  For |k n| < 0.1 the series
+// c'(n) = sum_{j>=2} (-i k)^j (j-1) n^{j-2} / j! = (-i k)^2 sum_{q>=0} (q+1)/(q+2)! (-i z)^q,
+// z = k n, truncated after q = 12 (the next term is below 1e-24): its real and imaginary
+// parts are the even and odd powers of z, two polynomials in z^2.
+QLG_HD cx<double> dc_dn(double kappa, double n, cx<double> e) {
   const double z = kappa * n;
   if (fabs(z) < 0.1) {
-    // sum_{j>=2} (-i kappa)^j (j-1) n^{j-2} / j!
-    cx<double> acc{0.0, 0.0};
-    cx<double> mik{0.0, -kappa};            // -i kappa
-    cx<double> pw = mik * mik;              // (-i kappa)^2
-    double npow = 1.0, fact = 2.0;
-    for (int j = 2; j <= 14; ++j) {
-      acc = acc + ((j - 1) * npow / fact) * pw;
-      pw = pw * mik;
-      npow *= n;
-      fact *= (j + 1);
-    }
-    return acc;
+    const double y = z * z;
+    // (q+1)/(q+2)! for q = 0..12, alternating in sign within each parity
+    const double pe = 1.0 / 2 + y * (-1.0 / 8 + y * (1.0 / 144 + y * (-1.0 / 5760 + y * (1.0 / 403200 +
+                      y * (-1.0 / 43545600 + y * (1.0 / 6706022400.0))))));
+    const double po = 1.0 / 3 + y * (-1.0 / 30 + y * (1.0 / 840 + y * (-1.0 / 45360 + y * (1.0 / 3991680 +
+                      y * (-1.0 / 518918400.0)))));
+    const double k2 = kappa * kappa;
+    return cx<double>{-k2 * pe, k2 * z * po};   // -k^2 (pe - i z po)
   }
-  double s, c;
-  sincos(z, &s, &c);
-  const cx<double> e{c, -s};                                  // e^{-i k n}
-  const cx<double> cn = (1.0 / n) * (e - cx<double>{1.0, 0.0});
+  const double in = rcp_t(n);
+  const cx<double> cn = in * (e - cx<double>{1.0, 0.0});
   const cx<double> t = cx<double>{0.0, -kappa} * e;            // -i k e^{-ikn}
-  return (1.0 / n) * (t - cn);
+  return in * (t - cn);
 }
 
 // In: a, b (input of U), la, lb (cotangents of U's outputs).
@@ -202,17 +215,23 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
   double dFx = 0.0, dFy = 0.0, dGz = 0.0;
   cx<double> lpsi[5] = {};
   const double cfac[4] = {2.0, Consts::r6, Consts::r6, 2.0};
-  const cx<double> e0{cos(f.phi0), -sin(f.phi0)};
-  const double sc = sinc_d(0.5 * f.phi);
-  // divided differences between neighbouring m: Delta = e^{-i phi0} e^{-i phi (m_i + m_{i+1})/2} sinc(phi/2)
+  // sinc(phi/2), from the sine of the frame's half phase
+  const double hp = 0.5 * f.phi;
+  const double sc = fabs(hp) < 1e-4 ? 1.0 - hp * hp / 6.0 : f.sh_phi * rcp_t(hp);
+  // divided differences between neighbouring m: Delta = e^{-i phi0} e^{-i phi (m_i + m_{i+1})/2} sinc(phi/2),
+  // m_i + m_{i+1} = 3, 1, -1, -3: powers of eh = e^{-i phi/2}
   cx<double> dlt[4];
-  for (int i = 0; i < 4; ++i) {
-    const double msum = (2 - i) + (1 - i);
-    dlt[i] = sc * (e0 * cx<double>{cos(0.5 * f.phi * msum), -sin(0.5 * f.phi * msum)});
+  {
+    const cx<double> w1 = sc * (f.e0 * f.eh), w3 = w1 * (f.eh * f.eh);
+    const cx<double> v1 = sc * (f.e0 * conj(f.eh)), v3 = v1 * conj(f.eh * f.eh);
+    dlt[0] = w3;
+    dlt[1] = w1;
+    dlt[2] = v1;
+    dlt[3] = v3;
   }
   const double kappa = theta * g2 / 5.0;
-  const cx<double> dcn = dc_dn(kappa, f.n);
-  const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * cx<double>{cos(kappa * f.n), -sin(kappa * f.n)};
+  const cx<double> dcn = dc_dn(kappa, f.n, f.ekn);
+  const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * f.ekn;
   // one 5-vector x; l holds the output cotangent on entry and P^H lambda_{y1} on exit
   auto one = [&](const cx<double>(&x)[5], cx<double>(&l)[5]) {
     cx<double> s{0.0, 0.0};

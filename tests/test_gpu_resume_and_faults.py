@@ -1,0 +1,138 @@
+"""Checkpoint/resume and numeric fault detection through the C ABI.
+
+Resume: a run split at any step, its qubits read back with qlg_get_qubits and loaded into a
+fresh context with qlg_set_qubits, ends bit-identical to the uninterrupted run (1D, 2D, 3D;
+both dtypes).  Faults: a non-finite amplitude loaded from the host is reported as
+QLG_ERR_NUMERIC by qlg_observables and by the decoding of device-side records, without
+breaking the context; so is a record whose qubit norm has drifted beyond the dtype's bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import qlg_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+G = (1.1, -0.6, 0.8)
+
+
+def lattice(*args, **kw):
+    from paper_1907_12834_amd.qlg import Lattice
+    return Lattice(*args, **kw)
+
+
+CASES = [
+    (1, (300,), {"steps_per_pass": 3, "qubit_split": 0}),
+    (1, (300,), {"steps_per_pass": 2, "qubit_split": 2}),
+    (2, (40, 70), {"tile_rows": 16}),
+    (3, (10, 12, 70), {"tile_rows": 8}),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("ndim,shape,plan", CASES)
+def test_resume_from_qubits_is_bit_identical(ndim, shape, plan, dtype):
+    psi = qi.random_field(shape, seed=81, scale=0.4)
+    dims = dict(nx=[shape[-1]], ny=[shape[-2]] if ndim >= 2 else None, nz=[shape[0]] if ndim == 3 else None)
+    n1, n2 = 13, 8   # split inside a 1D pass of several steps, and at an odd step
+    ref = lattice(ndim, g=G, eps=0.3, dtype=dtype, **dims)
+    ref.set_tuning(**plan)
+    ref.set_psi([torch.from_numpy(psi)])
+    ref.step(n1 + n2)
+    want = ref.get_qubits()[0].cpu().numpy()
+    first = lattice(ndim, g=G, eps=0.3, dtype=dtype, **dims)
+    first.set_tuning(**plan)
+    first.set_psi([torch.from_numpy(psi)])
+    first.step(n1)
+    saved = first.get_qubits()[0].cpu().numpy()   # the checkpoint, in host memory
+    first.close()
+    second = lattice(ndim, g=G, eps=0.3, dtype=dtype, **dims)
+    second.set_tuning(**plan)
+    second.set_qubits([torch.from_numpy(saved)])
+    second.step(n2)
+    got = second.get_qubits()[0].cpu().numpy()
+    assert np.array_equal(got, want)
+    assert second.observables()[0]["step"] == n2
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_non_finite_amplitude_is_reported(dtype):
+    from paper_1907_12834_amd.qlg import QLGError
+    a, b = qi.random_qubits((5, 40), seed=82, scale=0.3)
+    qb = np.stack([a, b])
+    lat = lattice(2, [40], [5], g=G, eps=0.3, dtype=dtype)
+    lat.set_qubits([torch.from_numpy(qb)])
+    assert lat.observables()[0]["step"] == 0             # finite state: accepted
+    bad = qb.copy()
+    bad[1, 3, 2, 17] = complex(np.nan, 0.0)               # one amplitude of qubit b, m = -1
+    lat.set_qubits([torch.from_numpy(bad)])
+    with pytest.raises(QLGError) as e:
+        lat.observables()
+    assert e.value.status == 7                           # QLG_ERR_NUMERIC
+    lat.step(3)                                          # the NaN spreads; still reported
+    with pytest.raises(QLGError) as e:
+        lat.observables()
+    assert e.value.status == 7
+    rec = lat.new_records(1)
+    lat.record_observables(rec, 0)
+    with pytest.raises(QLGError) as e:
+        lat.decode_records(rec)
+    assert e.value.status == 7
+    # a numeric error does not break the context: a finite state is accepted again
+    lat.set_qubits([torch.from_numpy(qb)])
+    lat.step(3)
+    assert lat.observables()[0]["step"] == 3
+    bad[0, 0, 0, 0] = complex(0.0, np.inf)
+    lat.set_qubits([torch.from_numpy(bad)])
+    with pytest.raises(QLGError) as e:
+        lat.observables()
+    assert e.value.status == 7
+
+
+@pytest.mark.parametrize("dtype,bound", [("c128", 1e-10), ("c64", 1e-4)])
+def test_norm_drift_in_a_record_is_reported(dtype, bound):
+    """The qubit norm of a record is checked against the norm at set time (held in the record):
+    a record whose norm is scaled beyond the dtype's bound decodes to QLG_ERR_NUMERIC, one
+    within it decodes."""
+    from paper_1907_12834_amd.qlg import QLGError
+    psi = qi.random_field((64,), seed=83, scale=0.4)
+    lat = lattice(1, [64], g=G, eps=0.3, dtype=dtype)
+    lat.set_psi([torch.from_numpy(psi)])
+    lat.step(5)
+    rec = lat.new_records(1)
+    lat.record_observables(rec, 0)
+    host = rec.cpu()
+    lat.decode_records(host)                             # as recorded: accepted
+    within = host.clone()
+    within[0, 0, 0] *= 1 + 0.5 * bound                   # slot 0: the qubit-norm sum
+    lat.decode_records(within)
+    beyond = host.clone()
+    beyond[0, 0, 0] *= 1 + 4 * bound
+    with pytest.raises(QLGError) as e:
+        lat.decode_records(beyond)
+    assert e.value.status == 7
+
+
+def test_tune_cache_file_persists_plans(tmp_path, monkeypatch):
+    """QLG_TUNE_CACHE names a text file of launch plans: a new context takes the last valid line
+    for its key (device, dtype, ndim, split, batched, size class), and qlg_autotune appends its
+    choice."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("QLG_TUNE_CACHE", str(path))
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    sites = 3000
+    key = "%s|0|1|0|0|%d" % (arch, (sites - 1).bit_length())   # c64, 1D, interleaved, single
+    path.write_text("%s 5 0 1 1\n%s 9 0 1 1\n" % (key, key))      # the second line is out of range
+    lat = lattice(1, [sites], g=G, eps=0.3, dtype="c64")
+    assert lat.tuning() == {"steps_per_pass": 5, "tile_rows": 0, "use_graph": 1, "qubit_split": 1}
+    lat.close()
+    lat2 = lattice(2, [100], [90], g=G, eps=0.3, dtype="c128")
+    plan = lat2.autotune()
+    last = path.read_text().splitlines()[-1].split()
+    assert last[0].startswith(arch + "|1|2|0|0|")
+    assert [int(v) for v in last[1:]] == [plan["steps_per_pass"], plan["tile_rows"], plan["use_graph"],
+                                          plan["qubit_split"]]
+    lat2.close()
+    lat3 = lattice(2, [100], [90], g=G, eps=0.3, dtype="c128")
+    assert lat3.tuning() == plan
