@@ -76,10 +76,17 @@ __device__ __forceinline__ void iprime4_lanes(cx<T> (&a)[5], cx<T> (&b)[5]) {
 }
 
 // Angles of interleaved substep j = 0..3 of a four-I' sequence, on a state that
-// carries the factor 4^j of the j I' before it (uniform selects, no indexing).
+// carries the factor 4^j of the j I' before it: the n terms' angles and F's scale
+// times 16^-j (exact).  Formed from the unscaled angles in registers, so that a
+// run-time j reads no kernel argument inside the row loop.
 template <typename T>
-__device__ __forceinline__ Angles<T> substep_angles(const Angles<T> (&t)[4], int j) {
-  return j == 0 ? t[0] : j == 1 ? t[1] : j == 2 ? t[2] : t[3];
+__device__ __forceinline__ Angles<T> substep_angles(const Angles<T>& base, int j) {
+  const T f = ldexp(T(1), -4 * j);
+  Angles<T> a = base;
+  a.tg0 *= f;
+  a.tg25 *= f;
+  a.fs = f;
+  return a;
 }
 
 __device__ __forceinline__ int64_t wrap64(int64_t x, int64_t n) {
@@ -102,8 +109,8 @@ struct StepArgs {
   const InstDesc* __restrict__ inst;
   const int32_t* __restrict__ tile2inst;
   double* __restrict__ ovpart;   // [ntiles][2] overlap partials (written when overlap != 0)
-  Angles<T> ang[4];              // interleaved U^{1/(4d)}, theta = eps^2 / (4 d), for a state
-                                 // scaled by 4^j (substep j of a four-I' sequence)
+  Angles<T> ang;                 // interleaved U^{1/(4d)}, theta = eps^2 / (4 d), unscaled state
+                                 // (substep_angles scales it for substep j of a four-I' sequence)
   Angles<T> ang_full;            // plain split: theta = eps^2, unscaled state
   const double* __restrict__ pot;  // V(x), canonical scalar layout (nullptr: none); kExt kernels only
   double mu;                     // chemical potential; kExt kernels only
@@ -911,13 +918,7 @@ static StepArgs<T> step_args(const void* in, void* out, const LaunchGeom& g, dou
   A.inst = g.inst;
   A.tile2inst = g.tile2inst;
   A.ovpart = ovpart;
-  for (int j = 0; j < 4; ++j) {   // state scaled by 4^j: theta n and theta F unchanged
-    const T f = T(std::ldexp(1.0, -4 * j));
-    A.ang[j] = angles<T>(tg0, tg1, tg25);
-    A.ang[j].tg0 *= f;
-    A.ang[j].tg25 *= f;
-    A.ang[j].fs = f;
-  }
+  A.ang = angles<T>(tg0, tg1, tg25);
   A.ang_full = angles<T>(full_factor * tg0, full_factor * tg1, full_factor * tg25);
   A.pot = ext.V;
   A.mu = ext.mu;

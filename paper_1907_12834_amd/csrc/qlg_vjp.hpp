@@ -104,10 +104,10 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
     f.sh_phi = s1;
   }
   // c(n) = (e^{-i kappa n} - 1)/n = kappa sinc(h) (-sin h - i cos h), h = kappa n / 2
-  const double kappa = theta * g2 / 5.0, h = 0.5 * kappa * f.n;
+  const double kappa = theta * g2 * 0.2, h = 0.5 * kappa * f.n;
   double sh, ch;
   sincos_t(h, &sh, &ch);
-  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h / 6.0 : sh * rcp_t(h);
+  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h * (1.0 / 6.0) : sh * rcp_t(h);
   f.cs = cx<double>{-kappa * sinc * sh, -kappa * sinc * ch};
   f.ekn = cx<double>{ch, -sh} * cx<double>{ch, -sh};   // e^{-i kappa n}
   // frame
@@ -217,7 +217,7 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
   const double cfac[4] = {2.0, Consts::r6, Consts::r6, 2.0};
   // sinc(phi/2), from the sine of the frame's half phase
   const double hp = 0.5 * f.phi;
-  const double sc = fabs(hp) < 1e-4 ? 1.0 - hp * hp / 6.0 : f.sh_phi * rcp_t(hp);
+  const double sc = fabs(hp) < 1e-4 ? 1.0 - hp * hp * (1.0 / 6.0) : f.sh_phi * rcp_t(hp);
   // divided differences between neighbouring m: Delta = e^{-i phi0} e^{-i phi (m_i + m_{i+1})/2} sinc(phi/2),
   // m_i + m_{i+1} = 3, 1, -1, -3: powers of eh = e^{-i phi/2}
   cx<double> dlt[4];
@@ -229,9 +229,9 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     dlt[2] = v1;
     dlt[3] = v3;
   }
-  const double kappa = theta * g2 / 5.0;
+  const double kappa = theta * g2 * 0.2;
   const cx<double> dcn = dc_dn(kappa, f.n, f.ekn);
-  const cx<double> dcg = cx<double>{0.0, -theta / 5.0} * f.ekn;
+  const cx<double> dcg = cx<double>{0.0, -theta * 0.2} * f.ekn;
   // one 5-vector x; l holds the output cotangent on entry and P^H lambda_{y1} on exit
   auto one = [&](const cx<double>(&x)[5], cx<double>(&l)[5]) {
     cx<double> s{0.0, 0.0};
