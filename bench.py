@@ -51,41 +51,14 @@ PEAK_HBM_GBS = 8000.0
 OBS_EVERY = 100
 PREROLL_S = 0.2        # untimed steps right before each clock start, at least this long
 
-# HBM traffic of one launch of the fused step (complex64, interleaved split), by workload, kernel and
-# plan (steps per pass in 1D, band height in 2D and 3D), from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch,
-# mean over the dispatches of that plan), each scaled by what the same counter reads for a
-# 256 MiB device copy in the same run (FETCH_SIZE: x2.000, WRITE_SIZE: x1.000).  Valid only
-# for the kernel sources it was measured on.
+# HBM traffic of one launch of the fused step, by (workload, storage, split) and by kernel and
+# plan (steps per pass in 1D, band height in 2D and 3D), from rocprofv3 --pmc FETCH_SIZE and
+# --pmc WRITE_SIZE runs (KiB per dispatch, median over the dispatches of that plan), each scaled
+# by what the same counter reads for a 256 MiB device copy in the same run (FETCH_SIZE: x2.000,
+# WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "93d4cbc578062042", "fetch_scale": 262144.0 / 131093.1, "write_scale": 1.0,
-           "kib": {
-               # 1D two-soliton workload, L = 16384 (steps per pass; the 64-site kernels' S = 7
-               # and the chosen plan of that run: median, the mean being lifted by a few outliers)
-               "1d_two_soliton_scattering": {
-                   "k_step1d/S1": (769.6, 1280.0), "k_step1d/S2": (770.4, 1280.0), "k_step1d/S3": (769.9, 1280.0),
-                   "k_step1d/S4": (769.0, 1280.0), "k_step1d/S5": (779.8, 1280.0), "k_step1d/S6": (780.0, 1281.0),
-                   "k_step1d/S7": (782.0, 1280.0), "k_step1d_pair/S1": (762.2, 1280.0),
-                   "k_step1d_pair/S2": (762.9, 1280.0), "k_step1d_pair/S3": (762.4, 1280.0),
-                   "k_step1d_pair/S4": (761.5, 1280.0), "k_step1d_lanes/S1": (766.8, 1280.0),
-                   "k_step1d_lanes/S2": (767.0, 1280.0), "k_step1d_lanes/S3": (769.0, 1280.0)},
-               # 2D vortex-pair workload, 2048^2 (bands of rows)
-               "2d_vortex_pair": {
-                   "k_step2d/rows38": (234781.6, 328525.3), "k_step2d/rows76": (214349.1, 328191.2),
-                   "k_step2d/rows64": (220085.9, 328337.9), "k_step2d/rows32": (231564.2, 328711.8),
-                   "k_step2d/rows25": (238481.1, 329204.5), "k_step2d/rows19": (260785.1, 329015.4),
-                   "k_step2d/rows16": (272929.7, 330036.9), "k_step2d/rows128": (182796.2, 327894.3)},
-               # 3D vortex-line workload, 256^3: one step = z pass + y-x pass (sums of the two)
-               "3d_vortex_lines": {
-                   "k_step3d/rows16": (983204.5 + 1214905.4, 1310720.0 + 1323689.3),
-                   "k_step3d/rows32": (819395.7 + 1051515.7, 1310720.0 + 1316937.2),
-                   "k_step3d/rows64": (737450.9 + 921904.6, 1310720.0 + 1314032.1),
-                   "k_step3d/rows86": (722084.4 + 875162.9, 1310720.0 + 1314401.4),
-                   "k_step3d/rows128": (696474.5 + 809668.8, 1310720.0 + 1317562.4),
-                   "k_step3d/rows256": (675983.6 + 829412.5, 1310720.0 + 1317913.4)},
-               # the 512^3 cube, at the plan its autotuner chooses
-               "3d_vortex_lines_512": {
-                   "k_step3d/rows128": (5570906.8 + 8049981.2, 10485760.0 + 10506076.6)}}}
+TRAFFIC = {"sources_sha256_16": None, "fetch_scale": 2.0, "write_scale": 1.0, "kib": {}}
 
 
 def parse():
@@ -357,13 +330,15 @@ def batched_ratio(steps):
             "speedup": ts / tb, "plan": plan}
 
 
-def adjoint_ratio(steps, K):
-    """(forward with checkpoints + reverse sweep) vs the plain forward, 2D 512^2 vortex pair, c64."""
+def adjoint_ratio(steps, K, spin_texture=False):
+    """(forward with checkpoints + reverse sweep) vs the plain forward, 2D 512^2 vortex pair, c64
+    (with spin_texture: plus a seeded random spinor, so that F != 0 at every site)."""
     import torch
     import qlg_inputs as qi
     from paper_1907_12834_amd.qlg import Lattice
 
-    w = qi.adjoint_vortex_pair_2d_512(nsteps=steps, checkpoint_every=K)
+    w = (qi.adjoint_spin_texture_2d_512 if spin_texture else qi.adjoint_vortex_pair_2d_512)(
+        nsteps=steps, checkpoint_every=K)
     psi = torch.from_numpy(w.psi[0])
     lat = Lattice(2, w.nx, w.ny, g=w.g, eps=w.eps, dtype="c64")
     lat.set_psi([psi])
@@ -383,8 +358,10 @@ def adjoint_ratio(steps, K):
     dg = lat.adjoint_step(steps, K, ck, lam)
     torch.cuda.synchronize()
     ta = time.perf_counter() - t0
-    return {"workload": "2D %dx%d vortex pair, c64 forward, FP64 self-interaction Jacobian, %d steps, checkpoint "
-                        "every %d, gradient of the final energy" % (w.nx[0], w.ny[0], steps, K),
+    return {"workload": "2D %dx%d vortex pair%s, c64 forward, FP64 self-interaction Jacobian, %d steps, "
+                        "checkpoint every %d, gradient of the final energy" %
+                        (w.nx[0], w.ny[0], " with a random spinor of amplitude %g added (F != 0 everywhere)" %
+                         w.meta["noise"] if spin_texture else "", steps, K),
             "forward_s": tf, "forward_plus_adjoint_s": ta, "ratio": ta / tf,
             "dL_dg": [a + b for a, b in zip(dg, dg0)]}
 
@@ -438,9 +415,8 @@ def main():
         kernel = "k_step2d (z pass + y-x pass)"
         key = "k_step3d/rows%d" % m["tuning"]["tile_rows"]
     traffic = None
-    measured = TRAFFIC["kib"].get(args.workload, {})
-    if args.dtype == "c64" and args.split == "interleaved" and key in measured \
-            and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
+    measured = TRAFFIC["kib"].get("%s/%s/%s" % (args.workload, args.dtype, args.split), {})
+    if key in measured and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:
         fk, wk = measured[key]
         traffic = 1024.0 * (fk * TRAFFIC["fetch_scale"] + wk * TRAFFIC["write_scale"])
 
@@ -456,6 +432,8 @@ def main():
     adjoint = adjoint_ratio(args.adjoint_steps, 64) if args.adjoint_steps > 0 else None
     if adjoint:
         progress("adjoint: ratio %.3g" % adjoint["ratio"])
+        adjoint["spin_texture"] = adjoint_ratio(args.adjoint_steps, 64, spin_texture=True)
+        progress("adjoint, spin texture: ratio %.3g" % adjoint["spin_texture"]["ratio"])
     diag = diagnostics(args.workload, args.dtype, args.diag_reps) if args.diag_reps > 0 else None
     if diag:
         progress("diagnostics done")

@@ -209,21 +209,75 @@ struct Consts {
 };
 
 // Coefficients of W for one site, computed once and applied to a and to b.
+//
+// The real spin-2 rotation d(beta) satisfies d_{-m',-m} = (-1)^{m'-m} d_{m'm}, so it
+// commutes with the flip (J x)_m = (-1)^m x_{-m} and splits into blocks on the
+// combinations x_m +- x_{-m}: applied through them it takes 21 multiply-adds per
+// complex 5-vector instead of 25.  In terms of c = cos beta, s = sin beta the block
+// entries are
+//   A = (d22 + d2-2)/2 = 1/2 - s^2/4,  B = (d22 - d2-2)/2 = (d11 + d1-1)/2 = c/2,
+//   C = (d21 + d2-1)/2 = -s/2,         E = (d21 - d2-1)/2 = -s c/2,
+//   G = (d11 - d1-1)/2 = c^2 - 1/2,
+// with d20 = sqrt(3/8) s^2, d10 = -sqrt(3/2) s c, d00 = (3 c^2 - 1)/2.
+template <typename T>
+struct DBlocks {
+  T dA, dB, dC, dE, dG, d20, d10, d00;
+};
+
+template <typename T>
+QLG_HD DBlocks<T> d_blocks(T cb, T sb) {
+  const T r32 = T(Consts::r32), r38 = T(Consts::r38);
+  const T sb2 = sb * sb, cb2 = cb * cb, sbcb = sb * cb;
+  DBlocks<T> D;
+  D.dA = T(0.5) - T(0.25) * sb2;
+  D.dB = T(0.5) * cb;
+  D.dC = T(-0.5) * sb;
+  D.dE = T(-0.5) * sbcb;
+  D.dG = cb2 - T(0.5);
+  D.d20 = r38 * sb2;
+  D.d10 = -r32 * sbcb;
+  D.d00 = T(1.5) * cb2 - T(0.5);
+  return D;
+}
+
 template <typename T>
 struct WCoef {
   cx<T> p[5];                                  // psi = a + b
   cx<T> cs;                                    // (exp(-i th g2 n/5) - 1) / n (0/0 -> -i th g2/5)
   cx<T> dl[5];                                 // exp(-i (th g0 n + k phi)) - 1, k = 2..-2
   cx<T> u, u2;                                 // e^{i alpha}, e^{2 i alpha}
-  T d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;   // d^2_{m'm}(beta), m' >= |m|
+  DBlocks<T> d;                                // d^2(beta) in the blocks above
 };
+
+// y = d(beta)^T x and y = d(beta) x for a complex 5-vector (m = 2..-2) through the
+// blocks of WCoef: with s0 = x_2 + x_-2, t0 = x_2 - x_-2, s1 = x_1 + x_-1, t1 = x_1 - x_-1,
+//   (d^T x)_{2,-2} = (A s0 - E t1 + d20 x0) +- (B t0 - C s1),
+//   (d^T x)_{1,-1} = (C t0 + B s1) +- (E s0 + G t1 - d10 x0),
+//   (d^T x)_0      = d20 s0 + d10 t1 + d00 x0,
+//   (d x)_{2,-2}   = (A s0 + E t1 + d20 x0) +- (B t0 + C s1),
+//   (d x)_{1,-1}   = (B s1 - C t0) +- (G t1 - E s0 + d10 x0),
+//   (d x)_0        = d20 s0 - d10 t1 + d00 x0.
+template <typename T, bool kTranspose>
+QLG_HD void d_apply(const DBlocks<T>& W, const cx<T> (&x)[5], cx<T> (&y)[5]) {
+  const cx<T> s0 = x[0] + x[4], t0 = x[0] - x[4], s1 = x[1] + x[3], t1 = x[1] - x[3];
+  const T sgn = kTranspose ? T(-1) : T(1);
+  const cx<T> P = rfma(W.d20, x[2], rfma(sgn * W.dE, t1, W.dA * s0));
+  const cx<T> Q = rfma(sgn * W.dC, s1, W.dB * t0);
+  const cx<T> R = rfma(-sgn * W.dC, t0, W.dB * s1);
+  const cx<T> S = rfma(sgn * W.d10, x[2], rfma(W.dG, t1, (-sgn) * W.dE * s0));
+  y[0] = P + Q;
+  y[4] = P - Q;
+  y[1] = R + S;
+  y[3] = R - S;
+  y[2] = rfma(W.d00, x[2], rfma(-sgn * W.d10, t1, W.d20 * s0));
+}
 
 // kExt: the equation of motion carries the psi-independent term (V(x) + mu) psi_m
 // (Sec. II, "Additional terms"); ext = theta (V(x) + mu) joins the density phase.
 template <typename T, bool kExt = false>
 QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angles<T> ang, WCoef<T>& W,
                            T ext = T(0)) {
-  const T r6 = T(Consts::r6), r32 = T(Consts::r32), r38 = T(Consts::r38);
+  const T r6 = T(Consts::r6);
   T q[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -272,32 +326,20 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
   const T sinc = fabs(h2) < T(1e-4) ? T(1) - h2 * h2 * T(1.0 / 6.0) : s2 * rcp_t(h2);
   W.cs = cx<T>{-ang.tg25 * sinc * s2, -ang.tg25 * sinc * c2};
 
-  // frame of F: u = e^{i alpha}, cos beta, sin beta, 1 +- cos beta without cancellation
+  // frame of F: u = e^{i alpha}, cos beta, sin beta.  With F_perp = 0, beta is 0 or pi
+  // exactly, and d(beta) is taken exactly diagonal or anti-diagonal, so that components that
+  // are zero and have no source stay exactly zero.
   cx<T> u{T(1), T(0)};
-  T cb = T(1), sb = T(0), opc = T(2), omc = T(0);
+  T cb = T(1), sb = T(0);
   if (has_perp) u = cx<T>{Fx * ip, Fy * ip};
   if (has_F) {
-    cb = Fz * iF;
+    cb = has_perp ? Fz * iF : (Fz >= T(0) ? T(1) : T(-1));
     sb = Fperp * iF;
-    // |F| (1 + cos beta) = |F| + F_z, |F| (1 - cos beta) = F_perp^2 / (|F| + F_z): the larger
-    // of |F| +- F_z is formed directly and the other from it
-    const T big = Fn + fabs(Fz);
-    const T other = Fp2 * rcp_t(big);
-    opc = (Fz >= T(0) ? big : other) * iF;
-    omc = (Fz >= T(0) ? other : big) * iF;
   }
   W.u = u;
   W.u2 = u * u;
-  // spin-2 Wigner small-d entries d_{m'm}(beta) for m' >= |m| (the rest by symmetry)
-  W.d22 = T(0.25) * opc * opc;
-  W.d21 = T(-0.5) * sb * opc;
-  W.d20 = r38 * sb * sb;
-  W.d2m1 = T(-0.5) * sb * omc;
-  W.d2m2 = T(0.25) * omc * omc;
-  W.d11 = T(0.5) * opc * (T(2) * cb - T(1));
-  W.d10 = -r32 * sb * cb;
-  W.d1m1 = T(0.5) * omc * (T(2) * cb + T(1));
-  W.d00 = T(0.5) * (T(3) * cb * cb - T(1));
+  // spin-2 Wigner small-d matrix d(beta) in the blocks of d_apply
+  W.d = d_blocks(cb, sb);
 }
 
 // x <- exp(-i th g0 n) R P x for one 5-vector x (a or b).
@@ -309,15 +351,6 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
 // 20000 steps of the 1D two-soliton run, against 9e-7 with one rounding).
 template <typename T>
 QLG_HD void w_apply(cx<T> (&x)[5], const WCoef<T>& W) {
-  // full d matrix D[row m'][col m], rows/cols ordered m = 2..-2, from
-  // d_{m'm} = (-1)^{m-m'} d_{mm'} = d_{-m,-m'}
-  const T D[5][5] = {
-      {W.d22, W.d21, W.d20, W.d2m1, W.d2m2},
-      {-W.d21, W.d11, W.d10, W.d1m1, W.d2m1},
-      {W.d20, -W.d10, W.d00, W.d10, W.d20},
-      {-W.d2m1, W.d1m1, -W.d10, W.d11, W.d21},
-      {W.d2m2, -W.d2m1, W.d20, -W.d21, W.d22},
-  };
   const cx<T> uc = conj(W.u), u2c = conj(W.u2);
   // singlet correction sv = cs (v^H x) v, conj(v_m) = (-1)^m psi_{-m}, v_m = (-1)^m conj(psi_{-m})
   cx<T> s = W.p[4] * x[0];
@@ -341,22 +374,12 @@ QLG_HD void w_apply(cx<T> (&x)[5], const WCoef<T>& W) {
   w[4] = (x[4] + sv[4]) * u2c;
   // z = (Lambda' - I) d^T w
   cx<T> z[5];
+  d_apply<T, true>(W.d, w, z);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    cx<T> acc = D[0][k] * w[0];
-#pragma unroll
-    for (int m = 1; m < 5; ++m) acc = rfma(D[m][k], w[m], acc);
-    z[k] = W.dl[k] * acc;
-  }
+  for (int k = 0; k < 5; ++k) z[k] = W.dl[k] * z[k];
   // t = d z; x += sv + Phi t
   cx<T> t5[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    cx<T> acc = D[m][0] * z[0];
-#pragma unroll
-    for (int k = 1; k < 5; ++k) acc = rfma(D[m][k], z[k], acc);
-    t5[m] = acc;
-  }
+  d_apply<T, false>(W.d, z, t5);
   x[0] = x[0] + cfma(t5[0], u2c, sv[0]);
   x[1] = x[1] + cfma(t5[1], uc, sv[1]);
   x[2] = x[2] + (t5[2] + sv[2]);

@@ -45,29 +45,15 @@ struct UFrame {
   double sh_phi;       // sin(phi/2)
   cx<double> ekn;      // e^{-i kappa n}, kappa = theta g2 / 5
   double ca, sa, cb, sb;
-  // d^2(beta) entries d_{m'm} for m' >= |m|; the rest by d_{m'm} = (-1)^{m-m'} d_{mm'} = d_{-m,-m'}
-  double d22, d21, d20, d2m1, d2m2, d11, d10, d1m1, d00;
+  DBlocks<double> d;   // d^2(beta) in the blocks of d_apply (qlg_math.hpp)
 };
-
-// Full d^2(beta) matrix [m'][m] (rows/columns m = 2..-2) from the nine stored entries,
-// built where it is used so that it need not stay live in registers.
-struct DMat {
-  double m[5][5];
-};
-QLG_HD DMat dmat(const UFrame& f) {
-  return DMat{{{f.d22, f.d21, f.d20, f.d2m1, f.d2m2},
-               {-f.d21, f.d11, f.d10, f.d1m1, f.d2m1},
-               {f.d20, -f.d10, f.d00, f.d10, f.d20},
-               {-f.d2m1, f.d1m1, -f.d10, f.d11, f.d21},
-               {f.d2m2, -f.d2m1, f.d20, -f.d21, f.d22}}};
-}
 
 // ext: theta (V + mu) of a psi-independent term (V(x) + mu) psi_m in the equation of
 // motion; it joins the density phase phi0 and, not depending on psi, adds nothing
 // to the derivatives with respect to n, F or the couplings.
 QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double theta, double g0,
                     double g1, double g2, UFrame& f, double ext = 0.0) {
-  const double r6 = Consts::r6, r32 = Consts::r32, r38 = Consts::r38;
+  const double r6 = Consts::r6;
   double q[5];
   for (int m = 0; m < 5; ++m) {
     f.p[m] = a[m] + b[m];
@@ -112,51 +98,27 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
   f.ekn = cx<double>{ch, -sh} * cx<double>{ch, -sh};   // e^{-i kappa n}
   // frame
   f.ca = 1.0; f.sa = 0.0; f.cb = 1.0; f.sb = 0.0;
-  double opc = 2.0, omc = 0.0;
   if (Fp2 > tiny2) { f.ca = f.Fx * iP; f.sa = f.Fy * iP; }
-  if (Fn2 > tiny2) {
-    f.cb = f.Fz * iF;
+  if (Fn2 > tiny2) {   // F_perp = 0: beta = 0 or pi exactly (as in the forward)
+    f.cb = Fp2 > tiny2 ? f.Fz * iF : (f.Fz >= 0 ? 1.0 : -1.0);
     f.sb = f.Fperp * iF;
-    // |F| (1 +- cos beta) without cancellation: the larger of |F| +- F_z directly, the other from it
-    const double big = f.Fn + fabs(f.Fz), other = Fp2 * rcp_t(big);
-    opc = (f.Fz >= 0 ? big : other) * iF;
-    omc = (f.Fz >= 0 ? other : big) * iF;
   }
   f.u = cx<double>{f.ca, f.sa};
-  const double cb = f.cb, sb = f.sb;
-  f.d22 = 0.25 * opc * opc;
-  f.d21 = -0.5 * sb * opc;
-  f.d20 = r38 * sb * sb;
-  f.d2m1 = -0.5 * sb * omc;
-  f.d2m2 = 0.25 * omc * omc;
-  f.d11 = 0.5 * opc * (2 * cb - 1);
-  f.d10 = -r32 * sb * cb;
-  f.d1m1 = 0.5 * omc * (2 * cb + 1);
-  f.d00 = 0.5 * (3 * cb * cb - 1);
+  f.d = d_blocks(f.cb, f.sb);
 }
 
 // Q^H x = d^T Phi^* x (Phi^* multiplies component m by u^m)
 QLG_HD void to_frame(const UFrame& f, const cx<double> (&x)[5], cx<double> (&out)[5]) {
   const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
   const cx<double> w[5] = {x[0] * u2, x[1] * u, x[2], x[3] * uc, x[4] * u2c};
-  const DMat D = dmat(f);
-  for (int k = 0; k < 5; ++k) {
-    cx<double> acc = D.m[0][k] * w[0];
-    for (int m = 1; m < 5; ++m) acc = rfma(D.m[m][k], w[m], acc);
-    out[k] = acc;
-  }
+  d_apply<double, true>(f.d, w, out);
 }
 
 // Q z = Phi d z
 QLG_HD void from_frame(const UFrame& f, const cx<double> (&z)[5], cx<double> (&out)[5]) {
   const cx<double> u = f.u, u2 = u * u, uc = conj(u), u2c = conj(u2);
   cx<double> t[5];
-  const DMat D = dmat(f);
-  for (int m = 0; m < 5; ++m) {
-    cx<double> acc = D.m[m][0] * z[0];
-    for (int k = 1; k < 5; ++k) acc = rfma(D.m[m][k], z[k], acc);
-    t[m] = acc;
-  }
+  d_apply<double, false>(f.d, z, t);
   out[0] = t[0] * u2c;
   out[1] = t[1] * uc;
   out[2] = t[2];

@@ -287,6 +287,19 @@ def adjoint_vortex_pair_2d_512(n: int = 512, sep: float = 128.0, eps: float = 0.
                     nsteps, {"sep": sep, "seed": seed, "checkpoint_every": checkpoint_every})
 
 
+def adjoint_spin_texture_2d_512(n: int = 512, sep: float = 128.0, eps: float = 0.1, seed: int = 2019,
+                                noise_seed: int = 78, noise: float = 0.05, nsteps: int = 2000,
+                                checkpoint_every: int = 64) -> Workload:
+    """The 512^2 adjoint workload's vortex pair plus a seeded complex Gaussian spinor of amplitude
+    `noise` in every component, so that F != 0 at every site and the spin factor of the
+    self-interaction and its derivative act everywhere (in the vortex pair m = +-1 are empty and
+    F = 0 for the whole run)."""
+    w = adjoint_vortex_pair_2d_512(n, sep, eps, seed, nsteps, checkpoint_every)
+    psi = w.psi[0] + random_field((n, n), noise_seed, noise)
+    return Workload("2d_adjoint_spin_texture_%dx%d" % (n, n), 2, [n], [n], [psi], w.g, eps, nsteps,
+                    dict(w.meta, noise=noise, noise_seed=noise_seed))
+
+
 def adjoint_vortex_pair_2d_64(n: int = 64, sep: float = 16.0, eps: float = 0.4, seed: int = 2019) -> np.ndarray:
     """The vortex-pair construction on the 64^2 lattice of the adjoint's finite-difference and
     reference-gradient checks: separation 16 sites and eps = 0.4, so the cores fit the box."""

@@ -50,12 +50,19 @@ def test_traffic_table_is_consistent():
     assert math.isclose(t["fetch_scale"], 2.0, rel_tol=1e-3) and t["write_scale"] == 1.0
     sites = {"1d_two_soliton_scattering": 16384, "2d_vortex_pair": 2048 ** 2, "3d_vortex_lines": 256 ** 3,
              "3d_vortex_lines_512": 512 ** 3}
-    for workload, plans in t["kib"].items():
+    if t["kib"]:
+        assert t["sources_sha256_16"] == bench.kernel_sources_sha()   # measured on these sources
+    for entry, plans in t["kib"].items():
+        workload, storage, split = entry.split("/")
+        assert storage in ("c64", "c128") and split in ("interleaved", "plain")
         ndim = bench.WORKLOADS[workload][0]
+        half = bench.BYTES_PER_SITE_PASS[storage] // 2
         for key, (fetch, write) in plans.items():
             assert fetch > 0 and write > 0
-            # a launch writes at least the state it produces: 80 B per site per pass (KiB here)
-            assert write >= 0.99 * 80 * sites[workload] * bench.PASSES_PER_STEP[ndim] / 1024, (workload, key)
+            # a launch writes at least the state it produces: 10 amplitudes per site per pass (KiB here)
+            assert write >= 0.99 * half * sites[workload] * bench.PASSES_PER_STEP[ndim] / 1024, (entry, key)
+            # and reads at least the state it consumes
+            assert fetch * t["fetch_scale"] >= 0.99 * half * sites[workload] * bench.PASSES_PER_STEP[ndim] / 1024
 
 
 def test_oracle_baseline_record():
