@@ -34,9 +34,11 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic work per site-update, counted from the per-site formulas.
 # Flops count add/sub/mul as 1 and fma as 2 in the per-site formulas of
-# qlg_math.hpp; the three sincos, two square roots and five divisions of each
-# self-interaction are not counted.
-FLOPS_U = 894          # one application of U (coefficients 190 + 2 x 352 per 5-vector)
+# qlg_math.hpp; the three sincos, two reciprocal square roots and two
+# reciprocals of each self-interaction are not counted.  One U: coefficients 178
+# (psi, n, F, the phases and the rotation's blocks), then 288 per 5-vector a and b
+# (singlet 84, frame phases 24, d^T 58, diagonal 30, d 58, recombination 34).
+FLOPS_U = 754          # one application of U (coefficients 178 + 2 x 288 per 5-vector)
 FLOPS_IPRIME = 85      # one I' (two collides 2 x 40 + its share of the exact 1/256 per step, 5)
 FLOPS_PER_SITE_STEP = {d: 4 * d * (FLOPS_U + FLOPS_IPRIME) for d in (1, 2, 3)}
 # plain split: one U (theta = eps^2) and the 4 d I' of a step
@@ -58,7 +60,15 @@ PREROLL_S = 0.2        # untimed steps right before each clock start, at least t
 # WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": None, "fetch_scale": 2.0, "write_scale": 1.0, "kib": {}}
+TRAFFIC = {"sources_sha256_16": "7509e19100fe148e", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
+           "kib": {
+               # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
+               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365985.0, 655360.0)},
+               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232314.0, 328667.0)},
+               "2d_vortex_pair/c64/plain": {"k_step2d/rows38": (229347.0, 330788.0)},
+               # 3D 256^3 vortex lines: one step = z pass + y-x pass (sums of the two)
+               "3d_vortex_lines/c64/interleaved": {"k_step3d/rows32": (819386.0 + 1053540.0,
+                                                                       1310720.0 + 1317050.0)}}}
 
 
 def parse():
