@@ -62,6 +62,8 @@ KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_am
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
 TRAFFIC = {"sources_sha256_16": "7509e19100fe148e", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
            "kib": {
+               # 1D two-soliton lattice, L = 16384: the two-lane kernel at 2 steps per pass
+               "1d_two_soliton_scattering/c64/interleaved": {"k_step1d_lanes/S2": (764.0, 1280.0)},
                # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
                "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365985.0, 655360.0)},
                "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232314.0, 328667.0)},
