@@ -21,13 +21,26 @@ namespace {
 
 struct Site {
   InstDesc d;
+  int c;            // the 256-site chunk this workgroup owns
   int s, x, y, z;
   bool ok;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its own L2.
+// Consecutive chunks (a row and the rows next to it, whose cotangents and states the kinetic
+// pull-back and the chain's I' read again) are given to one XCD, so that those re-reads hit
+// its L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int chunk_of_block(int b, int nblocks) {
+  const int x = b % kXcds, l = b / kXcds;
+  const int per = nblocks / kXcds, extra = nblocks % kXcds;
+  return x * per + (x < extra ? x : extra) + l;
+}
+
 __device__ __forceinline__ Site site_here(const LaunchGeom& g) {
   Site r;
-  const int c = blockIdx.x;
+  const int c = chunk_of_block(blockIdx.x, gridDim.x);
+  r.c = c;
   r.d = g.inst[g.chunk2inst[c]];
   r.s = (c - r.d.chunk_begin) * kChunk + threadIdx.x;
   r.ok = r.s < r.d.sites;
@@ -261,7 +274,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z,
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lam, r.d, r.s, la, lb);
   }
-  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
+  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)r.c);
 }
 
 // One adjoint substep of the interleaved split, fused: lambda_out = (dU)^H I'^H lambda_in,
@@ -284,7 +297,7 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lout, r.d, r.s, la, lb);
   }
-  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)blockIdx.x);
+  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)r.c);
 }
 
 // acc[0..2] += sum over chunks of part (single block, fixed order).  Unrolling
@@ -383,9 +396,9 @@ __global__ __launch_bounds__(kChunk) void k_energy_grad(const cx<T>* __restrict_
     e *= meas; en *= meas; ef *= meas; es *= meas;
   }
   // four partials in a 6-double slot per chunk: two block sums (e, en, ef) and (es, 0, 0)
-  block_sum3(e, en, ef, part + 6 * (int64_t)blockIdx.x);
+  block_sum3(e, en, ef, part + 6 * (int64_t)r.c);
   __syncthreads();
-  block_sum3(es, 0.0, 0.0, part + 6 * (int64_t)blockIdx.x + 3);
+  block_sum3(es, 0.0, 0.0, part + 6 * (int64_t)r.c + 3);
 }
 
 // Fidelity objective, pass 1: chunk partials of eps^d <target|psi> (re, im).
@@ -408,7 +421,7 @@ __global__ __launch_bounds__(kChunk) void k_fid_overlap(const cx<T>* __restrict_
     re *= meas;
     im *= meas;
   }
-  block_sum3(re, im, 0.0, part + 3 * (int64_t)blockIdx.x);
+  block_sum3(re, im, 0.0, part + 3 * (int64_t)r.c);
 }
 
 // Per-instance sum of the pass-1 partials into ov[inst][3].
@@ -429,7 +442,7 @@ __global__ __launch_bounds__(kChunk) void k_fid_grad(const cx<T>* __restrict__ t
                                                     LaunchGeom g, double meas, const double* __restrict__ ov) {
   const Site r = site_here(g);
   if (!r.ok) return;
-  const int inst = g.chunk2inst[blockIdx.x];
+  const int inst = g.chunk2inst[r.c];
   const cx<double> o{ov[3 * inst], ov[3 * inst + 1]};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
