@@ -60,17 +60,12 @@ PREROLL_S = 0.2        # untimed steps right before each clock start, at least t
 # WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "7509e19100fe148e", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
+TRAFFIC = {"sources_sha256_16": "f746a52d6013cc9c", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
            "kib": {
-               # 1D two-soliton lattice, L = 16384: the two-lane kernel at 2 steps per pass
-               "1d_two_soliton_scattering/c64/interleaved": {"k_step1d_lanes/S2": (764.0, 1280.0)},
-               # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
-               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365985.0, 655360.0)},
-               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232314.0, 328667.0)},
-               "2d_vortex_pair/c64/plain": {"k_step2d/rows38": (229347.0, 330788.0)},
-               # 3D 256^3 vortex lines: one step = z pass + y-x pass (sums of the two)
-               "3d_vortex_lines/c64/interleaved": {"k_step3d/rows32": (819386.0 + 1053540.0,
-                                                                       1310720.0 + 1317050.0)}}}
+               # 2D 2048^2 vortex pair, complex128: bands of 38 rows, the y half over two launches
+               # (sums of the two)
+               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows38/ysplit": (424210.0 + 413130.0,
+                                                                              655360.0 + 657360.0)}}}
 
 
 def parse():
@@ -85,7 +80,7 @@ def parse():
     ap.add_argument("--plan", default=None,
                     help="fix the launch plan instead of autotuning it (for profiler runs, where the "
                          "tracer's per-launch overhead would steer the autotuner): 1D 'S:qubit_split', "
-                         "2D and 3D the band height in rows")
+                         "2D and 3D the band height in rows, or 'rows:1' for the y half over two launches")
     ap.add_argument("--split", choices=["interleaved", "plain"], default="interleaved",
                     help="operator splitting of the step (the benchmark uses the interleaved one)")
     ap.add_argument("--secondary", choices=["c64", "c128", "none"], default="c64",
@@ -175,7 +170,8 @@ def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="i
             S, qs = (int(v) for v in plan.split(":"))
             lat.set_tuning(steps_per_pass=S, qubit_split=qs)
         else:
-            lat.set_tuning(tile_rows=int(plan))
+            rows, _, ys = plan.partition(":")
+            lat.set_tuning(tile_rows=int(rows), qubit_split=int(ys or 0))
     else:
         lat.autotune()
     lat.set_tuning(use_graph=True)
@@ -412,7 +408,9 @@ def main():
     flops_site = (FLOPS_PER_SITE_STEP if args.split == "interleaved" else FLOPS_PER_SITE_STEP_PLAIN)[ndim]
     flops_launch = flops_site * sites_per_launch
     achieved_tflops = flops_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
-    bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L * PASSES_PER_STEP[ndim]
+    # 2D and 3D plans with qubit_split 1 run the y (and z) half over two launches: twice the passes
+    ysplit = ndim >= 2 and m["tuning"]["qubit_split"] == 1
+    bytes_launch = BYTES_PER_SITE_PASS[args.dtype] * L * PASSES_PER_STEP[ndim] * (2 if ysplit else 1)
     hbm_gbs = bytes_launch / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     # the roofline that bounds this launch: flops per algorithmic byte against the ridge point
     intensity = flops_launch / bytes_launch
@@ -421,11 +419,11 @@ def main():
         kernel = ("k_step1d", "k_step1d_pair", "k_step1d_lanes")[m["tuning"]["qubit_split"]]
         key = "%s/S%d" % (kernel, S)
     elif ndim == 2:
-        kernel = "k_step2d"
-        key = "%s/rows%d" % (kernel, m["tuning"]["tile_rows"])
+        kernel = "k_step2d (the two halves of the y half)" if ysplit else "k_step2d"
+        key = "k_step2d/rows%d%s" % (m["tuning"]["tile_rows"], "/ysplit" if ysplit else "")
     else:   # a launch here is one step: the z pass and the y-x pass of the same kernel
-        kernel = "k_step2d (z pass + y-x pass)"
-        key = "k_step3d/rows%d" % m["tuning"]["tile_rows"]
+        kernel = "k_step2d (z pass + y-x pass%s)" % (", each over two launches" if ysplit else "")
+        key = "k_step3d/rows%d%s" % (m["tuning"]["tile_rows"], "/ysplit" if ysplit else "")
     traffic = None
     measured = TRAFFIC["kib"].get("%s/%s/%s" % (args.workload, args.dtype, args.split), {})
     if key in measured and kernel_sources_sha() == TRAFFIC["sources_sha256_16"]:

@@ -266,11 +266,20 @@ double angle_scale(const qlg_ctx* c) {   // interleaved theta = eps^2 / (4 d)
   return c->p.eps * c->p.eps / (4.0 * c->p.ndim);
 }
 
+// Whether one step leaves the state in the copy it started from: a 3D step (its z pass
+// from `in` to `out`, its y-x pass back), and a 2D step whose y half is split over two
+// launches (the same way).  Otherwise a pass writes the other copy.
+bool step_returns(const qlg_ctx* c) {
+  return c->p.ndim == 3 || (c->p.ndim == 2 && c->tuning.qubit_split == 1);
+}
+
 // One pass of the fused step from `in` to `out` (1D: `steps` steps; 2D: one step).
-// 3D: one step as two passes, the z pass from `in` to `out` and the y-x pass from `out`
-// back to `in`, so the state stays in `in`; with keep_state (timing runs) both passes
-// read `in` and write `out`, leaving `in` unchanged.  ev0 / ev1 are stamped at the
-// start of the first and the end of the last kernel.
+// 3D, and 2D with the y half split (qubit_split 1): one step as several launches that
+// alternate between `in` and `out`, ending in `in`: 3D the z pass (one launch, or two with
+// the split) and the y-x pass (one or two), 2D the two halves of the y half, the second
+// with the x half; with keep_state (timing runs) every launch reads `in` and writes `out`,
+// leaving `in` unchanged.  ev0 / ev1 are stamped at the start of the first and the end of
+// the last kernel.
 hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, void* in, void* out, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr, bool keep_state = false) {
   const double th = angle_scale(c);
@@ -281,20 +290,48 @@ hipError_t launch_pass(qlg_ctx* c, int steps, bool overlap, void* in, void* out,
   qlg::ExtPot ext = c->ext;
   ext.theta = th;
   const int rows = c->tuning.tile_rows;
+  const int dt = c->p.dtype;
   if (c->p.ndim == 1)
-    return qlg::launch_step1d(c->p.dtype, steps, c->tuning.qubit_split, plain, overlap, in, out, g, tg0, tg1,
+    return qlg::launch_step1d(dt, steps, c->tuning.qubit_split, plain, overlap, in, out, g, tg0, tg1, tg25, ext,
+                              ov, c->stream, ev0, ev1);
+  const double ff = c->p.ndim == 2 ? 8.0 : 12.0;
+  // A 3D step over four launches overwrites `in` (the state before the step) with its second
+  // launch, so a step that records the overlap with that state runs as two launches.  Both
+  // forms compute the same numbers: the split stores the state between its launches at its
+  // true scale, an exact power-of-two rescaling of the one-launch form's intermediate.
+  const bool ysplit = c->tuning.qubit_split == 1 && !(c->p.ndim == 3 && overlap);
+  if (c->p.ndim == 2 && !ysplit)
+    return qlg::launch_step2d(dt, plain, overlap, rows, false, true, qlg::kWhole, ff, in, out, in, g, tg0, tg1,
                               tg25, ext, ov, c->stream, ev0, ev1);
-  if (c->p.ndim == 2)
-    return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, true, 8.0, in, out, in, g, tg0, tg1, tg25,
-                              ext, ov, c->stream, ev0, ev1);
-  hipError_t e = qlg::launch_step2d(c->p.dtype, plain, false, rows, true, true, 12.0, in, out, in, g, tg0, tg1,
-                                    tg25, ext, ov, c->stream, ev0, nullptr);
-  if (e != hipSuccess) return e;
-  if (keep_state)
-    return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, false, 12.0, in, out, in, g, tg0, tg1,
-                              tg25, ext, ov, c->stream, nullptr, ev1);
-  return qlg::launch_step2d(c->p.dtype, plain, overlap, rows, false, false, 12.0, out, in, in, g, tg0, tg1, tg25,
-                            ext, ov, c->stream, nullptr, ev1);
+  // the launches of one step: (z pass, part, applies the plain U, records the overlap)
+  struct L { bool zpass; int part; bool plain_u; bool last; };
+  L seq[4];
+  int n = 0;
+  if (c->p.ndim == 3) {
+    if (ysplit) {
+      seq[n++] = {true, qlg::kYFirst, true, false};
+      seq[n++] = {true, qlg::kYSecond, false, false};
+    } else {
+      seq[n++] = {true, qlg::kWhole, true, false};
+    }
+  }
+  if (ysplit) {
+    seq[n++] = {false, qlg::kYFirst, c->p.ndim == 2, false};
+    seq[n++] = {false, qlg::kYSecond, false, true};
+  } else {
+    seq[n++] = {false, qlg::kWhole, false, true};
+  }
+  void* src = in;
+  void* dst = out;
+  for (int k = 0; k < n; ++k) {
+    const L& l = seq[k];
+    hipError_t e = qlg::launch_step2d(dt, plain, l.last && overlap, rows, l.zpass, l.plain_u, l.part, ff, src,
+                                      dst, in, g, tg0, tg1, tg25, ext, ov, c->stream, k == 0 ? ev0 : nullptr,
+                                      k == n - 1 ? ev1 : nullptr);
+    if (e != hipSuccess) return e;
+    if (!keep_state) std::swap(src, dst);
+  }
+  return hipSuccess;
 }
 
 // Enqueue nsteps as passes of steps_per_pass (1D) or single steps (2D), ping-ponging
@@ -313,7 +350,7 @@ qlg_status enqueue_steps(qlg_ctx* c, int64_t nsteps, int* cur, bool timed) {
     }
     hipError_t e = launch_pass(c, s, last, c->copy(*cur), c->copy(1 - *cur), e0, e1);
     if (e != hipSuccess) return hip_check(c, e, "step kernel launch");
-    if (c->p.ndim < 3) *cur = 1 - *cur;   // a 3D step returns to its own copy
+    if (!step_returns(c)) *cur = 1 - *cur;
     left -= s;
     ++launch;
   }
@@ -343,7 +380,7 @@ const char* tuning_error(const qlg_ctx* c, const qlg_tuning& n) {
     if (n.qubit_split == 2 && n.steps_per_pass > kMaxStepsLanes) return "steps_per_pass must be 1..3 with qubit_split 2";
   } else {
     if (n.steps_per_pass != 1) return "steps_per_pass must be 1 in 2D and 3D";
-    if (n.qubit_split != 0) return "qubit_split must be 0 in 2D and 3D";
+    if (n.qubit_split != 0 && n.qubit_split != 1) return "qubit_split must be 0 or 1 in 2D and 3D";
     if (n.tile_rows < kMinTileRows || n.tile_rows > kMaxTileRows) return "tile_rows must be 8..256";
   }
   return nullptr;
@@ -697,7 +734,7 @@ qlg_status qlg_step(qlg_ctx* c, int64_t nsteps) {
     }
     s = hip_check(c, hipGraphLaunch(it->second, c->stream), "graph launch");
     if (s) return s;
-    if (launches % 2 && c->p.ndim < 3) c->cur = 1 - c->cur;
+    if (launches % 2 && !step_returns(c)) c->cur = 1 - c->cur;
   } else {
     int cur = c->cur;
     s = enqueue_steps(c, nsteps, &cur, false);
@@ -770,7 +807,8 @@ qlg_status qlg_autotune(qlg_ctx* c) {
   if (s) return s;
   // Candidates in order of preference: among plans within 2 % of the fastest the first one
   // wins, so that timing noise does not flip the plan (fewer launches first, then the
-  // one-lane-per-site kernel before the split ones; taller 2D bands first).
+  // one-lane-per-site kernel before the split ones; 2D and 3D: the whole y half in one
+  // launch before the split one, taller bands first).
   std::vector<qlg_tuning> cand;
   if (c->p.ndim == 1) {
     for (int S = kMaxSteps1D; S >= 1; --S)
@@ -796,7 +834,8 @@ qlg_status qlg_autotune(qlg_ctx* c) {
       if (ntiles(r) <= k * nsimd && std::find(rows.begin(), rows.end(), r) == rows.end()) rows.push_back(r);
     }
     std::sort(rows.begin(), rows.end(), [](int x, int y) { return x > y; });
-    for (int r : rows) cand.push_back(qlg_tuning{1, r, c->tuning.use_graph, 0});
+    for (int split = 0; split <= 1; ++split)
+      for (int r : rows) cand.push_back(qlg_tuning{1, r, c->tuning.use_graph, split});
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(c, QLG_ERR_DEVICE, "event create");

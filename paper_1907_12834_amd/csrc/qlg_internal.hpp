@@ -61,12 +61,17 @@ constexpr int kLaneTileSites = 32;
 hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overlap, const void* in, void* out,
                          const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
                          double* ovpart, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Part of a step that one launch of the 2D kernel runs: all four y (or z) stages, then
+// the x half unless it is a z pass (kWhole); or the y half over two launches, kYFirst (the
+// two stages that move qubit b) and kYSecond (the two that move qubit a, then the x half),
+// each with a two-stage row pipeline: half the LDS per wavefront.
+enum StepPart : int { kWhole = 0, kYFirst = 1, kYSecond = 2 };
 // 2D step, or one pass of a 3D step: zpass = the four z substeps only (rows along z,
 // 64-column tiles, the 3D z-pass tile table); otherwise the y and x substeps of each
 // z plane.  full_factor: theta of the plain split's single U over the interleaved theta
 // (4 ndim); plain_u: this pass applies that U (2D, 3D z pass).  prev (may equal out):
 // the state before the step, for the overlap partials.
-hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u, int part,
                          double full_factor, const void* in, void* out, const void* prev, const LaunchGeom& g,
                          double tg0, double tg1, double tg25, const ExtPot& ext, double* ovpart,
                          hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -101,6 +101,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Row access of the 2D kernel through buffer resources.  A resource covers one row of one
+// amplitude plane (base and record count are wavefront-uniform, in scalar registers); a lane
+// passes its byte offset in the row.  The hardware drops a store whose offset is at or beyond
+// the record count and returns 0 for such a load, so a lane or a row with nothing to write
+// still issues its store, without a branch: every path through the row loop then issues the
+// same memory instructions, and the compiler's wait for the row loaded ahead does not also
+// wait for the stores of the row before it.
+constexpr int kBufWord3 = 0x00020000;   // resource word 3 on gfx9: 32-bit data format, no swizzle
+constexpr uint32_t kOffNone = 0x80000000u;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const cx<T>* row, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(row), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ cx<float> buf_load(const cx<float>*, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ cx<double> buf_load(const cx<double>*, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(cx<float> v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(cx<double> v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, 0);
+}
+
 // Kernel arguments shared by the fused step kernels.
 template <typename T>
 struct StepArgs {
@@ -542,20 +572,32 @@ __device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>*
   }
 }
 
-// LDS words per wavefront for the y pipeline: 4 stages x (cn[5], mq[5]) x 64 lanes.
-constexpr int kStageSlots = 4 * 10;
+// LDS words per wavefront and y stage of the pipeline: (cn[5], mq[5]) x 64 lanes.
+constexpr int kSlotsPerStage = 10;
 constexpr int k2DWaves = 2;   // wavefronts per workgroup of the 2D kernel
 
-template <typename T, bool kExt>
-__global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
+// Parts of a step (StepPart): a launch of kYFirst or kYSecond keeps a two-stage pipeline,
+// half the LDS of the four-stage one, which lets two wavefronts share a SIMD in complex128.
+// The state between the two launches is the true state (scale 1).
+template <int kPart>
+constexpr int stages_of() { return kPart == kWhole ? 4 : 2; }
+
+// With the y half split, a launch's pipeline leaves LDS for two wavefronts per SIMD: the
+// register budget is set to match (256 per lane).
+template <typename T, bool kExt, int kPart>
+__global__ __launch_bounds__(64 * k2DWaves) __attribute__((amdgpu_waves_per_eu(kPart == kWhole ? 1 : 2)))
+void k_step2d(StepArgs<T> A) {
+  constexpr int kStages = stages_of<kPart>();
+  constexpr int kLag = 2 * kStages;          // rows between a row's load and its store
   // Per-lane pipeline buffers live in LDS; every lane reads back only the
   // slots it wrote itself, so no barrier is needed anywhere in the kernel.
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int wv = threadIdx.x >> 6;
+  // the tile and everything derived from it are wavefront-uniform (scalar registers)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * k2DWaves + wv;
   if (w >= A.ntiles) return;
   const int lane = threadIdx.x & (kLanes - 1);
-  cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStageSlots * kLanes) + lane;
+  cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStages * kSlotsPerStage * kLanes) + lane;
   const InstDesc d = A.inst[A.tile2inst[w]];
   // Tile -> (x tile, band, plane).  The rows of a band stream along y (2D, and the y-x
   // pass of a 3D step: one z plane per band) or along z (the z pass of a 3D step: one y
@@ -576,121 +618,136 @@ __global__ __launch_bounds__(64 * k2DWaves) void k_step2d(StepArgs<T> A) {
   const bool xvalid = lane >= halo && lane < kLanes - halo && x < nx;
   const bool plain = A.plain != 0;
   const bool plain_u = A.plain_u != 0;
+  // byte offsets of this lane's site in a row: the load's (periodic column) and the
+  // store's (beyond any record count for a halo lane or a column past the lattice)
+  const uint32_t row_bytes = (uint32_t)nx * (uint32_t)sizeof(cx<T>);
+  const uint32_t off_ld = (uint32_t)xw * (uint32_t)sizeof(cx<T>);
+  const uint32_t off_st = xvalid ? (uint32_t)x * (uint32_t)sizeof(cx<T>) : kOffNone;
 #pragma unroll
-  for (int j = 0; j < kStageSlots; ++j) my[j * kLanes] = cx<T>{T(0), T(0)};
+  for (int j = 0; j < kStages * kSlotsPerStage; ++j) my[j * kLanes] = cx<T>{T(0), T(0)};
 
   double ore = 0.0, oim = 0.0;
-  const int nrows = A.tile_rows + 8;
+  const int nrows = A.tile_rows + kLag;
   // Rows are loaded one iteration ahead, so that a row's HBM latency overlaps the
-  // arithmetic of the row before it.  (complex128 holds the extra row in accumulation
-  // registers: its occupancy, one wave per SIMD, is set by the pipeline's LDS.)
-  constexpr bool kAhead = true;
-  // lattice row of the next load (row y0 - 4 + r of the band, periodic), advanced by one
-  // per load instead of a division per row
-  int yl = (int)wrap64(y0 - 4, nrow);
-  // with kExt, e is the (V + mu) angle of the row's site in this lane
-  auto load_row = [&](cx<T>(&a)[5], cx<T>(&b)[5], T& e) {
-    const int64_t s = pbase + (int64_t)yl * rstride + xw;
-    yl = yl + 1 == nrow ? 0 : yl + 1;
-    const cx<T>* src = A.in + d.off + s;
+  // arithmetic of the row before it.
+  // lattice row of the next load (row y0 - kStages + r of the band, periodic), advanced by
+  // one per load instead of a division per row
+  int yl = (int)wrap64(y0 - kStages, nrow);
+  // with kExt, e is the (V + mu) angle of the row's site in this lane; a load with
+  // live == false (after the band's last row) reads nothing and returns zeros
+  auto load_row = [&](cx<T>(&a)[5], cx<T>(&b)[5], T& e, bool live) {
+    const int64_t s = d.off + pbase + (int64_t)yl * rstride;
+    const uint32_t nrec = live ? row_bytes : 0u;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      a[m] = src[m * d.stride];
-      b[m] = src[(5 + m) * d.stride];
+      a[m] = buf_load(A.in, row_rsrc(A.in + s + m * d.stride, nrec), off_ld);
+      b[m] = buf_load(A.in, row_rsrc(A.in + s + (5 + m) * d.stride, nrec), off_ld);
     }
-    if constexpr (kExt) e = ext_angle(A, d, s);
+    if constexpr (kExt) e = ext_angle(A, d, s - d.off + xw);
+    yl = yl + 1 == nrow ? 0 : yl + 1;
   };
-  // (V + mu) angles of the rows at the four y stages and of the row leaving for the
-  // x half: stage j works on the row loaded j iterations ago, the x half on the row
-  // loaded four iterations ago
-  T e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0), e4 = T(0), ne = T(0);
+  // Stores of lattice row yo; a row outside the lattice (or a row still in the pipeline,
+  // live == false) has record count 0, so its stores write nothing.
+  auto store_row = [&](const cx<T>(&a)[5], const cx<T>(&b)[5], int yo, bool live) {
+    const bool on = live && yo >= 0 && yo < nrow;
+    const int64_t s = d.off + pbase + (int64_t)(on ? yo : 0) * rstride;
+    const uint32_t nrec = on ? row_bytes : 0u;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      buf_store(a[m], row_rsrc(A.out + s + m * d.stride, nrec), off_st);
+      buf_store(b[m], row_rsrc(A.out + s + (5 + m) * d.stride, nrec), off_st);
+    }
+  };
+  // (V + mu) angles: stage i of this launch works on the row loaded i iterations ago,
+  // the x half on the row loaded kStages iterations ago
+  T er[kStages + 1];
+#pragma unroll
+  for (int i = 0; i <= kStages; ++i) er[i] = T(0);
+  T ne = T(0);
   cx<T> na[5], nb[5];
-  if (kAhead) load_row(na, nb, ne);
+  load_row(na, nb, ne, true);
+  {
+    // the stores of a row that writes nothing, so that the loop is entered, as it is
+    // re-entered, with one row of stores issued after the row loaded ahead
+    const cx<T> z[5] = {};
+    store_row(z, z, 0, false);
+  }
 #pragma unroll 1
   for (int r = 0; r < nrows; ++r) {
     cx<T> a[5], b[5];
-    T en = T(0);
-    if (kAhead) {
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        a[m] = na[m];
-        b[m] = nb[m];
-      }
-      en = ne;
-      if (r + 1 < nrows) load_row(na, nb, ne);
-    } else {
-      load_row(a, b, en);
+    for (int m = 0; m < 5; ++m) {
+      a[m] = na[m];
+      b[m] = nb[m];
     }
+    const T en = ne;
+    __builtin_amdgcn_sched_barrier(0);
+    load_row(na, nb, ne, r + 1 < nrows);
     if constexpr (kExt) {
-      e4 = e3;
-      e3 = e2;
-      e2 = e1;
-      e1 = e0;
-      e0 = en;
-    }
-    // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y; slot k of this lane's LDS
-    // holds stage k's pending rows.  The plain split applies its single U at stage 0.
-    // Stage k leaves its output times 4 (the factor 1/4 of its I' is deferred): all
-    // rows pass the same stages, so pending and streaming rows carry the same
-    // scale; one exact multiplication by 1/256 ends each half.
-#pragma unroll 1
-    for (int j = 0; j < 2; ++j) {
-      if (!plain || (j == 0 && plain_u))
-        potential<T, kExt>(a, b, plain ? A.ang_full : substep_angles(A.ang, j), j == 0 ? e0 : e1);
-      y_stage_lds<T, 1>(a, b, my + j * 10 * kLanes);
-    }
-#pragma unroll 1
-    for (int j = 2; j < 4; ++j) {
-      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), j == 2 ? e2 : e3);
-      y_stage_lds<T, 0>(a, b, my + j * 10 * kLanes);
-    }
-    if (r < 8) continue;
-    // x half for rows that have left the y pipeline complete (r >= 8)
-    scale_by(a, b, T(1.0 / 256.0));
-    const int yo = y0 - 8 + r;           // row leaving the pipeline
-    if (zp) {                            // 3D z pass: the rows are complete
-      if (xvalid && yo < nrow) {
-        cx<T>* dst = A.out + d.off + pbase + yo * rstride + x;
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          dst[m * d.stride] = a[m];
-          dst[(5 + m) * d.stride] = b[m];
+      for (int i = kStages; i > 0; --i) er[i] = er[i - 1];
+      er[0] = en;
+    }
+    // y half: stages (y,b), (y,b), (y,a), (y,a), each [U] I'_y, all four or two of them in
+    // this launch; slot i of this lane's LDS holds stage i's pending rows.  The plain split
+    // applies its single U at the step's first stage.  Stage i leaves its output times 4
+    // (the factor 1/4 of its I' is deferred): all rows pass the same stages, so pending and
+    // streaming rows carry the same scale, and the U of stage i takes angles for a state
+    // times 4^i; one exact multiplication ends each half.
+    if constexpr (kPart != kYSecond) {
+#pragma unroll 1
+      for (int i = 0; i < 2; ++i) {
+        if (!plain || (i == 0 && plain_u))
+          potential<T, kExt>(a, b, plain ? A.ang_full : substep_angles(A.ang, i), i == 0 ? er[0] : er[1]);
+        y_stage_lds<T, 1>(a, b, my + i * kSlotsPerStage * kLanes);
+      }
+    }
+    if constexpr (kPart != kYFirst) {
+      constexpr int i0 = kPart == kWhole ? 2 : 0;
+#pragma unroll 1
+      for (int i = i0; i < i0 + 2; ++i) {
+        if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, i), i == i0 ? er[i0] : er[i0 + 1]);
+        y_stage_lds<T, 0>(a, b, my + i * kSlotsPerStage * kLanes);
+      }
+    }
+    // The row leaving the pipeline is complete from r = kLag on.  The pipeline fill issues
+    // the same stores, all dropped, so that every path through the loop issues the same
+    // memory instructions in the same order.
+    const int yo = y0 - kLag + r;
+    const bool done = r >= kLag;
+    if (done) {
+      scale_by(a, b, T(kStages == 4 ? 1.0 / 256.0 : 1.0 / 16.0));
+      if (kPart != kYFirst && !zp) {     // x half (not after the b stages, not in a z pass)
+#pragma unroll 1
+        for (int j = 0; j < 2; ++j) {
+          if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), er[kStages]);
+          iprime4_lanes<T, 1>(a, b);
+        }
+#pragma unroll 1
+        for (int j = 2; j < 4; ++j) {
+          if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), er[kStages]);
+          iprime4_lanes<T, 0>(a, b);
+        }
+        scale_by(a, b, T(1.0 / 256.0));
+        if (A.overlap && yo < nrow) {
+          // the state before the step at this site; in a step of several launches it is the
+          // location this lane writes below (and no other lane reads or writes it), so it is
+          // read first.  Halo lanes read zeros and add nothing.
+          const int64_t s = d.off + pbase + (int64_t)yo * rstride;
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            const cx<T> po = buf_load(A.prev, row_rsrc(A.prev + s + m * d.stride, row_bytes), off_st) +
+                             buf_load(A.prev, row_rsrc(A.prev + s + (5 + m) * d.stride, row_bytes), off_st);
+            const cx<T> c = cmulc(a[m] + b[m], po);
+            if (xvalid) {
+              ore += (double)c.re;
+              oim += (double)c.im;
+            }
+          }
         }
       }
-      continue;
     }
-#pragma unroll 1
-    for (int j = 0; j < 2; ++j) {
-      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), e4);
-      iprime4_lanes<T, 1>(a, b);
-    }
-#pragma unroll 1
-    for (int j = 2; j < 4; ++j) {
-      if (!plain) potential<T, kExt>(a, b, substep_angles(A.ang, j), e4);
-      iprime4_lanes<T, 0>(a, b);
-    }
-    scale_by(a, b, T(1.0 / 256.0));
-    if (xvalid && yo < nrow) {
-      const int64_t o = d.off + pbase + yo * rstride + x;
-      cx<T>* dst = A.out + o;
-      if (A.overlap) {
-        // the state before the step at this site; in a 3D step it is the location this lane
-        // writes below (and no other lane reads or writes it), so it is read first
-        const cx<T>* old = A.prev + o;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          const cx<T> po = old[m * d.stride] + old[(5 + m) * d.stride];
-          const cx<T> c = cmulc(a[m] + b[m], po);
-          ore += (double)c.re;
-          oim += (double)c.im;
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        dst[m * d.stride] = a[m];
-        dst[(5 + m) * d.stride] = b[m];
-      }
-    }
+    store_row(a, b, yo, done);
   }
   if (A.overlap) {
     ore = wave_sum(ore);
@@ -993,15 +1050,21 @@ hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overl
   return hipGetLastError();
 }
 
+template <typename T, bool kExt, int kPart>
+static void launch_step2d_k(dim3 grid, dim3 block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                            const StepArgs<T>& args) {
+  const size_t lds = sizeof(cx<T>) * stages_of<kPart>() * kSlotsPerStage * kLanes * k2DWaves;
+  launch_timed(k_step2d<T, kExt, kPart>, grid, block, lds, st, ev0, ev1, args);
+}
+
 template <typename T>
-static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u, int part,
                                   double full_factor, const void* in, void* out, const void* prev,
                                   const LaunchGeom& g, double tg0, double tg1, double tg25, const ExtPot& ext,
                                   double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int ntiles = zpass ? g.ntiles_z : g.ntiles;
   if (ntiles == 0) return hipSuccess;
   const dim3 grid((ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
-  const size_t lds = sizeof(cx<T>) * kStageSlots * kLanes * k2DWaves;
   auto args = step_args<T>(in, out, g, tg0, tg1, tg25, full_factor, ext, ovpart, 1, tile_rows, plain, overlap);
   args.prev = (const cx<T>*)prev;
   args.zpass = zpass ? 1 : 0;
@@ -1010,21 +1073,28 @@ static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool 
     args.tile2inst = g.tile2inst_z;
     args.ntiles = g.ntiles_z;
   }
-  if (ext.on()) launch_timed(k_step2d<T, true>, grid, block, lds, st, ev0, ev1, args);
-  else launch_timed(k_step2d<T, false>, grid, block, lds, st, ev0, ev1, args);
+  if (ext.on()) {
+    if (part == kYFirst) launch_step2d_k<T, true, kYFirst>(grid, block, st, ev0, ev1, args);
+    else if (part == kYSecond) launch_step2d_k<T, true, kYSecond>(grid, block, st, ev0, ev1, args);
+    else launch_step2d_k<T, true, kWhole>(grid, block, st, ev0, ev1, args);
+  } else {
+    if (part == kYFirst) launch_step2d_k<T, false, kYFirst>(grid, block, st, ev0, ev1, args);
+    else if (part == kYSecond) launch_step2d_k<T, false, kYSecond>(grid, block, st, ev0, ev1, args);
+    else launch_step2d_k<T, false, kWhole>(grid, block, st, ev0, ev1, args);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u,
+hipError_t launch_step2d(int dtype, bool plain, bool overlap, int tile_rows, bool zpass, bool plain_u, int part,
                          double full_factor, const void* in, void* out, const void* prev, const LaunchGeom& g,
                          double tg0, double tg1, double tg25, const ExtPot& ext, double* ovpart,
                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (tile_rows < 1) return hipErrorInvalidValue;
+  if (tile_rows < 1 || part < kWhole || part > kYSecond) return hipErrorInvalidValue;
   if (dtype == 0)
-    return launch_step2d_t<float>(plain, overlap, tile_rows, zpass, plain_u, full_factor, in, out, prev, g, tg0,
-                                  tg1, tg25, ext, ovpart, st, ev0, ev1);
-  return launch_step2d_t<double>(plain, overlap, tile_rows, zpass, plain_u, full_factor, in, out, prev, g, tg0,
-                                 tg1, tg25, ext, ovpart, st, ev0, ev1);
+    return launch_step2d_t<float>(plain, overlap, tile_rows, zpass, plain_u, part, full_factor, in, out, prev, g,
+                                  tg0, tg1, tg25, ext, ovpart, st, ev0, ev1);
+  return launch_step2d_t<double>(plain, overlap, tile_rows, zpass, plain_u, part, full_factor, in, out, prev, g,
+                                 tg0, tg1, tg25, ext, ovpart, st, ev0, ev1);
 }
 
 #define QLG_ELEMWISE(NAME, KERNEL, SRC_T, DST_T)                                                    \

@@ -33,15 +33,17 @@ def oracle_qubits3(a, b, nsteps, eps, g, split="interleaved", V=None, mu=0.0):
     return A.numpy(), B.numpy()
 
 
+@pytest.mark.parametrize("ysplit", [0, 1])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("split", ["interleaved", "plain"])
 @pytest.mark.parametrize("shape,rows", [((5, 7, 70), 8), ((9, 3, 130), 16), ((17, 2, 9), 8),
                                         ((3, 20, 64), 16), ((1, 1, 1), 8), ((2, 1, 65), 8)])
-def test_3d_random_qubits(dtype, split, shape, rows):
+def test_3d_random_qubits(dtype, split, shape, rows, ysplit):
+    """Ragged 3D lattices; ysplit 1: the z and the y half each over two launches."""
     g, eps, nsteps = (1.1, -0.6, 0.7), 0.45, 3
     a, b = qi.random_qubits(shape, seed=sum(shape) * 13 + rows, scale=0.4)
     lat = lattice3([shape], g=g, eps=eps, dtype=dtype, split=split)
-    lat.set_tuning(tile_rows=rows)
+    lat.set_tuning(tile_rows=rows, qubit_split=ysplit)
     lat.set_qubits([torch.from_numpy(np.stack([a, b]))])
     lat.step(nsteps)
     got = lat.get_qubits()[0].cpu().numpy()
@@ -50,14 +52,15 @@ def test_3d_random_qubits(dtype, split, shape, rows):
     assert err <= TOL[dtype], err
 
 
-def test_3d_batched_instances_and_observables():
+@pytest.mark.parametrize("ysplit", [0, 1])
+def test_3d_batched_instances_and_observables(ysplit):
     """Three 3D instances of different shape in one context; every state and every observable
     (norms, populations, energy, overlap energy) against the oracle."""
     shapes = [(6, 5, 70), (3, 9, 20), (11, 2, 3)]
     g, eps, nsteps = (1.0, -0.4, 0.6), 0.4, 4
     psis = [qi.random_field(s, seed=70 + i, scale=0.4) for i, s in enumerate(shapes)]
     lat = lattice3(shapes, g=g, eps=eps, dtype="c128")
-    lat.set_tuning(tile_rows=8)
+    lat.set_tuning(tile_rows=8, qubit_split=ysplit)
     lat.set_psi([torch.from_numpy(p) for p in psis])
     lat.step(nsteps - 1)
     prev = [p.cpu().numpy() for p in lat.get_psi()]

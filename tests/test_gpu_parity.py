@@ -191,10 +191,11 @@ def test_two_solitons_L16384_light_cone_samples(dtype):
 # ---------------------------------------------------------------------------
 # Observables
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("ndim,plan", [(1, None), (1, (3, 1)), (1, (2, 2)), (1, (3, 2)), (2, None)])
+@pytest.mark.parametrize("ndim,plan", [(1, None), (1, (3, 1)), (1, (2, 2)), (1, (3, 2)), (2, None), (2, (1, 1))])
 def test_observables_match_oracle(ndim, plan):
     """Observables and the overlap energy of the last step (recorded by the step kernel of the
-    plan: steps per pass, qubit split) against the oracle."""
+    plan: steps per pass, qubit split; in 2D qubit split 1 is the y half over two launches)
+    against the oracle."""
     g, eps, nsteps = (1.0, -0.5, 0.5), 0.2, 9
     shape = (300,) if ndim == 1 else (19, 70)
     a, b = qi.random_qubits(shape, seed=33, scale=0.4)
@@ -275,22 +276,42 @@ def test_bright_soliton_overlap_energy_on_gpu():
 # ---------------------------------------------------------------------------
 # 2D
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ysplit", [0, 1])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("split", ["interleaved", "plain"])
 @pytest.mark.parametrize("shape,rows", [((37, 130), 16), ((23, 57), 8), ((70, 9), 32), ((2, 4), 8),
                                         ((1, 1), 8), ((5, 200), 64)])
-def test_2d_random_qubits(dtype, split, shape, rows):
+def test_2d_random_qubits(dtype, split, shape, rows, ysplit):
+    """Ragged 2D lattices in several band heights, the y half in one launch or two."""
     ny, nx = shape
     g, eps, nsteps = (1.1, -0.6, 0.7), 0.4, 5
     a, b = qi.random_qubits(shape, seed=ny * 1000 + nx, scale=0.5)
     lat = lattice(2, [nx], [ny], g=g, eps=eps, dtype=dtype, split=split)
-    lat.set_tuning(tile_rows=rows)
+    lat.set_tuning(tile_rows=rows, qubit_split=ysplit)
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)
     got = lat.get_qubits()[0].cpu().numpy()
     ra, rb = oracle_qubits(a, b, nsteps, eps, g, split)
     err = rel_l2(got, np.stack([ra, rb]))
     assert err <= TOL[dtype], err
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_y_split_switched_mid_run(use_graph):
+    """The y half in one launch or two leaves the state in different copies of the ping-pong
+    pair; switching the plan between steps keeps the state (against the oracle)."""
+    shape = (30, 50)
+    g, eps = (1.0, -0.5, 0.5), 0.3
+    a, b = qi.random_qubits(shape, seed=17, scale=0.5)
+    lat = lattice(2, [shape[1]], [shape[0]], g=g, eps=eps, dtype="c128")
+    lat.set_tuning(tile_rows=8, use_graph=use_graph)
+    lat.set_qubits([qubits_tensor(a, b)])
+    for n, ysplit in ((3, 0), (4, 1), (1, 1), (2, 0), (5, 1)):
+        lat.set_tuning(qubit_split=ysplit)
+        lat.step(n)
+    got = lat.get_qubits()[0].cpu().numpy()
+    ra, rb = oracle_qubits(a, b, 15, eps, g)
+    assert rel_l2(got, np.stack([ra, rb])) <= 1e-12
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -398,7 +419,7 @@ def test_batched_2d_uneven():
         assert rel_l2(gq, np.stack([ra, rb])) <= 1e-12
 
 
-@pytest.mark.parametrize("ndim,qsplit", [(1, 0), (1, 1), (1, 2), (2, 0)])
+@pytest.mark.parametrize("ndim,qsplit", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1)])
 def test_graph_replay_equals_eager(ndim, qsplit):
     shape = (777,) if ndim == 1 else (40, 90)
     a, b = qi.random_qubits(shape, seed=5, scale=0.5)
@@ -406,8 +427,7 @@ def test_graph_replay_equals_eager(ndim, qsplit):
     for use_graph in (False, True):
         lat = lattice(ndim, [shape[-1]], [shape[0]] if ndim == 2 else None, g=(1, -0.5, 0.5), eps=0.3,
                       dtype="c64")
-        lat.set_tuning(use_graph=use_graph, steps_per_pass=2 if ndim == 1 else None,
-                       qubit_split=qsplit if ndim == 1 else None)
+        lat.set_tuning(use_graph=use_graph, steps_per_pass=2 if ndim == 1 else None, qubit_split=qsplit)
         lat.set_qubits([qubits_tensor(a, b)])
         outs = []
         for rep in range(3):   # replay the same captured graph several times, with eager work between

@@ -72,17 +72,19 @@ def test_1d_potential_random_qubits(dtype, split, plan):
     assert err <= TOL[dtype], err
 
 
+@pytest.mark.parametrize("ysplit", [0, 1])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("split", ["interleaved", "plain"])
 @pytest.mark.parametrize("shape,rows", [((37, 130), 16), ((23, 57), 8), ((5, 200), 64), ((1, 1), 8)])
-def test_2d_potential_random_qubits(dtype, split, shape, rows):
-    """V + mu on ragged 2D lattices in several band heights (the y pipeline's row ring)."""
+def test_2d_potential_random_qubits(dtype, split, shape, rows, ysplit):
+    """V + mu on ragged 2D lattices in several band heights (the y pipeline's row ring), the y
+    half in one launch or two."""
     ny, nx = shape
     g, eps, mu, nsteps = (1.1, -0.6, 0.7), 0.4, -0.8, 5
     a, b = qi.random_qubits(shape, seed=ny * 7 + nx, scale=0.4)
     V = smooth_potential(shape, seed=ny + nx)
     lat = lattice(2, [nx], [ny], g=g, eps=eps, dtype=dtype, split=split)
-    lat.set_tuning(tile_rows=rows)
+    lat.set_tuning(tile_rows=rows, qubit_split=ysplit)
     lat.set_potential(V, mu)
     lat.set_qubits([qubits_tensor(a, b)])
     lat.step(nsteps)

@@ -26,7 +26,9 @@ CASES = [
     (1, (300,), {"steps_per_pass": 3, "qubit_split": 0}),
     (1, (300,), {"steps_per_pass": 2, "qubit_split": 2}),
     (2, (40, 70), {"tile_rows": 16}),
+    (2, (40, 70), {"tile_rows": 16, "qubit_split": 1}),
     (3, (10, 12, 70), {"tile_rows": 8}),
+    (3, (10, 12, 70), {"tile_rows": 8, "qubit_split": 1}),
 ]
 
 
