@@ -60,12 +60,8 @@ PREROLL_S = 0.2        # untimed steps right before each clock start, at least t
 # WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "f746a52d6013cc9c", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
-           "kib": {
-               # 2D 2048^2 vortex pair, complex128: bands of 38 rows, the y half over two launches
-               # (sums of the two)
-               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows38/ysplit": (424210.0 + 413130.0,
-                                                                              655360.0 + 657360.0)}}}
+TRAFFIC = {"sources_sha256_16": "285bcb28f2a5a673", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
+           "kib": {}}
 
 
 def parse():

@@ -98,6 +98,40 @@ QLG_HD void sincos_t(double x, double* s, double* c) {
     sincos(x, s, c);
   }
 }
+// sin x, cos x and sin(x)/x for |x| <= 1/16 by the short series of sincos_t (sin(x)/x is
+// 1 + x^2 ps, the polynomial of the sine before its final multiply-add): no branch, and
+// no division for sin(x)/x.
+QLG_HD void sincos_short(float x, float* s, float* c, float* sx) {
+  const float x2 = x * x;
+  const float ps = -1.0f / 6 + x2 * (1.0f / 120);
+  *sx = 1.0f + x2 * ps;
+  *s = x * *sx;
+  *c = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24 + x2 * (-1.0f / 720)));
+}
+QLG_HD void sincos_short(double x, double* s, double* c, double* sx) {
+  const double x2 = x * x;
+  double ps = 1.0 / 362880.0, pc = 1.0 / 40320.0;
+  ps = fma(x2, ps, -1.0 / 5040.0);
+  pc = fma(x2, pc, -1.0 / 720.0);
+  ps = fma(x2, ps, 1.0 / 120.0);
+  pc = fma(x2, pc, 1.0 / 24.0);
+  ps = fma(x2, ps, -1.0 / 6.0);
+  pc = fma(x2, pc, -0.5);
+  *sx = fma(x2, ps, 1.0);
+  *s = fma(x * x2, ps, x);
+  *c = fma(x2, pc, 1.0);
+}
+
+// Whether p holds on every active lane of the wavefront (the host build: p itself).  A
+// branch on it is uniform: no execution-mask changes, both sides never run.
+QLG_HD bool all_lanes(bool p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_ballot_w64(!p) == 0;
+#else
+  return p;
+#endif
+}
+
 QLG_HD float sqrt_t(float x) { return sqrtf(x); }
 QLG_HD double sqrt_t(double x) { return sqrt(x); }
 
@@ -297,18 +331,31 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
   // (phi ~ 0) and F is taken along z
   const T tiny2 = sizeof(T) == 4 ? T(1e-36) : T(1e-300);   // normal in both formats
   const bool has_F = Fn2 > tiny2, has_perp = Fp2 > tiny2;
-  const T iF = has_F ? rsqrt_t(Fn2) : T(0);
-  const T ip = has_perp ? rsqrt_t(Fp2) : T(0);
+  // (selects around unconditional evaluations: no divergent branch)
+  const T rF = rsqrt_t(has_F ? Fn2 : T(1)), rp = rsqrt_t(has_perp ? Fp2 : T(1));
+  const T iF = has_F ? rF : T(0);
+  const T ip = has_perp ? rp : T(0);
   const T Fn = Fn2 * iF;
   const T Fperp = Fp2 * ip;
 
-  // half-angle phases: mu = exp(-i x) - 1 = -2 sin(x/2) (sin(x/2) + i cos(x/2))
-  T s0, c0, s1, c1, s2, c2;
+  // half-angle phases: mu = exp(-i x) - 1 = -2 sin(x/2) (sin(x/2) + i cos(x/2)).  When all
+  // three half angles of every lane are at most 1/16 (the usual case) they take the short
+  // series without a branch per lane, the singlet's sin(h)/h included.
+  T s0, c0, s1, c1, s2, c2, sinc;
   const T h2 = T(0.5) * ang.tg25 * n;
-  if constexpr (kExt) sincos_t(T(0.5) * (ang.tg0 * n + ext), &s0, &c0);
-  else sincos_t(T(0.5) * ang.tg0 * n, &s0, &c0);
-  sincos_t(T(0.5) * ang.tg1 * Fn, &s1, &c1);
-  sincos_t(h2, &s2, &c2);
+  const T h0 = kExt ? T(0.5) * (ang.tg0 * n + ext) : T(0.5) * ang.tg0 * n;
+  const T h1 = T(0.5) * ang.tg1 * Fn;
+  if (all_lanes(fmax(fmax(fabs(h0), fabs(h1)), fabs(h2)) <= T(0.0625))) {
+    T x0, x1;
+    sincos_short(h0, &s0, &c0, &x0);
+    sincos_short(h1, &s1, &c1, &x1);
+    sincos_short(h2, &s2, &c2, &sinc);
+  } else {
+    sincos_t(h0, &s0, &c0);
+    sincos_t(h1, &s1, &c1);
+    sincos_t(h2, &s2, &c2);
+    sinc = fabs(h2) < T(1e-4) ? T(1) - h2 * h2 * T(1.0 / 6.0) : s2 * rcp_t(h2);
+  }
   const cx<T> mu0{T(-2) * s0 * s0, T(-2) * s0 * c0};
   const cx<T> mu1{T(-2) * s1 * s1, T(-2) * s1 * c1};
   // nu_k = exp(-i k phi) - 1 for k = 2, 1, -1, -2
@@ -323,19 +370,16 @@ QLG_HD void w_coefficients(const cx<T> (&a)[5], const cx<T> (&b)[5], const Angle
 
   // singlet coefficient (exp(-i th g2 n/5) - 1) / n = th g2/5 * sinc(h) * (-sin h - i cos h),
   // h = th g2 n / 10: no division by n, so empty or denormal sites stay finite
-  const T sinc = fabs(h2) < T(1e-4) ? T(1) - h2 * h2 * T(1.0 / 6.0) : s2 * rcp_t(h2);
   W.cs = cx<T>{-ang.tg25 * sinc * s2, -ang.tg25 * sinc * c2};
 
   // frame of F: u = e^{i alpha}, cos beta, sin beta.  With F_perp = 0, beta is 0 or pi
   // exactly, and d(beta) is taken exactly diagonal or anti-diagonal, so that components that
   // are zero and have no source stay exactly zero.
-  cx<T> u{T(1), T(0)};
-  T cb = T(1), sb = T(0);
-  if (has_perp) u = cx<T>{Fx * ip, Fy * ip};
-  if (has_F) {
-    cb = has_perp ? Fz * iF : (Fz >= T(0) ? T(1) : T(-1));
-    sb = Fperp * iF;
-  }
+  const cx<T> u{has_perp ? Fx * ip : T(1), has_perp ? Fy * ip : T(0)};
+  const T cz = Fz >= T(0) ? T(1) : T(-1), cp = Fz * iF;
+  const T cf = has_perp ? cp : cz;
+  const T cb = has_F ? cf : T(1);
+  const T sb = Fperp * iF;   // 0 without F
   W.u = u;
   W.u2 = u * u;
   // spin-2 Wigner small-d matrix d(beta) in the blocks of d_apply
