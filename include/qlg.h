@@ -113,7 +113,11 @@ typedef struct qlg_tuning {
                              tiles, steps_per_pass 1..7); 2 = two neighbouring lanes of
                              one wavefront (32-site tiles, steps_per_pass 1..3).  1 and 2
                              spread a lattice too small to fill the chip over twice the
-                             lanes.  2D and 3D: must be 0 */
+                             lanes.  2D and 3D: 0 = the four y (3D: also z) substeps of a
+                             pass in one launch; 1 = in two launches, qubit b's two then qubit
+                             a's two (with the x substeps): half the LDS per wavefront, twice
+                             the HBM round trips (the state between the launches is the true
+                             state; both forms give the same numbers) */
 } qlg_tuning;
 
 typedef struct qlg_ctx qlg_ctx;
