@@ -27,10 +27,23 @@ struct Sizes {
   int64_t nck = 0;     // checkpoints
   int nsub = 4;        // substeps per step
   int nrec = 4;        // recorded self-interaction inputs per step (nsub, or 1 for the plain split)
-  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_acc = 0, work = 0;
+  int64_t nchunks = 0; // 256-site chunks of the per-site kernels
+  int64_t nx4 = 0;     // wavefronts of the fused x substeps (56 columns of one row each)
+  int64_t nparts = 0;  // dg partials (3 doubles each) of one step's reverse sweep
+  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_xpre = 0, off_acc = 0, work = 0;
 };
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// wavefronts of k_adj_x4: ceil(nx / 56) per row of each instance
+int64_t adjoint_x4_waves(const qlg_params* p) {
+  int64_t n = 0;
+  for (int i = 0; i < p->nbatch; ++i) {
+    const int64_t ny = p->ndim >= 2 ? p->ny[i] : 1, nz = p->ndim == 3 ? p->nz[i] : 1;
+    n += (p->nx[i] + qlg::kValid2D - 1) / qlg::kValid2D * ny * nz;
+  }
+  return n;
+}
 
 int64_t adjoint_chunks(const qlg_params* p) {
   int64_t n = 0;
@@ -55,13 +68,19 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   // chunks of the per-site kernels: ceil(sites / 256) per instance, as the context's layout
   // counts them (every extent of the instance, 1D to 3D)
   const int64_t nchunks = adjoint_chunks(p);
+  s->nchunks = nchunks;
+  s->nx4 = adjoint_x4_waves(p);
+  // a step's dg partials: per chunk for the substeps of one launch each (all of the plain split;
+  // the z and y ones of the interleaved split), then per wavefront for the four fused x substeps
+  s->nparts = p->split == QLG_SPLIT_PLAIN ? s->nsub * nchunks : (s->nsub - 4) * nchunks + s->nx4;
   size_t o = 0;
   // inputs of every self-interaction of one checkpoint segment: [K][nrec] state copies
   s->off_zrec = o;  o += up256((size_t)K * (size_t)s->nrec * s->copy);
   s->off_y = o;     o += up256(2 * s->copy);   // ping-pong of the forward chain
   s->off_lam = o;   o += up256(2 * s->lam);
-  // dg partials of every substep of one step: [nsub][nchunks][3]
-  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)s->nsub * (size_t)std::max<int64_t>(nchunks, 1));
+  // dg partials of one step: [nparts][3]
+  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)std::max<int64_t>(s->nparts, 1));
+  s->off_xpre = o;  o += up256(sizeof(int) * ((size_t)p->nbatch + 1));   // k_adj_x4's instance prefix
   s->off_acc = o;   o += up256(sizeof(double) * 4);
   s->work = o;
   return QLG_OK;
@@ -159,9 +178,13 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   if (nsteps == 0) return QLG_OK;
   if (!ckpt_dev || !work_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "checkpoint or work buffer is NULL");
   if (work_bytes < s.work) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "work buffer too small");
-  // every substep kernel writes 3 partials per chunk of the context's layout; the workspace
-  // region between off_part and off_acc must hold all of them
-  if ((size_t)3 * s.nsub * (size_t)std::max(v.geom.nchunks, 1) * sizeof(double) > s.off_acc - s.off_part)
+  // every per-chunk substep kernel writes 3 partials per chunk of the context's layout, the fused x
+  // kernel 3 per wavefront; the workspace region between off_part and off_xpre must hold a step's
+  const bool plain = p.split == QLG_SPLIT_PLAIN;
+  const int64_t nparts_ctx = plain ? (int64_t)s.nsub * v.geom.nchunks
+                                   : (int64_t)(s.nsub - 4) * v.geom.nchunks + s.nx4;
+  if (v.geom.nchunks != s.nchunks || (size_t)3 * std::max<int64_t>(nparts_ctx, 1) * sizeof(double) >
+                                         s.off_xpre - s.off_part)
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "adjoint partials exceed their workspace region");
   if (((uintptr_t)work_dev & 255) || ((uintptr_t)ckpt_dev & 255))
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
@@ -176,7 +199,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   const hipStream_t str = v.stream;
   const int nd = p.ndim, dt = p.dtype, nsub = s.nsub, nrec = s.nrec;
   const int nchunks = g.nchunks;
-  const bool plain = p.split == QLG_SPLIT_PLAIN;
+  int* xpre = (int*)(W + s.off_xpre);
   const double theta = p.eps * p.eps / (4.0 * nd);
   const double theta_u = plain ? p.eps * p.eps : theta;
   // substep k of a step acts along z, y, x in that order (the last axis of each dimension first)
@@ -186,17 +209,42 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
 
   hipError_t e = qlg::launch_zero(acc, 4, str);
   if (e == hipSuccess) e = qlg::launch_lam_layout(true, lambda_dev, lam[0], g, str);
+  if (e == hipSuccess && !plain) e = qlg::launch_x4_prefix(g, xpre, str);
   if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint setup");
   int lc = 0;
   const int64_t nseg = s.nck;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t t0 = seg * K;
     const int n_in = (int)std::min<int64_t>(K, nsteps - t0);
-    // Forward chain from the checkpoint: substep k of step j is "I'_{k-1} then U_k"
-    // (the I' of the previous substep, none for the first one), recording every U input.
     const void* src = (const char*)ckpt_dev + (size_t)seg * s.copy;
     int yb = 0;
-    for (int j = 0; j < n_in; ++j) {
+    // Forward chain from the checkpoint: substep k of step j is "I'_{k-1} then U_k"
+    // (the I' of the previous substep, none for the first one), recording every U input.
+    if (!plain) {
+      // interleaved split: link (0, 0) alone, then per step the links (j, 1 .. nsub - 4) one
+      // launch each and the four links that apply x factors, (j, nsub - 3 .. nsub - 1) and
+      // (j + 1, 0), in one launch (three in the segment's last step)
+      const double tg0 = theta_u * p.g0, tg1 = theta_u * p.g1, tg25 = theta_u * p.g2 / 5.0;
+      e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(0, 0), g, -1, 0, true, tg0, tg1, tg25, v.ext, theta_u, str);
+      src = ybuf[yb];
+      yb ^= 1;
+      for (int j = 0; j < n_in && e == hipSuccess; ++j) {
+        for (int k = 1; k <= nsub - 4 && e == hipSuccess; ++k) {
+          e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(j, k), g, axis_of(k - 1), qb_of(k - 1), true, tg0, tg1,
+                                tg25, v.ext, theta_u, str);
+          src = ybuf[yb];
+          yb ^= 1;
+        }
+        if (e != hipSuccess) break;
+        void* const r[4] = {zbuf(j, nsub - 3), zbuf(j, nsub - 2), zbuf(j, nsub - 1),
+                            j + 1 < n_in ? zbuf(j + 1, 0) : nullptr};
+        e = qlg::launch_chain_x4(dt, src, ybuf[yb], r, g, xpre, (int)s.nx4, tg0, tg1, tg25, v.ext, theta_u, str);
+        src = ybuf[yb];
+        yb ^= 1;
+      }
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+    }
+    for (int j = 0; j < n_in && plain; ++j) {
       for (int k = 0; k < nsub; ++k) {
         const int kp = k == 0 ? nsub - 1 : k - 1;
         const bool first = j == 0 && k == 0;
@@ -211,7 +259,16 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
       }
     }
     for (int j = n_in - 1; j >= 0; --j) {
-      for (int k = nsub - 1; k >= 0; --k) {
+      if (!plain) {
+        // the step's last four substeps (along x) in one kernel, their dg partials after those
+        // of the nsub - 4 per-chunk substeps
+        const void* zx[4] = {zbuf(j, nsub - 1), zbuf(j, nsub - 2), zbuf(j, nsub - 3), zbuf(j, nsub - 4)};
+        e = qlg::launch_adj_x4(dt, zx, lam[lc], lam[1 - lc], g, xpre, (int)s.nx4, theta_u, p.g0, p.g1, p.g2,
+                               v.ext, part + (size_t)3 * (nsub - 4) * nchunks, str);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint x substeps kernel");
+        lc = 1 - lc;
+      }
+      for (int k = plain ? nsub - 1 : nsub - 5; k >= 0; --k) {
         if (plain) {
           e = qlg::launch_sub_iprime_adj(lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), str);
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint kinetic kernel");
@@ -227,7 +284,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         e = qlg::launch_sub_vjp(dt, zbuf(j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
       } else {
-        e = qlg::launch_dg_accumulate(part, nsub * nchunks, acc, str);
+        e = qlg::launch_dg_accumulate(part, (int)s.nparts, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint parameter-gradient reduction");
       }
     }

@@ -129,6 +129,68 @@ __device__ __forceinline__ void collide2_adj(cx<double> (&a)[5], cx<double> (&b)
   }
 }
 
+// Moves of a double by one lane across the whole wavefront (DPP wave_shl:1 / wave_shr:1);
+// the end lane, a halo lane here, reads 0.
+template <int Ctrl>
+__device__ __forceinline__ double lane_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, Ctrl, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), Ctrl, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+constexpr int kFromNextLane = 0x130;   // lane i reads lane i + 1
+constexpr int kFromPrevLane = 0x138;   // lane i reads lane i - 1
+template <int Ctrl>
+__device__ __forceinline__ float lane_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true));
+}
+template <int Ctrl, typename T>
+__device__ __forceinline__ cx<T> lane_move(cx<T> v) {
+  return cx<T>{lane_move<Ctrl>(v.re), lane_move<Ctrl>(v.im)};
+}
+
+// I'_{x,q} with x along the lanes, in the operation order of iprime_site: C, q from x + 1, C,
+// q from x - 1, and its exact 1/4.  Q = 1: qubit b moves; Q = 0: qubit a.
+template <int Q, typename T>
+__device__ __forceinline__ void iprime_lanes(cx<T> (&a)[5], cx<T> (&b)[5]) {
+  collide2(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (Q) b[m] = lane_move<kFromNextLane>(b[m]);
+    else   a[m] = lane_move<kFromNextLane>(a[m]);
+  }
+  collide2(a, b);
+  scale_quarter(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (Q) b[m] = lane_move<kFromPrevLane>(b[m]);
+    else   a[m] = lane_move<kFromPrevLane>(a[m]);
+  }
+}
+
+// lambda <- I'^H_{x,q} lambda with x along the lanes: q from x + 1, C^H, q from x - 1, C^H, 1/4
+// (the order of iprime_adj_site).  Q = 1: qubit b moves; Q = 0: qubit a.
+template <int Q>
+__device__ __forceinline__ void iprime_adj_lanes(cx<double> (&a)[5], cx<double> (&b)[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (Q) b[m] = lane_move<kFromNextLane>(b[m]);
+    else   a[m] = lane_move<kFromNextLane>(a[m]);
+  }
+  collide2_adj(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (Q) b[m] = lane_move<kFromPrevLane>(b[m]);
+    else   a[m] = lane_move<kFromPrevLane>(a[m]);
+  }
+  collide2_adj(a, b);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[m] = 0.25 * a[m];
+    b[m] = 0.25 * b[m];
+  }
+}
+
 }  // namespace
 
 // (I' in)(x) for I'_{axis,q} = S_q C S_q^T C, from `in` at x-1, x, x+1, with the fused
@@ -298,6 +360,144 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
     store_site(lout, r.d, r.s, la, lb);
   }
   block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)r.c);
+}
+
+// The four adjoint substeps along x of a step, fused: for k = k0 + 3, ..., k0 (qubits a, a, b, b),
+//   lambda <- (dU_k)^H I'^H_{x,q_k} lambda  at the recorded inputs z_k.
+// A wavefront takes 56 columns of one row (x tiles of each row, rows of each instance in order,
+// instances by the prefix table xpre) plus 4 halo columns on each side: each I'^H reaches one
+// site, so after the four substeps the middle 56 lanes hold the cotangent of their sites, read
+// and written once instead of once per substep.  The x shifts are lane moves.  Only the 56 owned
+// lanes add to the dg partial of the wavefront (part[3 w + 0..2]).
+// (One wave per SIMD: its registers, 256 + about 100 accumulation registers, do not fit the
+// 256 of two waves without spilling to scratch, which measured 1.5x slower.)
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_adj_x4(const cx<T>* __restrict__ z3, const cx<T>* __restrict__ z2,
+                                                  const cx<T>* __restrict__ z1, const cx<T>* __restrict__ z0,
+                                                  const cx<double>* __restrict__ lin, cx<double>* __restrict__ lout,
+                                                  LaunchGeom g, const int* __restrict__ xpre, int nwaves,
+                                                  double theta, double g0, double g1, double g2,
+                                                  const double* __restrict__ pot, double mu,
+                                                  double* __restrict__ part) {
+  constexpr int kWaves = kChunk / kLanes;
+  const int w = chunk_of_block(blockIdx.x, gridDim.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= nwaves) return;
+  const int lane = threadIdx.x & (kLanes - 1);
+  // instance: the last i with xpre[i] <= w (wavefront-uniform)
+  int lo = 0, hi = g.nbatch;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (xpre[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  const InstDesc d = g.inst[lo];
+  const int t = w - xpre[lo];
+  const int ntx = (d.nx + kValid2D - 1) / kValid2D;
+  const int tx = t % ntx, row = t / ntx;
+  const int x = tx * kValid2D - kHalo2D + lane;
+  const int xw = x < 0 ? x + d.nx * ((-x + d.nx - 1) / d.nx) : x % d.nx;
+  const bool own = lane >= kHalo2D && lane < kLanes - kHalo2D && x < d.nx;
+  const int s = row * d.nx + xw;
+  cx<double> la[5], lb[5];
+  load_site(lin, d, s, la, lb);
+  const double ext = theta * ((pot ? pot[d.psi_off / 5 + s] : 0.0) + mu);
+  double dg[3] = {0.0, 0.0, 0.0};
+  // each substep's recorded input is loaded one substep ahead, so that its latency overlaps
+  // the previous substep's arithmetic (one wavefront per SIMD hides nothing by itself)
+  cx<T> na[5], nb[5];
+  load_site_nt(z3, d, s, na, nb);
+#pragma unroll 1
+  for (int i = 0; i < 4; ++i) {   // k0 + 3, k0 + 2 (qubit a), k0 + 1, k0 (qubit b)
+    cx<double> a[5], b[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      a[m] = cx<double>{(double)na[m].re, (double)na[m].im};
+      b[m] = cx<double>{(double)nb[m].re, (double)nb[m].im};
+    }
+    if (i < 3) load_site_nt(i == 0 ? z2 : i == 1 ? z1 : z0, d, s, na, nb);
+    if (i < 2) iprime_adj_lanes<0>(la, lb);
+    else iprime_adj_lanes<1>(la, lb);
+    double dgl[3] = {0.0, 0.0, 0.0};
+    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dgl, ext);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dg[k] += own ? dgl[k] : 0.0;
+  }
+  if (own) store_site(lout, d, s, la, lb);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dg[k] += __shfl_xor(dg[k], o, kLanes);
+  }
+  if (lane == 0) {
+    part[3 * (int64_t)w] = dg[0];
+    part[3 * (int64_t)w + 1] = dg[1];
+    part[3 * (int64_t)w + 2] = dg[2];
+  }
+}
+
+// The links of the recorded forward chain that apply x kinetic factors, fused: for the links
+// (j, nsub - 3), (j, nsub - 2), (j, nsub - 1) and, when r3 is set, (j + 1, 0),
+//   z <- I'_{x,q}(y) (q = b, b, a, a),  r_i <- z,  y <- U(z),
+// on the tiles of k_adj_x4 (56 columns of one row plus 4 halo columns on each side, the x
+// shifts as lane moves): the state is read and written once for the four links.  Only the
+// owned lanes store their records and the output.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_chain_x4(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                    cx<T>* __restrict__ r0, cx<T>* __restrict__ r1,
+                                                    cx<T>* __restrict__ r2, cx<T>* __restrict__ r3,
+                                                    LaunchGeom g, const int* __restrict__ xpre, int nwaves,
+                                                    Angles<T> ang, const double* __restrict__ pot, double mu,
+                                                    double theta) {
+  constexpr int kWaves = kChunk / kLanes;
+  const int w = chunk_of_block(blockIdx.x, gridDim.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= nwaves) return;
+  const int lane = threadIdx.x & (kLanes - 1);
+  int lo = 0, hi = g.nbatch;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (xpre[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  const InstDesc d = g.inst[lo];
+  const int t = w - xpre[lo];
+  const int ntx = (d.nx + kValid2D - 1) / kValid2D;
+  const int tx = t % ntx, row = t / ntx;
+  const int x = tx * kValid2D - kHalo2D + lane;
+  const int xw = x < 0 ? x + d.nx * ((-x + d.nx - 1) / d.nx) : x % d.nx;
+  const bool own = lane >= kHalo2D && lane < kLanes - kHalo2D && x < d.nx;
+  const int s = row * d.nx + xw;
+  cx<T> a[5], b[5];
+  load_site(in, d, s, a, b);
+  const bool ext = pot || mu != 0.0;
+  const T e = T(theta) * T((pot ? pot[d.psi_off / 5 + s] : 0.0) + mu);
+  auto link = [&](cx<T>* __restrict__ rec) {
+    if (own) store_site_nt(rec, d, s, a, b);
+    if (ext) potential<T, true>(a, b, ang, e);
+    else potential(a, b, ang);
+  };
+  iprime_lanes<1>(a, b);
+  link(r0);
+  iprime_lanes<1>(a, b);
+  link(r1);
+  iprime_lanes<0>(a, b);
+  link(r2);
+  if (r3) {
+    iprime_lanes<0>(a, b);
+    link(r3);
+  }
+  if (own) store_site(out, d, s, a, b);
+}
+
+// xpre[i] = wavefronts of k_adj_x4 before instance i (xpre[nbatch] = all of them).
+__global__ void k_x4_prefix(LaunchGeom g, int* __restrict__ xpre) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int acc = 0;
+  for (int i = 0; i < g.nbatch; ++i) {
+    xpre[i] = acc;
+    const InstDesc d = g.inst[i];
+    acc += (d.nx + kValid2D - 1) / kValid2D * d.ny * d.nz;
+  }
+  xpre[g.nbatch] = acc;
 }
 
 // acc[0..2] += sum over chunks of part (single block, fixed order).  Unrolling
@@ -502,6 +702,46 @@ hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* la
   else
     hipLaunchKernelGGL(k_sub_adj<double>, QLG_GRID, (const cx<double>*)z, (const cx<double>*)lam_in,
                        (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, ext.V, ext.mu, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_x4(int dtype, const void* in, void* out, void* const rec[4], const LaunchGeom& g,
+                           const int* xpre, int nwaves, double tg0, double tg1, double tg25, const ExtPot& ext,
+                           double theta, hipStream_t st) {
+  if (nwaves <= 0) return hipSuccess;
+  constexpr int kWaves = kChunk / kLanes;
+  const dim3 grid((nwaves + kWaves - 1) / kWaves), block(kChunk);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_chain_x4<float>, grid, block, 0, st, (const cx<float>*)in, (cx<float>*)out,
+                       (cx<float>*)rec[0], (cx<float>*)rec[1], (cx<float>*)rec[2], (cx<float>*)rec[3], g, xpre,
+                       nwaves, Angles<float>{(float)tg0, (float)tg1, (float)tg25}, ext.V, ext.mu, theta);
+  else
+    hipLaunchKernelGGL(k_chain_x4<double>, grid, block, 0, st, (const cx<double>*)in, (cx<double>*)out,
+                       (cx<double>*)rec[0], (cx<double>*)rec[1], (cx<double>*)rec[2], (cx<double>*)rec[3], g,
+                       xpre, nwaves, Angles<double>{tg0, tg1, tg25}, ext.V, ext.mu, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_x4_prefix(const LaunchGeom& g, int* xpre, hipStream_t st) {
+  hipLaunchKernelGGL(k_x4_prefix, dim3(1), dim3(64), 0, st, g, xpre);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_x4(int dtype, const void* const z[4], const void* lam_in, void* lam_out, const LaunchGeom& g,
+                         const int* xpre, int nwaves, double theta, double g0, double g1, double g2,
+                         const ExtPot& ext, double* part, hipStream_t st) {
+  if (nwaves <= 0) return hipSuccess;
+  constexpr int kWaves = kChunk / kLanes;
+  const dim3 grid((nwaves + kWaves - 1) / kWaves), block(kChunk);
+  const double* pot = ext.V;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_adj_x4<float>, grid, block, 0, st, (const cx<float>*)z[0], (const cx<float>*)z[1],
+                       (const cx<float>*)z[2], (const cx<float>*)z[3], (const cx<double>*)lam_in,
+                       (cx<double>*)lam_out, g, xpre, nwaves, theta, g0, g1, g2, pot, ext.mu, part);
+  else
+    hipLaunchKernelGGL(k_adj_x4<double>, grid, block, 0, st, (const cx<double>*)z[0], (const cx<double>*)z[1],
+                       (const cx<double>*)z[2], (const cx<double>*)z[3], (const cx<double>*)lam_in,
+                       (cx<double>*)lam_out, g, xpre, nwaves, theta, g0, g1, g2, pot, ext.mu, part);
   return hipGetLastError();
 }
 

@@ -20,6 +20,21 @@ hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom&
 hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* lam_out, const LaunchGeom& g, int axis,
                           int qb, double theta, double g0, double g1, double g2, const ExtPot& ext, double* part,
                           hipStream_t st);
+// The four adjoint substeps along x of one step in one launch (k_adj_x4): z[0..3] are the
+// recorded inputs of substeps k0 + 3, k0 + 2, k0 + 1, k0 (the order they are undone in);
+// nwaves = xpre[nbatch] wavefronts of 56 columns of one row; one dg partial per wavefront
+// into part[nwaves][3] (no accumulation).
+hipError_t launch_adj_x4(int dtype, const void* const z[4], const void* lam_in, void* lam_out, const LaunchGeom& g,
+                         const int* xpre, int nwaves, double theta, double g0, double g1, double g2,
+                         const ExtPot& ext, double* part, hipStream_t st);
+// The chain links that apply x kinetic factors, fused (k_chain_x4): links (j, nsub - 3 ..
+// nsub - 1) and, when rec[3] is not null, (j + 1, 0); rec[i] receives the input of the
+// link's U, out the state after the last.  Tiles as launch_adj_x4's.
+hipError_t launch_chain_x4(int dtype, const void* in, void* out, void* const rec[4], const LaunchGeom& g,
+                           const int* xpre, int nwaves, double tg0, double tg1, double tg25, const ExtPot& ext,
+                           double theta, hipStream_t st);
+// xpre[0..nbatch]: prefix sums over the instances of ceil(nx / 56) ny nz (device table)
+hipError_t launch_x4_prefix(const LaunchGeom& g, int* xpre, hipStream_t st);
 // acc[0..2] += sum of nparts consecutive 3-vectors of part (fixed order)
 hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hipStream_t st);
 // energy objective: canonical complex128 cotangent + chunk partials [nchunks][4]
