@@ -335,6 +335,14 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_eve
  * Asynchronous on the context's stream. */
 qlg_status qlg_set_psi_adjoint(qlg_ctx* ctx, const void* lambda_dev, void* dpsi_dev);
 
+/* Fault injection, for tests of the error-state contract above: puts the context into the
+ * state that a failed HIP launch or copy leaves, without touching the device — returns
+ * QLG_ERR_DEVICE, after which every call on the context except qlg_destroy and
+ * qlg_last_error returns QLG_ERR_STATE, and qlg_last_error names `reason` (may be NULL).
+ * Enqueues nothing; other contexts are not affected.  QLG_ERR_ARG for a NULL context,
+ * QLG_ERR_STATE if the context is already in the error state. */
+qlg_status qlg_inject_device_error(qlg_ctx* ctx, const char* reason);
+
 /* Human-readable status name, and the last error message of a context. */
 const char* qlg_status_string(qlg_status status);
 const char* qlg_last_error(const qlg_ctx* ctx);

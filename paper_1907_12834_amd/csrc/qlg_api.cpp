@@ -438,6 +438,12 @@ const char* qlg_status_string(qlg_status s) {
 
 const char* qlg_last_error(const qlg_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
+qlg_status qlg_inject_device_error(qlg_ctx* c, const char* reason) {
+  qlg_status s = check_ctx(c);
+  if (s) return s;
+  return fail(c, QLG_ERR_DEVICE, std::string("injected device error: ") + (reason ? reason : ""));
+}
+
 qlg_status qlg_query_sizes(const qlg_params* p, size_t* state_bytes, size_t* scratch_bytes) {
   const char* msg = nullptr;
   qlg_status s = validate(p, &msg);
@@ -798,6 +804,7 @@ qlg_status qlg_set_tuning(qlg_ctx* c, const qlg_tuning* t) {
 
 qlg_status qlg_get_tuning(const qlg_ctx* c, qlg_tuning* t) {
   if (!c || !t) return QLG_ERR_ARG;
+  if (c->broken) return QLG_ERR_STATE;
   *t = c->tuning;
   return QLG_OK;
 }
@@ -893,6 +900,7 @@ qlg_status qlg_set_timing(qlg_ctx* c, int32_t enable) {
 
 qlg_status qlg_last_kernel_ms(qlg_ctx* c, double* ms, int64_t* launches) {
   if (!c || !ms || !launches) return QLG_ERR_ARG;
+  if (c->broken) return QLG_ERR_STATE;
   *ms = c->time_launches ? c->time_ms / c->time_launches : 0.0;
   *launches = c->time_launches;
   return QLG_OK;

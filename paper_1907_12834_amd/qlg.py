@@ -30,8 +30,8 @@ EXPORTED = [
     "qlg_get_qubits", "qlg_set_potential", "qlg_fields", "qlg_vorticity", "qlg_find_vortices", "qlg_step", "qlg_observables", "qlg_record_observables", "qlg_decode_records",
     "qlg_set_tuning", "qlg_get_tuning",
     "qlg_autotune", "qlg_set_timing", "qlg_last_kernel_ms", "qlg_adjoint_query",
-    "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_set_psi_adjoint", "qlg_status_string",
-    "qlg_last_error", "qlg_destroy",
+    "qlg_forward_record", "qlg_objective_grad", "qlg_adjoint_step", "qlg_set_psi_adjoint",
+    "qlg_inject_device_error", "qlg_status_string", "qlg_last_error", "qlg_destroy",
 ]
 
 
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "qlg_objective_grad": (i32, [vp, i32, vp, vp, P(dbl), P(dbl)]),
         "qlg_adjoint_step": (i32, [vp, i64, i32, vp, vp, vp, sz, P(dbl)]),
         "qlg_set_psi_adjoint": (i32, [vp, vp, vp]),
+        "qlg_inject_device_error": (i32, [vp, ctypes.c_char_p]),
         "qlg_status_string": (ctypes.c_char_p, [i32]),
         "qlg_last_error": (ctypes.c_char_p, [vp]),
         "qlg_destroy": (None, [vp]),

@@ -5,6 +5,8 @@ fresh context with qlg_set_qubits, ends bit-identical to the uninterrupted run (
 both dtypes).  Faults: a non-finite amplitude loaded from the host is reported as
 QLG_ERR_NUMERIC by qlg_observables and by the decoding of device-side records, without
 breaking the context; so is a record whose qubit norm has drifted beyond the dtype's bound.
+A failed HIP call (injected) leaves the context in the error state, every later call returning
+QLG_ERR_STATE.
 """
 import numpy as np
 import pytest
@@ -138,3 +140,44 @@ def test_tune_cache_file_persists_plans(tmp_path, monkeypatch):
     lat2.close()
     lat3 = lattice(2, [100], [90], g=G, eps=0.3, dtype="c128")
     assert lat3.tuning() == plan
+
+
+def test_error_state_after_a_device_failure():
+    """The error-state contract of the C ABI: after a failed HIP call (injected through
+    qlg_inject_device_error, which touches no device memory) every call on the context except
+    qlg_destroy and qlg_last_error returns QLG_ERR_STATE, the message names the failure, and
+    other contexts keep working."""
+    import ctypes
+    from paper_1907_12834_amd.qlg import QLGError, lib
+    ERR_DEVICE, ERR_STATE = 4, 6
+    shape = (24, 70)
+    psi = qi.random_field(shape, seed=5, scale=0.4)
+    bad = lattice(2, nx=[shape[1]], ny=[shape[0]], g=G, eps=0.3, dtype="c128")
+    good = lattice(2, nx=[shape[1]], ny=[shape[0]], g=G, eps=0.3, dtype="c128")
+    for lat in (bad, good):
+        lat.set_psi([torch.from_numpy(psi)])
+        lat.step(3)
+    L = lib()
+    assert L.qlg_inject_device_error(bad.ctx, b"test") == ERR_DEVICE
+    assert "injected device error: test" in L.qlg_last_error(bad.ctx).decode()
+    assert L.qlg_inject_device_error(bad.ctx, None) == ERR_STATE
+    calls = [lambda: bad.step(1), lambda: bad.observables(), lambda: bad.get_psi(),
+             lambda: bad.set_psi([torch.from_numpy(psi)]), lambda: bad.get_qubits(), lambda: bad.autotune(),
+             lambda: bad.set_tuning(tile_rows=8), lambda: bad.tuning(), lambda: bad.fields(("n",)),
+             lambda: bad.vorticity(0), lambda: bad.set_timing(True), lambda: bad.last_kernel_ms(),
+             lambda: bad.forward_record(4, 2)]
+    for k, call in enumerate(calls):
+        try:
+            call()
+        except QLGError as err:
+            assert err.status == ERR_STATE, (k, err)
+        else:
+            pytest.fail("call %d returned normally on a context in the error state" % k)
+    assert L.qlg_step(bad.ctx, ctypes.c_int64(1)) == ERR_STATE
+    # the failure stays with its context
+    ref = lattice(2, nx=[shape[1]], ny=[shape[0]], g=G, eps=0.3, dtype="c128")
+    ref.set_psi([torch.from_numpy(psi)])
+    ref.step(5)
+    good.step(2)
+    assert np.array_equal(good.get_qubits()[0].cpu().numpy(), ref.get_qubits()[0].cpu().numpy())
+    bad.close()   # qlg_destroy of a context in the error state
