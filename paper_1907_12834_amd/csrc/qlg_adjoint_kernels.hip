@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kChunk) void k_adj_x4(const cx<T>* __restrict__ z3,
     if (i < 2) iprime_adj_lanes<0>(la, lb);
     else iprime_adj_lanes<1>(la, lb);
     double dgl[3] = {0.0, 0.0, 0.0};
-    potential_vjp(a, b, la, lb, theta, g0, g1, g2, dgl, ext);
+    potential_vjp<true>(a, b, la, lb, theta, g0, g1, g2, dgl, ext);
 #pragma unroll
     for (int k = 0; k < 3; ++k) dg[k] += own ? dgl[k] : 0.0;
   }

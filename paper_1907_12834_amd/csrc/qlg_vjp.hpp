@@ -42,7 +42,7 @@ struct UFrame {
   cx<double> E[5];     // e^{-i (phi0 + m phi)}, m = 2..-2
   cx<double> u;        // e^{i alpha}
   cx<double> e0, eh;   // e^{-i phi0}, e^{-i phi/2}
-  double sh_phi;       // sin(phi/2)
+  double sinc_hp;      // sin(phi/2) / (phi/2)
   cx<double> ekn;      // e^{-i kappa n}, kappa = theta g2 / 5
   double ca, sa, cb, sb;
   DBlocks<double> d;   // d^2(beta) in the blocks of d_apply (qlg_math.hpp)
@@ -51,6 +51,12 @@ struct UFrame {
 // ext: theta (V + mu) of a psi-independent term (V(x) + mu) psi_m in the equation of
 // motion; it joins the density phase phi0 and, not depending on psi, adds nothing
 // to the derivatives with respect to n, F or the couplings.
+// kUniform: when the three angles (phi0, phi/2 and the singlet's kappa n / 2) are at most
+// 1/16 on every lane of the wavefront, all lanes take the short sine/cosine series without a
+// per-lane branch (one uniform test), sin(x)/x from the same polynomials, and the frame as
+// selects: for kernels that run one wavefront per SIMD, where every branch instruction costs
+// an issue slot of the VALU.  The results are those of the per-lane form to rounding.
+template <bool kUniform = false>
 QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double theta, double g0,
                     double g1, double g2, UFrame& f, double ext = 0.0) {
   const double r6 = Consts::r6;
@@ -69,16 +75,38 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
   const double Fn2 = Fp2 + f.Fz * f.Fz;
   // |F|, F_perp and their reciprocals (below the normal range the frame is immaterial: phi ~ 0)
   const double tiny2 = 1e-300;
-  const double iP = Fp2 > tiny2 ? rsqrt_t(Fp2) : 0.0, iF = Fn2 > tiny2 ? rsqrt_t(Fn2) : 0.0;
+  const bool has_F = Fn2 > tiny2, has_perp = Fp2 > tiny2;
+  double iP, iF;
+  if constexpr (kUniform) {
+    const double rP = rsqrt_t(has_perp ? Fp2 : 1.0), rF = rsqrt_t(has_F ? Fn2 : 1.0);
+    iP = has_perp ? rP : 0.0;
+    iF = has_F ? rF : 0.0;
+  } else {
+    iP = has_perp ? rsqrt_t(Fp2) : 0.0;
+    iF = has_F ? rsqrt_t(Fn2) : 0.0;
+  }
   f.Fperp = Fp2 * iP;
   f.Fn = Fn2 * iF;
   f.phi0 = theta * g0 * f.n + ext;
   f.phi = theta * g1 * f.Fn;
+  // c(n) = (e^{-i kappa n} - 1)/n = kappa sinc(h) (-sin h - i cos h), h = kappa n / 2
+  const double kappa = theta * g2 * 0.2, h = 0.5 * kappa * f.n;
+  const double hp = 0.5 * f.phi;
+  double s0, c0, s1, c1, sh, ch, sinc;
+  if (kUniform && all_lanes(fmax(fmax(fabs(f.phi0), fabs(hp)), fabs(h)) <= 0.0625)) {
+    double x0;
+    sincos_short(f.phi0, &s0, &c0, &x0);
+    sincos_short(hp, &s1, &c1, &f.sinc_hp);
+    sincos_short(h, &sh, &ch, &sinc);
+  } else {
+    sincos_t(f.phi0, &s0, &c0);
+    sincos_t(hp, &s1, &c1);
+    sincos_t(h, &sh, &ch);
+    sinc = fabs(h) < 1e-4 ? 1.0 - h * h * (1.0 / 6.0) : sh * rcp_t(h);
+    f.sinc_hp = fabs(hp) < 1e-4 ? 1.0 - hp * hp * (1.0 / 6.0) : s1 * rcp_t(hp);
+  }
   // E_m = e^{-i phi0} (e^{-i phi})^m from two phases: e^{-i phi0} and eh = e^{-i phi/2}
   {
-    double s0, c0, s1, c1;
-    sincos_t(f.phi0, &s0, &c0);
-    sincos_t(0.5 * f.phi, &s1, &c1);
     const cx<double> e0{c0, -s0}, eh{c1, -s1}, e1 = eh * eh;
     f.E[2] = e0;
     f.E[1] = e0 * e1;
@@ -87,21 +115,24 @@ QLG_HD void u_frame(const cx<double> (&a)[5], const cx<double> (&b)[5], double t
     f.E[4] = f.E[3] * conj(e1);
     f.e0 = e0;
     f.eh = eh;
-    f.sh_phi = s1;
   }
-  // c(n) = (e^{-i kappa n} - 1)/n = kappa sinc(h) (-sin h - i cos h), h = kappa n / 2
-  const double kappa = theta * g2 * 0.2, h = 0.5 * kappa * f.n;
-  double sh, ch;
-  sincos_t(h, &sh, &ch);
-  const double sinc = fabs(h) < 1e-4 ? 1.0 - h * h * (1.0 / 6.0) : sh * rcp_t(h);
   f.cs = cx<double>{-kappa * sinc * sh, -kappa * sinc * ch};
   f.ekn = cx<double>{ch, -sh} * cx<double>{ch, -sh};   // e^{-i kappa n}
-  // frame
-  f.ca = 1.0; f.sa = 0.0; f.cb = 1.0; f.sb = 0.0;
-  if (Fp2 > tiny2) { f.ca = f.Fx * iP; f.sa = f.Fy * iP; }
-  if (Fn2 > tiny2) {   // F_perp = 0: beta = 0 or pi exactly (as in the forward)
-    f.cb = Fp2 > tiny2 ? f.Fz * iF : (f.Fz >= 0 ? 1.0 : -1.0);
-    f.sb = f.Fperp * iF;
+  // frame (F_perp = 0: beta = 0 or pi exactly, as in the forward)
+  if constexpr (kUniform) {
+    f.ca = has_perp ? f.Fx * iP : 1.0;
+    f.sa = has_perp ? f.Fy * iP : 0.0;
+    const double cz = f.Fz >= 0 ? 1.0 : -1.0, cp = f.Fz * iF;
+    const double cf = has_perp ? cp : cz;
+    f.cb = has_F ? cf : 1.0;
+    f.sb = f.Fperp * iF;   // 0 without F
+  } else {
+    f.ca = 1.0; f.sa = 0.0; f.cb = 1.0; f.sb = 0.0;
+    if (has_perp) { f.ca = f.Fx * iP; f.sa = f.Fy * iP; }
+    if (has_F) {
+      f.cb = has_perp ? f.Fz * iF : (f.Fz >= 0 ? 1.0 : -1.0);
+      f.sb = f.Fperp * iF;
+    }
   }
   f.u = cx<double>{f.ca, f.sa};
   f.d = d_blocks(f.cb, f.sb);
@@ -139,9 +170,10 @@ QLG_HD void apply_S(const cx<double> (&z)[5], cx<double> (&out)[5]) {
 // c'(n) = sum_{j>=2} (-i k)^j (j-1) n^{j-2} / j! = (-i k)^2 sum_{q>=0} (q+1)/(q+2)! (-i z)^q,
 // z = k n, truncated after q = 12 (the next term is below 1e-24): its real and imaginary
 // parts are the even and odd powers of z, two polynomials in z^2.
+template <bool kUniform = false>
 QLG_HD cx<double> dc_dn(double kappa, double n, cx<double> e) {
   const double z = kappa * n;
-  if (fabs(z) < 0.1) {
+  auto series = [&]() {
     const double y = z * z;
     // (q+1)/(q+2)! for q = 0..12, alternating in sign within each parity
     const double pe = 1.0 / 2 + y * (-1.0 / 8 + y * (1.0 / 144 + y * (-1.0 / 5760 + y * (1.0 / 403200 +
@@ -150,7 +182,12 @@ QLG_HD cx<double> dc_dn(double kappa, double n, cx<double> e) {
                       y * (-1.0 / 518918400.0)))));
     const double k2 = kappa * kappa;
     return cx<double>{-k2 * pe, k2 * z * po};   // -k^2 (pe - i z po)
+  };
+  const bool small = fabs(z) < 0.1;
+  if constexpr (kUniform) {
+    if (all_lanes(small)) return series();   // the usual case, without a per-lane branch
   }
+  if (small) return series();
   const double in = rcp_t(n);
   const cx<double> cn = in * (e - cx<double>{1.0, 0.0});
   const cx<double> t = cx<double>{0.0, -kappa} * e;            // -i k e^{-ikn}
@@ -159,11 +196,12 @@ QLG_HD cx<double> dc_dn(double kappa, double n, cx<double> e) {
 
 // In: a, b (input of U), la, lb (cotangents of U's outputs).
 // Out: la, lb replaced by cotangents of a, b; dg[0..2] incremented.
+template <bool kUniform = false>
 QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx<double> (&la)[5],
                           cx<double> (&lb)[5], double theta, double g0, double g1, double g2, double (&dg)[3],
                           double ext = 0.0) {
   UFrame f;
-  u_frame(a, b, theta, g0, g1, g2, f, ext);
+  u_frame<kUniform>(a, b, theta, g0, g1, g2, f, ext);
   const double tau = theta * g1;
   cx<double> v[5];
   {
@@ -177,9 +215,7 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
   double dFx = 0.0, dFy = 0.0, dGz = 0.0;
   cx<double> lpsi[5] = {};
   const double cfac[4] = {2.0, Consts::r6, Consts::r6, 2.0};
-  // sinc(phi/2), from the sine of the frame's half phase
-  const double hp = 0.5 * f.phi;
-  const double sc = fabs(hp) < 1e-4 ? 1.0 - hp * hp * (1.0 / 6.0) : f.sh_phi * rcp_t(hp);
+  const double sc = f.sinc_hp;   // sinc(phi/2)
   // divided differences between neighbouring m: Delta = e^{-i phi0} e^{-i phi (m_i + m_{i+1})/2} sinc(phi/2),
   // m_i + m_{i+1} = 3, 1, -1, -3: powers of eh = e^{-i phi/2}
   cx<double> dlt[4];
@@ -192,7 +228,7 @@ QLG_HD void potential_vjp(const cx<double> (&a)[5], const cx<double> (&b)[5], cx
     dlt[3] = v3;
   }
   const double kappa = theta * g2 * 0.2;
-  const cx<double> dcn = dc_dn(kappa, f.n, f.ekn);
+  const cx<double> dcn = dc_dn<kUniform>(kappa, f.n, f.ekn);
   const cx<double> dcg = cx<double>{0.0, -theta * 0.2} * f.ekn;
   // one 5-vector x; l holds the output cotangent on entry and P^H lambda_{y1} on exit
   auto one = [&](const cx<double>(&x)[5], cx<double>(&l)[5]) {
