@@ -66,7 +66,10 @@ TRAFFIC = {"sources_sha256_16": "285bcb28f2a5a673", "fetch_scale": 262144.0 / 13
                "1d_two_soliton_scattering/c64/interleaved": {"k_step1d_lanes/S2": (740.5, 1280.0)},
                # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
                "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365700.7, 655360.0)},
-               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232967.5, 328211.8)},
+               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232967.5, 328211.8),
+                                                  # the y half over two launches (sums of the two)
+                                                  "k_step2d/rows19/ysplit": (239680.0 + 234990.0,
+                                                                             331270.0 + 329280.0)},
                "2d_vortex_pair/c64/plain": {"k_step2d/rows38": (229592.2, 330088.1)},
                # 3D 256^3 vortex lines: one step = z pass + y-x pass, each over two launches
                # (z: b stages, a stages; y: b stages, a stages + x half), sums of the four

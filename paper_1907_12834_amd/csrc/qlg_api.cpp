@@ -853,20 +853,42 @@ qlg_status qlg_autotune(qlg_ctx* c) {
     if ((s = build_tiles(c))) break;
     const int S = c->p.ndim == 1 ? t.steps_per_pass : 1;
     // passes read the current copy and write the other one without swapping: the state is
-    // unchanged.  One warm-up pass, then the best of two timed batches.
-    hipError_t e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur), nullptr, nullptr, true);
+    // unchanged.  The batch of passes is captured once as a hipGraph and replayed, as the runs
+    // replay theirs (eager launches would add a dispatch gap per launch, which the plans that
+    // split a step into more launches pay more of).  One warm-up replay, then the best of two.
     const int reps = 8;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e;
+    {
+      hipStream_t cap = nullptr;
+      e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      hipGraph_t graph = nullptr;
+      if (e == hipSuccess) {
+        hipStream_t saved = c->stream;
+        c->stream = cap;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        for (int k = 0; k < reps && e == hipSuccess; ++k)
+          e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur), nullptr, nullptr, true);
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+        c->stream = saved;
+        (void)hipStreamDestroy(cap);
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
     double per_step = 1e300;
+    if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
     for (int round = 0; round < 2 && e == hipSuccess; ++round) {
       e = hipEventRecord(e0, c->stream);
-      for (int k = 0; k < reps && e == hipSuccess; ++k)
-        e = launch_pass(c, S, false, c->copy(c->cur), c->copy(1 - c->cur), nullptr, nullptr, true);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
       if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e == hipSuccess) per_step = std::min(per_step, ms / (reps * (double)S));
     }
+    if (exec) (void)hipGraphExecDestroy(exec);
     if (e != hipSuccess) { s = hip_check(c, e, "autotune"); break; }
     per_step_ms.push_back(per_step);
   }
