@@ -60,21 +60,8 @@ PREROLL_S = 0.2        # untimed steps right before each clock start, at least t
 # WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "285bcb28f2a5a673", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
-           "kib": {
-               # 1D two-soliton lattice, L = 16384: the two-lane kernel at 2 steps per pass
-               "1d_two_soliton_scattering/c64/interleaved": {"k_step1d_lanes/S2": (740.5, 1280.0)},
-               # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
-               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365700.7, 655360.0)},
-               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows38": (232967.5, 328211.8),
-                                                  # the y half over two launches (sums of the two)
-                                                  "k_step2d/rows19/ysplit": (239680.0 + 234990.0,
-                                                                             331270.0 + 329280.0)},
-               "2d_vortex_pair/c64/plain": {"k_step2d/rows38": (229592.2, 330088.1)},
-               # 3D 256^3 vortex lines: one step = z pass + y-x pass, each over two launches
-               # (z: b stages, a stages; y: b stages, a stages + x half), sums of the four
-               "3d_vortex_lines/c64/interleaved": {"k_step3d/rows86/ysplit": (
-                   691285.9 + 691304.9 + 937231.6 + 857334.6, 1310720.0 + 1310720.0 + 1319585.5 + 1319286.8)}}}
+TRAFFIC = {"sources_sha256_16": "", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
+           "kib": {}}
 
 
 def parse():

@@ -574,18 +574,24 @@ __device__ __forceinline__ void y_stage_lds(cx<T> (&a)[5], cx<T> (&b)[5], cx<T>*
 
 // LDS words per wavefront and y stage of the pipeline: (cn[5], mq[5]) x 64 lanes.
 constexpr int kSlotsPerStage = 10;
-constexpr int k2DWaves = 2;   // wavefronts per workgroup of the 2D kernel
 
 // Parts of a step (StepPart): a launch of kYFirst or kYSecond keeps a two-stage pipeline,
 // half the LDS of the four-stage one, which lets two wavefronts share a SIMD in complex128.
 // The state between the two launches is the true state (scale 1).
 template <int kPart>
 constexpr int stages_of() { return kPart == kWhole ? 4 : 2; }
+// Wavefronts per workgroup: four for the single launch, two for the split.  The single
+// launch is meant to run one wavefront per SIMD: a workgroup of four lands one wavefront on
+// each SIMD of a CU; with workgroups of two and fewer than 256 registers per lane, the
+// wavefronts of two workgroups can share two SIMDs of a CU and leave the other two idle
+// (complex128 2D: 1.63 against 0.95 ms per step).
+template <int kPart>
+constexpr int waves_of() { return kPart == kWhole ? 4 : 2; }
 
 // With the y half split, a launch's pipeline leaves LDS for two wavefronts per SIMD: the
 // register budget is set to match (256 per lane).
 template <typename T, bool kExt, int kPart>
-__global__ __launch_bounds__(64 * k2DWaves) __attribute__((amdgpu_waves_per_eu(kPart == kWhole ? 1 : 2)))
+__global__ __launch_bounds__(64 * waves_of<kPart>()) __attribute__((amdgpu_waves_per_eu(kPart == kWhole ? 1 : 2)))
 void k_step2d(StepArgs<T> A) {
   constexpr int kStages = stages_of<kPart>();
   constexpr int kLag = 2 * kStages;          // rows between a row's load and its store
@@ -594,7 +600,7 @@ void k_step2d(StepArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the tile and everything derived from it are wavefront-uniform (scalar registers)
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * k2DWaves + wv;
+  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * waves_of<kPart>() + wv;
   if (w >= A.ntiles) return;
   const int lane = threadIdx.x & (kLanes - 1);
   cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStages * kSlotsPerStage * kLanes) + lane;
@@ -1051,9 +1057,10 @@ hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overl
 }
 
 template <typename T, bool kExt, int kPart>
-static void launch_step2d_k(dim3 grid, dim3 block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
-                            const StepArgs<T>& args) {
-  const size_t lds = sizeof(cx<T>) * stages_of<kPart>() * kSlotsPerStage * kLanes * k2DWaves;
+static void launch_step2d_k(int ntiles, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const StepArgs<T>& args) {
+  constexpr int kW = waves_of<kPart>();
+  const dim3 grid((ntiles + kW - 1) / kW), block(64 * kW);
+  const size_t lds = sizeof(cx<T>) * stages_of<kPart>() * kSlotsPerStage * kLanes * kW;
   launch_timed(k_step2d<T, kExt, kPart>, grid, block, lds, st, ev0, ev1, args);
 }
 
@@ -1064,7 +1071,6 @@ static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool 
                                   double* ovpart, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int ntiles = zpass ? g.ntiles_z : g.ntiles;
   if (ntiles == 0) return hipSuccess;
-  const dim3 grid((ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
   auto args = step_args<T>(in, out, g, tg0, tg1, tg25, full_factor, ext, ovpart, 1, tile_rows, plain, overlap);
   args.prev = (const cx<T>*)prev;
   args.zpass = zpass ? 1 : 0;
@@ -1074,13 +1080,13 @@ static hipError_t launch_step2d_t(bool plain, bool overlap, int tile_rows, bool 
     args.ntiles = g.ntiles_z;
   }
   if (ext.on()) {
-    if (part == kYFirst) launch_step2d_k<T, true, kYFirst>(grid, block, st, ev0, ev1, args);
-    else if (part == kYSecond) launch_step2d_k<T, true, kYSecond>(grid, block, st, ev0, ev1, args);
-    else launch_step2d_k<T, true, kWhole>(grid, block, st, ev0, ev1, args);
+    if (part == kYFirst) launch_step2d_k<T, true, kYFirst>(ntiles, st, ev0, ev1, args);
+    else if (part == kYSecond) launch_step2d_k<T, true, kYSecond>(ntiles, st, ev0, ev1, args);
+    else launch_step2d_k<T, true, kWhole>(ntiles, st, ev0, ev1, args);
   } else {
-    if (part == kYFirst) launch_step2d_k<T, false, kYFirst>(grid, block, st, ev0, ev1, args);
-    else if (part == kYSecond) launch_step2d_k<T, false, kYSecond>(grid, block, st, ev0, ev1, args);
-    else launch_step2d_k<T, false, kWhole>(grid, block, st, ev0, ev1, args);
+    if (part == kYFirst) launch_step2d_k<T, false, kYFirst>(ntiles, st, ev0, ev1, args);
+    else if (part == kYSecond) launch_step2d_k<T, false, kYSecond>(ntiles, st, ev0, ev1, args);
+    else launch_step2d_k<T, false, kWhole>(ntiles, st, ev0, ev1, args);
   }
   return hipGetLastError();
 }
