@@ -580,18 +580,17 @@ constexpr int kSlotsPerStage = 10;
 // The state between the two launches is the true state (scale 1).
 template <int kPart>
 constexpr int stages_of() { return kPart == kWhole ? 4 : 2; }
-// Wavefronts per workgroup: four for the single launch, two for the split.  The single
-// launch is meant to run one wavefront per SIMD: a workgroup of four lands one wavefront on
-// each SIMD of a CU; with workgroups of two and fewer than 256 registers per lane, the
-// wavefronts of two workgroups can share two SIMDs of a CU and leave the other two idle
-// (complex128 2D: 1.63 against 0.95 ms per step).
-template <int kPart>
-constexpr int waves_of() { return kPart == kWhole ? 4 : 2; }
+// Wavefronts per workgroup.  A workgroup of four lands one wavefront on each SIMD of a CU, so
+// the SIMDs hold equal numbers of wavefronts; with workgroups of two, the wavefronts of two
+// workgroups can share two SIMDs of a CU and leave the other two idle whenever the registers
+// allow two per SIMD (the single launch in complex128 2D: 1.63 against 0.95 ms per step; the
+// split and the complex64 kernels 1.5-3 % slower).
+constexpr int k2DWaves = 4;
 
 // With the y half split, a launch's pipeline leaves LDS for two wavefronts per SIMD: the
 // register budget is set to match (256 per lane).
 template <typename T, bool kExt, int kPart>
-__global__ __launch_bounds__(64 * waves_of<kPart>()) __attribute__((amdgpu_waves_per_eu(kPart == kWhole ? 1 : 2)))
+__global__ __launch_bounds__(64 * k2DWaves) __attribute__((amdgpu_waves_per_eu(kPart == kWhole ? 1 : 2)))
 void k_step2d(StepArgs<T> A) {
   constexpr int kStages = stages_of<kPart>();
   constexpr int kLag = 2 * kStages;          // rows between a row's load and its store
@@ -600,7 +599,7 @@ void k_step2d(StepArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the tile and everything derived from it are wavefront-uniform (scalar registers)
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * waves_of<kPart>() + wv;
+  const int w = xcd_contiguous_block(blockIdx.x, gridDim.x) * k2DWaves + wv;
   if (w >= A.ntiles) return;
   const int lane = threadIdx.x & (kLanes - 1);
   cx<T>* const my = reinterpret_cast<cx<T>*>(smem_raw) + wv * (kStages * kSlotsPerStage * kLanes) + lane;
@@ -1058,9 +1057,8 @@ hipError_t launch_step1d(int dtype, int steps, int split, bool plain, bool overl
 
 template <typename T, bool kExt, int kPart>
 static void launch_step2d_k(int ntiles, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const StepArgs<T>& args) {
-  constexpr int kW = waves_of<kPart>();
-  const dim3 grid((ntiles + kW - 1) / kW), block(64 * kW);
-  const size_t lds = sizeof(cx<T>) * stages_of<kPart>() * kSlotsPerStage * kLanes * kW;
+  const dim3 grid((ntiles + k2DWaves - 1) / k2DWaves), block(64 * k2DWaves);
+  const size_t lds = sizeof(cx<T>) * stages_of<kPart>() * kSlotsPerStage * kLanes * k2DWaves;
   launch_timed(k_step2d<T, kExt, kPart>, grid, block, lds, st, ev0, ev1, args);
 }
 
