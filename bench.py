@@ -60,8 +60,21 @@ PREROLL_S = 0.2        # untimed steps right before each clock start, at least t
 # WRITE_SIZE: x1.000).  Valid only for the kernel sources it was measured on.
 KERNEL_SOURCES = ["paper_1907_12834_amd/csrc/qlg_math.hpp", "paper_1907_12834_amd/csrc/qlg_kernels.hip",
                   "paper_1907_12834_amd/csrc/qlg_internal.hpp"]
-TRAFFIC = {"sources_sha256_16": "", "fetch_scale": 262144.0 / 131088.75, "write_scale": 1.0,
-           "kib": {}}
+TRAFFIC = {"sources_sha256_16": "6983e25ef22ca4b8", "fetch_scale": 262144.0 / 131088.5, "write_scale": 1.0,
+           "kib": {
+               # 1D two-soliton lattice, L = 16384: the two-lane kernel at 2 steps per pass
+               "1d_two_soliton_scattering/c64/interleaved": {"k_step1d_lanes/S2": (740.5, 1280.0)},
+               # 2D 2048^2 vortex pair (bands of rows, the autotuned plan of each)
+               "2d_vortex_pair/c128/interleaved": {"k_step2d/rows76": (365694.0, 655360.0)},
+               # the y half over two launches (sums of the two)
+               "2d_vortex_pair/c64/interleaved": {"k_step2d/rows25/ysplit": (199636.0 + 193654.0,
+                                                                         333441.0 + 330875.0)},
+               "2d_vortex_pair/c64/plain": {"k_step2d/rows38": (201067.0, 330155.0)},
+               # 3D cubes: one step = z pass + y-x pass (sums of the two)
+               "3d_vortex_lines/c64/interleaved": {"k_step3d/rows64": (737418.8 + 743753.5,
+                                                                       1310720.0 + 1312845.1)},
+               "3d_vortex_lines_512/c128/interleaved": {"k_step3d/rows128": (11141332.2 + 11250320.8,
+                                                                             20971520.0 + 20971520.0)}}}
 
 
 def parse():
