@@ -296,9 +296,11 @@ qlg_status qlg_last_kernel_ms(qlg_ctx* ctx, double* ms_host, int64_t* launches_h
  * checkpoint_every steps (>= 1), and for the adjoint workspace.  The workspace
  * holds the input of every self-interaction of one checkpoint segment
  * (checkpoint_every x 4 ndim state copies for the interleaved split,
- * checkpoint_every copies for the plain split) plus two state copies, two
+ * checkpoint_every copies for the plain split) twice, plus two state copies, two
  * complex128 cotangents and small reduction buffers: memory traded for
- * recomputation, so checkpoint_every bounds it. */
+ * recomputation, so checkpoint_every bounds it.  The second set of segment inputs
+ * comes last; it lets the reverse sweep recompute the next segment's inputs on a
+ * second stream while it pulls the cotangent back through the current segment. */
 qlg_status qlg_adjoint_query(const qlg_params* params, int64_t nsteps, int32_t checkpoint_every,
                              size_t* ckpt_bytes, size_t* work_bytes);
 
@@ -319,9 +321,15 @@ qlg_status qlg_objective_grad(qlg_ctx* ctx, int32_t kind, const void* target_dev
 /* Pull lambda back through the nsteps recorded by qlg_forward_record
  * (same nsteps and checkpoint_every): on entry lambda_dev holds dL/d(state at
  * the end), on exit dL/d(state at the start).  dg_host[3] is incremented by
- * dL/d(g0, g1, g2) accumulated over the steps.  work_dev must hold work_bytes
- * from qlg_adjoint_query.  The context's current state is left at the end
- * state of the recorded run.  Synchronises the stream. */
+ * dL/d(g0, g1, g2) accumulated over the steps.  work_dev holds work_bytes from
+ * qlg_adjoint_query, or at least that less the second set of segment inputs
+ * (checkpoint_every x 4 ndim state copies, checkpoint_every for the plain split;
+ * QLG_ERR_ARG below it), in which case the segments are recomputed and pulled back
+ * one after the other on the context's stream.  With the whole workspace the
+ * context makes, on first use, a second stream of default priority (released by
+ * qlg_destroy) for the recompute, ordered against its stream by events; the
+ * results are the same bit for bit.  The context's current state is left at the
+ * end state of the recorded run.  Synchronises the stream. */
 qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t checkpoint_every,
                             const void* ckpt_dev, void* lambda_dev, void* work_dev,
                             size_t work_bytes, double* dg_host);

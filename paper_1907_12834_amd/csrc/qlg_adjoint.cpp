@@ -30,7 +30,9 @@ struct Sizes {
   int64_t nchunks = 0; // 256-site chunks of the per-site kernels
   int64_t nx4 = 0;     // wavefronts of the fused x substeps (56 columns of one row each)
   int64_t nparts = 0;  // dg partials (3 doubles each) of one step's reverse sweep
-  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_xpre = 0, off_acc = 0, work = 0;
+  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_xpre = 0, off_acc = 0;
+  size_t off_zrec2 = 0;  // the second record buffer: the end of the workspace without it
+  size_t work = 0;
 };
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
@@ -82,6 +84,9 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)std::max<int64_t>(s->nparts, 1));
   s->off_xpre = o;  o += up256(sizeof(int) * ((size_t)p->nbatch + 1));   // k_adj_x4's instance prefix
   s->off_acc = o;   o += up256(sizeof(double) * 4);
+  // a second [K][nrec] record buffer, last, so that the next segment's inputs can be recomputed
+  // while the reverse sweep reads the current one's
+  s->off_zrec2 = o; o += up256((size_t)K * (size_t)s->nrec * s->copy);
   s->work = o;
   return QLG_OK;
 }
@@ -177,7 +182,10 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   if (!lambda_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "lambda is NULL");
   if (nsteps == 0) return QLG_OK;
   if (!ckpt_dev || !work_dev) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "checkpoint or work buffer is NULL");
-  if (work_bytes < s.work) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "work buffer too small");
+  if (work_bytes < s.off_zrec2) return qlg::ctx_fail(ctx, QLG_ERR_ARG, "work buffer too small");
+  // with the second record buffer, the recompute of segment i - 1 runs on the context's second
+  // stream while the reverse sweep of segment i runs on its stream
+  const bool overlap = work_bytes >= s.work && s.nck > 1;
   // every per-chunk substep kernel writes 3 partials per chunk of the context's layout, the fused x
   // kernel 3 per wavefront; the workspace region between off_part and off_xpre must hold a step's
   const bool plain = p.split == QLG_SPLIT_PLAIN;
@@ -190,7 +198,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
 
   char* W = (char*)work_dev;
-  char* zrec = W + s.off_zrec;             // zrec[j][r]: input of self-interaction r of step j of the segment
+  // zrec[buf][j][r]: input of self-interaction r of step j of a segment
+  char* zrec[2] = {W + s.off_zrec, W + s.off_zrec2};
   char* ybuf[2] = {W + s.off_y, W + s.off_y + s.copy};
   char* lam[2] = {W + s.off_lam, W + s.off_lam + s.lam};
   double* part = (double*)(W + s.off_part);
@@ -205,64 +214,100 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   // substep k of a step acts along z, y, x in that order (the last axis of each dimension first)
   auto axis_of = [&](int k) { return nd - 1 - k / 4; };
   auto qb_of = [&](int k) { return (k % 4) < 2 ? 1 : 0; };
-  auto zbuf = [&](int64_t j, int r) { return zrec + ((size_t)j * nrec + r) * s.copy; };
+  auto zbuf = [&](int b, int64_t j, int r) { return zrec[b] + ((size_t)j * nrec + r) * s.copy; };
+  auto seg_steps = [&](int64_t seg) { return (int)std::min<int64_t>(K, nsteps - seg * K); };
 
-  hipError_t e = qlg::launch_zero(acc, 4, str);
-  if (e == hipSuccess) e = qlg::launch_lam_layout(true, lambda_dev, lam[0], g, str);
-  if (e == hipSuccess && !plain) e = qlg::launch_x4_prefix(g, xpre, str);
-  if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint setup");
-  int lc = 0;
-  const int64_t nseg = s.nck;
-  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-    const int64_t t0 = seg * K;
-    const int n_in = (int)std::min<int64_t>(K, nsteps - t0);
+  // Forward chain of segment seg from its checkpoint into record buffer b, on stream q:
+  // substep k of step j is "I'_{k-1} then U_k" (the I' of the previous substep, none for the
+  // first one), recording every U input.
+  auto record_segment = [&](int64_t seg, int b, hipStream_t q) -> hipError_t {
+    const int n_in = seg_steps(seg);
     const void* src = (const char*)ckpt_dev + (size_t)seg * s.copy;
     int yb = 0;
-    // Forward chain from the checkpoint: substep k of step j is "I'_{k-1} then U_k"
-    // (the I' of the previous substep, none for the first one), recording every U input.
+    hipError_t e = hipSuccess;
     if (!plain) {
       // interleaved split: link (0, 0) alone, then per step the links (j, 1 .. nsub - 4) one
       // launch each and the four links that apply x factors, (j, nsub - 3 .. nsub - 1) and
       // (j + 1, 0), in one launch (three in the segment's last step)
       const double tg0 = theta_u * p.g0, tg1 = theta_u * p.g1, tg25 = theta_u * p.g2 / 5.0;
-      e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(0, 0), g, -1, 0, true, tg0, tg1, tg25, v.ext, theta_u, str);
+      e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(b, 0, 0), g, -1, 0, true, tg0, tg1, tg25, v.ext, theta_u, q);
       src = ybuf[yb];
       yb ^= 1;
       for (int j = 0; j < n_in && e == hipSuccess; ++j) {
         for (int k = 1; k <= nsub - 4 && e == hipSuccess; ++k) {
-          e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(j, k), g, axis_of(k - 1), qb_of(k - 1), true, tg0, tg1,
-                                tg25, v.ext, theta_u, str);
+          e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(b, j, k), g, axis_of(k - 1), qb_of(k - 1), true, tg0, tg1,
+                                tg25, v.ext, theta_u, q);
           src = ybuf[yb];
           yb ^= 1;
         }
         if (e != hipSuccess) break;
-        void* const r[4] = {zbuf(j, nsub - 3), zbuf(j, nsub - 2), zbuf(j, nsub - 1),
-                            j + 1 < n_in ? zbuf(j + 1, 0) : nullptr};
-        e = qlg::launch_chain_x4(dt, src, ybuf[yb], r, g, xpre, (int)s.nx4, tg0, tg1, tg25, v.ext, theta_u, str);
+        void* const r[4] = {zbuf(b, j, nsub - 3), zbuf(b, j, nsub - 2), zbuf(b, j, nsub - 1),
+                            j + 1 < n_in ? zbuf(b, j + 1, 0) : nullptr};
+        e = qlg::launch_chain_x4(dt, src, ybuf[yb], r, g, xpre, (int)s.nx4, tg0, tg1, tg25, v.ext, theta_u, q);
         src = ybuf[yb];
         yb ^= 1;
       }
-      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+      return e;
     }
-    for (int j = 0; j < n_in && plain; ++j) {
+    for (int j = 0; j < n_in; ++j) {
       for (int k = 0; k < nsub; ++k) {
         const int kp = k == 0 ? nsub - 1 : k - 1;
         const bool first = j == 0 && k == 0;
-        const bool has_u = !plain || k == 0;
-        if (j == n_in - 1 && k > (plain ? 0 : nsub - 1)) break;   // later links feed nothing recorded
-        e = qlg::launch_chain(dt, src, ybuf[yb], has_u ? zbuf(j, plain ? 0 : k) : nullptr, g,
-                              first ? -1 : axis_of(kp), qb_of(kp), has_u, theta_u * p.g0, theta_u * p.g1,
-                              theta_u * p.g2 / 5.0, v.ext, theta_u, str);
-        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+        const bool has_u = k == 0;
+        if (j == n_in - 1 && k > 0) break;   // later links feed nothing recorded
+        e = qlg::launch_chain(dt, src, ybuf[yb], has_u ? zbuf(b, j, 0) : nullptr, g, first ? -1 : axis_of(kp),
+                              qb_of(kp), has_u, theta_u * p.g0, theta_u * p.g1, theta_u * p.g2 / 5.0, v.ext,
+                              theta_u, q);
+        if (e != hipSuccess) return e;
         src = ybuf[yb];
         yb ^= 1;
       }
+    }
+    return e;
+  };
+
+  hipError_t e = qlg::launch_zero(acc, 4, str);
+  if (e == hipSuccess) e = qlg::launch_lam_layout(true, lambda_dev, lam[0], g, str);
+  if (e == hipSuccess && !plain) e = qlg::launch_x4_prefix(g, xpre, str);
+  if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint setup");
+  hipStream_t aux = nullptr;
+  hipEvent_t* ev = nullptr;   // [0], [1]: records of buffer 0, 1 ready; [2]: a sweep done; [3]: setup done
+  if (overlap) {
+    e = qlg::ctx_aux(ctx, &aux, &ev);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], str);
+    if (e == hipSuccess) e = hipStreamWaitEvent(aux, ev[3], 0);   // the chain reads xpre
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint second stream");
+  }
+  int lc = 0;
+  const int64_t nseg = s.nck;
+  if (overlap) {
+    e = record_segment(nseg - 1, 0, aux);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], aux);
+    if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+  }
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int n_in = seg_steps(seg);
+    int b = 0;
+    if (overlap) {
+      b = (int)((nseg - 1 - seg) & 1);
+      if (seg > 0) {
+        // the next segment's records go to the other buffer, once the sweep that read it ended
+        if (seg + 1 < nseg) e = hipStreamWaitEvent(aux, ev[2], 0);
+        if (e == hipSuccess) e = record_segment(seg - 1, 1 - b, aux);
+        if (e == hipSuccess) e = hipEventRecord(ev[1 - b], aux);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+      }
+      e = hipStreamWaitEvent(str, ev[b], 0);
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint stream order");
+    } else {
+      e = record_segment(seg, 0, str);
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
     }
     for (int j = n_in - 1; j >= 0; --j) {
       if (!plain) {
         // the step's last four substeps (along x) in one kernel, their dg partials after those
         // of the nsub - 4 per-chunk substeps
-        const void* zx[4] = {zbuf(j, nsub - 1), zbuf(j, nsub - 2), zbuf(j, nsub - 3), zbuf(j, nsub - 4)};
+        const void* zx[4] = {zbuf(b, j, nsub - 1), zbuf(b, j, nsub - 2), zbuf(b, j, nsub - 3), zbuf(b, j, nsub - 4)};
         e = qlg::launch_adj_x4(dt, zx, lam[lc], lam[1 - lc], g, xpre, (int)s.nx4, theta_u, p.g0, p.g1, p.g2,
                                v.ext, part + (size_t)3 * (nsub - 4) * nchunks, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint x substeps kernel");
@@ -274,19 +319,23 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint kinetic kernel");
         } else {
           // kinetic pull-back and self-interaction VJP of substep k in one kernel
-          e = qlg::launch_sub_adj(dt, zbuf(j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
+          e = qlg::launch_sub_adj(dt, zbuf(b, j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
                                   p.g1, p.g2, v.ext, part + (size_t)3 * k * nchunks, str);
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep kernel");
         }
         lc = 1 - lc;
       }
       if (plain) {
-        e = qlg::launch_sub_vjp(dt, zbuf(j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
+        e = qlg::launch_sub_vjp(dt, zbuf(b, j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
       } else {
         e = qlg::launch_dg_accumulate(part, (int)s.nparts, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint parameter-gradient reduction");
       }
+    }
+    if (overlap && seg > 1) {
+      e = hipEventRecord(ev[2], str);   // the sweep of this segment has read buffer b
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint stream order");
     }
   }
   e = qlg::launch_lam_layout(false, lam[lc], lambda_dev, g, str);

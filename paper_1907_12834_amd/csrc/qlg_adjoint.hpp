@@ -20,6 +20,9 @@ struct CtxView {
 };
 
 CtxView ctx_view(qlg_ctx* c);
+// The context's second stream (non-blocking, default priority) and four events for ordering
+// work between it and the context's stream; made on first use, released by qlg_destroy.
+hipError_t ctx_aux(qlg_ctx* c, hipStream_t* aux, hipEvent_t** ev);
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg);
 qlg_status ctx_step(qlg_ctx* c, int64_t nsteps);
 qlg_status ctx_hip(qlg_ctx* c, hipError_t e, const char* what);

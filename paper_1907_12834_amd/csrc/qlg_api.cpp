@@ -173,6 +173,9 @@ struct qlg_ctx {
   std::string err;
   // graphs keyed by (nsteps, start copy)
   std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+  // the adjoint's second stream (default priority) and its events, made on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -565,6 +568,14 @@ void qlg_destroy(qlg_ctx* c) {
   if (!c) return;
   drop_graphs(c);
   for (auto ev : c->ev) (void)hipEventDestroy(ev);
+  if (c->aux) {
+    // the adjoint orders every kernel of the second stream before the context's stream's end,
+    // but a failed call may have left some queued
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (auto ev : c->aux_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (c->static_dev >= 0) {
     // work still queued on the context's stream may use the array: let it finish first
     (void)hipStreamSynchronize(c->stream);
@@ -1014,6 +1025,25 @@ CtxView ctx_view(qlg_ctx* c) {
   v.res = c->sc(c->S.obs_res);
   v.ext = c->ext;
   return v;
+}
+hipError_t ctx_aux(qlg_ctx* c, hipStream_t* aux, hipEvent_t** ev) {
+  if (!c->aux) {
+    hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      c->aux = nullptr;
+      return e;
+    }
+    for (auto& x : c->aux_ev) {
+      e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        x = nullptr;
+        return e;
+      }
+    }
+  }
+  *aux = c->aux;
+  *ev = c->aux_ev;
+  return hipSuccess;
 }
 qlg_status ctx_fail(qlg_ctx* c, qlg_status s, const char* msg) { return fail(c, s, msg); }
 qlg_status ctx_step(qlg_ctx* c, int64_t nsteps) { return qlg_step(c, nsteps); }

@@ -421,3 +421,41 @@ def test_batched_2d_adjoint_matches_single_and_oracle(dtype):
     L0, gp0, gg0 = oracle_grad(f[1], G, eps, nsteps)
     tol = 1e-10 if dtype == "c128" else 1e-4
     assert rel(gp1, gp0.reshape(gp1.shape)) <= tol, rel(gp1, gp0.reshape(gp1.shape))
+
+
+@pytest.mark.parametrize("split", ["interleaved", "plain"])
+def test_adjoint_overlapped_recompute_matches_sequential(split):
+    """With the whole workspace the reverse sweep recomputes segment i - 1's self-interaction
+    inputs on the context's second stream while it pulls lambda back through segment i; with the
+    workspace less its second set of segment inputs it does one after the other on the context's
+    stream.  The same kernels compute the same numbers: bit-identical cotangent and dL/dg (four
+    segments, the last one ragged), and a workspace smaller still is refused."""
+    import ctypes
+    from paper_1907_12834_amd.qlg import Lattice, lib, _device_bytes
+    shape = (20, 24)
+    psi0 = qi.random_field(shape, seed=63, scale=0.4)
+    eps, nsteps, K = 0.3, 11, 3
+    lat = Lattice(2, [shape[1]], [shape[0]], g=G, eps=eps, dtype="c128", split=split)
+    lat.set_psi([torch.from_numpy(psi0)])
+    ck = lat.forward_record(nsteps, K)
+    val, lam0, dg0 = lat.objective_grad("energy")
+    ckb, wk = lat.adjoint_sizes(nsteps, K)
+    copy = ckb // -(-nsteps // K)
+    nrec = 8 if split == "interleaved" else 1
+    second = (K * nrec * copy + 255) // 256 * 256
+    res = []
+    for work_bytes in (wk, wk - second):
+        lam = lam0.clone()
+        work = _device_bytes(work_bytes, lat.device)
+        dg = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+        st = lib().qlg_adjoint_step(lat.ctx, nsteps, K, ck.data_ptr(), lam.data_ptr(), work.data_ptr(),
+                                    work_bytes, dg)
+        assert st == 0, lib().qlg_last_error(lat.ctx)
+        res.append((lam.cpu().numpy(), list(dg)))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+    lam = lam0.clone()
+    work = _device_bytes(wk - second - 256, lat.device)
+    dg = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib().qlg_adjoint_step(lat.ctx, nsteps, K, ck.data_ptr(), lam.data_ptr(), work.data_ptr(),
+                                  wk - second - 256, dg) == 1
