@@ -165,6 +165,7 @@ struct qlg_ctx {
   qlg::ExtPot ext;               // external potential (caller's device array) and mu
   bool tuned = false;
   int static_dev = -1;            // device whose static scratch this context uses, or -1
+  int device = 0;                 // the device current at qlg_init (the buffers' device)
   // bookkeeping
   int64_t step_count = 0;
   bool has_overlap = false;
@@ -475,6 +476,10 @@ static qlg_status init_ctx(const qlg_params* p, void* state_dev, size_t state_by
   qlg_ctx* c = new (std::nothrow) qlg_ctx();
   if (!c) return QLG_ERR_OOM;
   c->static_dev = static_dev;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return QLG_ERR_DEVICE;
+  }
   c->p = *p;
   c->nx.assign(p->nx, p->nx + p->nbatch);
   if (p->ndim >= 2) c->ny.assign(p->ny, p->ny + p->nbatch);
@@ -1028,18 +1033,26 @@ CtxView ctx_view(qlg_ctx* c) {
 }
 hipError_t ctx_aux(qlg_ctx* c, hipStream_t* aux, hipEvent_t** ev) {
   if (!c->aux) {
-    hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      c->aux = nullptr;
-      return e;
-    }
+    // on the context's device, whichever device is current
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != c->device) e = hipSetDevice(c->device);
+    if (e != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e != hipSuccess) c->aux = nullptr;
     for (auto& x : c->aux_ev) {
+      if (e != hipSuccess) break;
       e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
-      if (e != hipSuccess) {
-        x = nullptr;
-        return e;
-      }
+      if (e != hipSuccess) x = nullptr;
     }
+    if (e != hipSuccess) {   // leave nothing half made
+      for (auto& x : c->aux_ev)
+        if (x) (void)hipEventDestroy(x), x = nullptr;
+      if (c->aux) (void)hipStreamDestroy(c->aux), c->aux = nullptr;
+    }
+    const hipError_t r = cur != c->device ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return e;
+    if (r != hipSuccess) return r;
   }
   *aux = c->aux;
   *ev = c->aux_ev;
