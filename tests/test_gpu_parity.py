@@ -356,6 +356,30 @@ def test_vortex_pair_2048_light_cone_samples(dtype):
         assert rel_l2(sub, ref) <= (1e-12 if dtype == "c128" else 1e-4), (cy, cx, rel_l2(sub, ref))
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_spin_texture_2048_light_cone_samples(dtype):
+    """The 2048^2 workload with a seeded complex Gaussian spinor of amplitude 0.05 added to every
+    component (the adjoint's spin-texture recipe): m = +-1 are populated and F != 0 at every site,
+    so the spin rotation of the self-interaction acts everywhere (the vortex pair alone keeps
+    F = 0).  Autotuned configuration, 20 steps, light-cone windows vs the oracle."""
+    w = qi.vortex_pair_2d_2048()
+    psi = w.psi[0] + qi.random_field((2048, 2048), seed=79, scale=0.05)
+    nsteps = 20
+    lat = lattice(2, [2048], [2048], g=w.g, eps=w.eps, dtype=dtype)
+    lat.autotune()
+    lat.set_psi([torch.from_numpy(psi)])
+    lat.step(nsteps)
+    got = lat.get_psi()[0].cpu().numpy()
+    for cy, cx in ((1024, 1024 - 64), (300, 1700), (2047, 0)):
+        ref = light_cone_oracle_2d(psi, cy, cx, nsteps, w.eps, w.g, half_out=2)
+        fz = 2 * (np.abs(ref[0]) ** 2 - np.abs(ref[4]) ** 2) + np.abs(ref[1]) ** 2 - np.abs(ref[3]) ** 2
+        fp = 2 * np.conj(ref[0]) * ref[1] + 6 ** 0.5 * (np.conj(ref[1]) * ref[2] + np.conj(ref[2]) * ref[3]) \
+            + 2 * np.conj(ref[3]) * ref[4]
+        assert np.min(np.sqrt(fz ** 2 + np.abs(fp) ** 2)) > 1e-3     # the spin factor is not the identity
+        sub = got[:, (np.arange(cy - 2, cy + 3) % 2048)[:, None], (np.arange(cx - 2, cx + 3) % 2048)[None, :]]
+        assert rel_l2(sub, ref) <= TOL[dtype], (cy, cx, rel_l2(sub, ref))
+
+
 # ---------------------------------------------------------------------------
 # Batched, graphs, autotune
 # ---------------------------------------------------------------------------
