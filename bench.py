@@ -12,7 +12,8 @@ lattice; `value` is sites * steps / wall time of the timed region, inputs
 resident in HBM.  The observables are recorded on the device every 100 steps
 and read back and decoded once, at the end of the timed region.  Every
 hipGraph the timed region replays is captured before the clock starts.
-`secondary` repeats the run in complex64.  Other workloads (`--workload`):
+`secondary` repeats the run in complex64, `spin_texture` on the field plus a
+seeded random spinor (F != 0 at every site).  Other workloads (`--workload`):
 the 1D two-soliton scattering lattice (L = 16384) and the 3D vortex-line
 cubes.
 
@@ -37,7 +38,9 @@ sys.path.insert(0, ROOT)
 # qlg_math.hpp; the three sincos, two reciprocal square roots and two
 # reciprocals of each self-interaction are not counted.  One U: coefficients 178
 # (psi, n, F, the phases and the rotation's blocks), then 288 per 5-vector a and b
-# (singlet 84, frame phases 24, d^T 58, diagonal 30, d 58, recombination 34).
+# (singlet 84, frame phases 24, d^T 58, diagonal 30, d 58, recombination 34), the count of
+# the FP64 form; the FP32 form adds the singlet correction to x in a separate step (10 more
+# per 5-vector, not counted).
 FLOPS_U = 754          # one application of U (coefficients 178 + 2 x 288 per 5-vector)
 FLOPS_IPRIME = 85      # one I' (two collides 2 x 40 + its share of the exact 1/256 per step, 5)
 FLOPS_PER_SITE_STEP = {d: 4 * d * (FLOPS_U + FLOPS_IPRIME) for d in (1, 2, 3)}
@@ -102,6 +105,9 @@ def parse():
                     help="steps of the forward+adjoint vs forward comparison (0 = skip)")
     ap.add_argument("--trap-steps", type=int, default=4000,
                     help="steps of the same workload with a harmonic trap and chemical potential (0 = skip)")
+    ap.add_argument("--texture-steps", type=int, default=2000,
+                    help="2D and 3D: steps of the same workload with a seeded random spinor of amplitude "
+                         "0.05 added to every component, so that F != 0 at every site (0 = skip)")
     ap.add_argument("--diag-reps", type=int, default=50,
                     help="launches of the per-site field and vorticity kernels timed on the workload's "
                          "lattice (0 = skip)")
@@ -161,13 +167,23 @@ def trap_potential(w, ndim):
     return omega ** 2 * r2 / 4, 0.5
 
 
+def spin_texture(w, ndim):
+    """The workload's field plus a seeded complex Gaussian spinor of amplitude 0.05 in every
+    component: m = +-1 are populated and F != 0 at every site, so the spin rotation of the
+    self-interaction acts everywhere (the vortex states keep F = 0 for the whole run)."""
+    import qlg_inputs as qi
+    return w.psi[0] + qi.random_field(tuple(workload_shape(w, ndim)), seed=79, scale=0.05)
+
+
 def measure(dtype, steps, warmup, workload="1d_two_soliton_scattering", split="interleaved", trap=False,
-            plan=None):
-    """Run the workload (with a harmonic trap and mu if `trap`); return rate, wall time,
-    per-launch kernel time and plan."""
+            plan=None, texture=False):
+    """Run the workload (with a harmonic trap and mu if `trap`, on the spin texture if `texture`);
+    return rate, wall time, per-launch kernel time and plan."""
     import torch
 
     w = workload_input(workload, steps)
+    if texture:
+        w.psi[0] = spin_texture(w, WORKLOADS[workload][0])
     ndim = WORKLOADS[workload][0]
     L = int(np.prod(workload_shape(w, ndim)))   # sites
     lat = workload_lattice(w, ndim, dtype, split)
@@ -468,6 +484,17 @@ def main():
                      (kern_ms / S) if kern_ms > 0 and mt["kern_ms"] > 0 else None,
                      "norm_drift": mt["drift"]}
         progress("potential: %.4g site-updates/s" % mt["value"])
+    texture = None
+    if args.texture_steps > 0 and ndim >= 2:
+        mx = measure(args.dtype, args.texture_steps, min(args.warmup, 200), args.workload, args.split,
+                     plan=args.plan, texture=True)
+        texture = {"what": "the same workload plus a seeded random spinor of amplitude 0.05 in every "
+                           "component (F != 0 at every site: the spin rotation acts everywhere)",
+                   "steps": args.texture_steps, "value": mx["value"], "unit": "site-updates/s",
+                   "kernel_ms_avg": mx["kern_ms"], "plan": mx["tuning"],
+                   "kernel_time_vs_workload": mx["kern_ms"] / kern_ms if kern_ms > 0 and mx["kern_ms"] > 0
+                   else None, "norm_drift": mx["drift"]}
+        progress("spin texture: %.4g site-updates/s" % mx["value"])
     cpu = cpu_baseline(w, args.cpu_steps if ndim == 1 else max(1, args.cpu_steps // 500), ndim) \
         if args.cpu_steps > 0 else None
 
@@ -517,6 +544,7 @@ def main():
         "repeats": m["repeats"],
         "value_over_repeats_median": m["value"] / m["repeats"]["median"] if m["repeats"] else None,
         "secondary": secondary,
+        "spin_texture": texture,
         "batched": batched,
         "adjoint": adjoint,
         "diagnostics": diag,
