@@ -464,9 +464,17 @@ class Lattice:
                     "qlg_objective_grad")
         return val.value, lam, list(dg)
 
-    def adjoint_step(self, nsteps: int, checkpoint_every: int, ckpt: torch.Tensor, lam: torch.Tensor):
-        """Pull lam (complex128 canonical qubits) back over the recorded run; returns dL/dg."""
-        _, wk = self.adjoint_sizes(nsteps, checkpoint_every)
+    def adjoint_step(self, nsteps: int, checkpoint_every: int, ckpt: torch.Tensor, lam: torch.Tensor,
+                     overlap: bool = True):
+        """Pull lam (complex128 canonical qubits) back over the recorded run; returns dL/dg.
+        overlap=False passes the workspace without its second set of segment inputs
+        (checkpoint_every x 4 ndim state copies, checkpoint_every for the plain split): less device
+        memory, the segment recompute then runs on the context's stream between the sweeps."""
+        ck, wk = self.adjoint_sizes(nsteps, checkpoint_every)
+        if not overlap and nsteps > 0:
+            copy = ck // -(-int(nsteps) // int(checkpoint_every))
+            nrec = 1 if self.params.split == 1 else 4 * self.params.ndim
+            wk -= (int(checkpoint_every) * nrec * copy + 255) // 256 * 256
         work = _device_bytes(wk, self.device)
         dg = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
         lam = lam.contiguous()

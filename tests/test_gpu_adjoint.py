@@ -452,8 +452,13 @@ def test_adjoint_overlapped_recompute_matches_sequential(split):
                                     work_bytes, dg)
         assert st == 0, lib().qlg_last_error(lat.ctx)
         res.append((lam.cpu().numpy(), list(dg)))
-    assert np.array_equal(res[0][0], res[1][0])
-    assert res[0][1] == res[1][1]
+    for overlap in (True, False):   # the binding's two workspace sizes
+        lam = lam0.clone()
+        dg = lat.adjoint_step(nsteps, K, ck, lam, overlap=overlap)
+        res.append((lam.cpu().numpy(), dg))
+    for r in res[1:]:
+        assert np.array_equal(res[0][0], r[0])
+        assert res[0][1] == r[1]
     lam = lam0.clone()
     work = _device_bytes(wk - second - 256, lat.device)
     dg = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
