@@ -3,14 +3,15 @@
 //
 // Reverse sweep over a recorded run of nsteps with a checkpoint every K steps:
 //   for each segment, last to first:
-//     recompute the segment's step states from its checkpoint (fused step kernel);
-//     for each step of the segment, last to first:
-//       recompute the inputs of the step's self-interaction substeps (per-substep kernels);
-//       for each substep k, last to first:
-//         lambda <- I'_k^H lambda          (exact inverse of the unitary kinetic factor)
-//         lambda <- (dU/dz)^H lambda       (FP64 Jacobian at the recomputed substep input)
+//     recompute, from the segment's checkpoint, the input of every self-interaction substep of
+//     its steps (a chain of per-substep kernels, the four x substeps of a step in one);
+//     for each step of the segment, last to first, and each substep k, last to first:
+//       lambda <- I'_k^H lambda          (exact inverse of the unitary kinetic factor)
+//       lambda <- (dU/dz)^H lambda       (FP64 Jacobian at the recomputed substep input)
 //   (plain split: one U with theta = eps^2 before the I' list, so only the step input is needed.)
-// dL/dg accumulates in FP64 on the device in a fixed order.
+// With two record buffers the recompute of the segment before runs on the context's second
+// stream while the sweep pulls lambda back through the current one.  dL/dg accumulates in FP64
+// on the device in a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -275,7 +276,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   if (overlap) {
     e = qlg::ctx_aux(ctx, &aux, &ev);
     if (e == hipSuccess) e = hipEventRecord(ev[3], str);
-    if (e == hipSuccess) e = hipStreamWaitEvent(aux, ev[3], 0);   // the chain reads xpre
+    // the recompute reads xpre and the checkpoints, written on the context's stream
+    if (e == hipSuccess) e = hipStreamWaitEvent(aux, ev[3], 0);
     if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint second stream");
   }
   int lc = 0;
