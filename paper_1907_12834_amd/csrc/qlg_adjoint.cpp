@@ -38,6 +38,9 @@ struct Sizes {
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
+// dg partials per chunk of the fused per-site substep kernel (one per wavefront)
+constexpr int64_t kSubAdjParts = qlg::kChunk / qlg::kLanes;
+
 // wavefronts of k_adj_x4: ceil(nx / 56) per row of each instance
 int64_t adjoint_x4_waves(const qlg_params* p) {
   int64_t n = 0;
@@ -73,9 +76,11 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   const int64_t nchunks = adjoint_chunks(p);
   s->nchunks = nchunks;
   s->nx4 = adjoint_x4_waves(p);
-  // a step's dg partials: per chunk for the substeps of one launch each (all of the plain split;
-  // the z and y ones of the interleaved split), then per wavefront for the four fused x substeps
-  s->nparts = p->split == QLG_SPLIT_PLAIN ? s->nsub * nchunks : (s->nsub - 4) * nchunks + s->nx4;
+  // a step's dg partials: per chunk for the substeps of the plain split, per wavefront (four per
+  // chunk) for the z and y substeps of the interleaved split, then per wavefront for its four
+  // fused x substeps
+  s->nparts = p->split == QLG_SPLIT_PLAIN ? s->nsub * nchunks
+                                         : (s->nsub - 4) * kSubAdjParts * nchunks + s->nx4;
   size_t o = 0;
   // inputs of every self-interaction of one checkpoint segment: [K][nrec] state copies
   s->off_zrec = o;  o += up256((size_t)K * (size_t)s->nrec * s->copy);
@@ -191,7 +196,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   // kernel 3 per wavefront; the workspace region between off_part and off_xpre must hold a step's
   const bool plain = p.split == QLG_SPLIT_PLAIN;
   const int64_t nparts_ctx = plain ? (int64_t)s.nsub * v.geom.nchunks
-                                   : (int64_t)(s.nsub - 4) * v.geom.nchunks + s.nx4;
+                                   : (int64_t)(s.nsub - 4) * kSubAdjParts * v.geom.nchunks + s.nx4;
   if (v.geom.nchunks != s.nchunks || (size_t)3 * std::max<int64_t>(nparts_ctx, 1) * sizeof(double) >
                                          s.off_xpre - s.off_part)
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "adjoint partials exceed their workspace region");
@@ -311,7 +316,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         // of the nsub - 4 per-chunk substeps
         const void* zx[4] = {zbuf(b, j, nsub - 1), zbuf(b, j, nsub - 2), zbuf(b, j, nsub - 3), zbuf(b, j, nsub - 4)};
         e = qlg::launch_adj_x4(dt, zx, lam[lc], lam[1 - lc], g, xpre, (int)s.nx4, theta_u, p.g0, p.g1, p.g2,
-                               v.ext, part + (size_t)3 * (nsub - 4) * nchunks, str);
+                               v.ext, part + (size_t)3 * (nsub - 4) * kSubAdjParts * nchunks, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint x substeps kernel");
         lc = 1 - lc;
       }
@@ -322,7 +327,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         } else {
           // kinetic pull-back and self-interaction VJP of substep k in one kernel
           e = qlg::launch_sub_adj(dt, zbuf(b, j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
-                                  p.g1, p.g2, v.ext, part + (size_t)3 * k * nchunks, str);
+                                  p.g1, p.g2, v.ext, part + (size_t)3 * k * kSubAdjParts * nchunks, str);
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep kernel");
         }
         lc = 1 - lc;

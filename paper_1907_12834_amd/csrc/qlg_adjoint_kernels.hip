@@ -37,9 +37,9 @@ __device__ __forceinline__ int chunk_of_block(int b, int nblocks) {
   return x * per + (x < extra ? x : extra) + l;
 }
 
-__device__ __forceinline__ Site site_here(const LaunchGeom& g) {
+// This thread's site in chunk c (thread t of the workgroup takes site t of the chunk).
+__device__ __forceinline__ Site site_of_chunk(const LaunchGeom& g, int c) {
   Site r;
-  const int c = chunk_of_block(blockIdx.x, gridDim.x);
   r.c = c;
   r.d = g.inst[g.chunk2inst[c]];
   r.s = (c - r.d.chunk_begin) * kChunk + threadIdx.x;
@@ -48,6 +48,10 @@ __device__ __forceinline__ Site site_here(const LaunchGeom& g) {
   r.y = r.ok ? (r.s / r.d.nx) % r.d.ny : 0;
   r.z = r.ok ? r.s / (r.d.nx * r.d.ny) : 0;
   return r;
+}
+
+__device__ __forceinline__ Site site_here(const LaunchGeom& g) {
+  return site_of_chunk(g, chunk_of_block(blockIdx.x, gridDim.x));
 }
 
 // site index of the neighbour at offset dir (+1 / -1) along axis (0 = x, 1 = y, 2 = z), periodic
@@ -341,15 +345,28 @@ __global__ __launch_bounds__(kChunk) void k_sub_vjp(const cx<T>* __restrict__ z,
 
 // One adjoint substep of the interleaved split, fused: lambda_out = (dU)^H I'^H lambda_in,
 // the kinetic pull-back recomputed per site from lambda_in at x-1, x, x+1 along `axis`,
-// then the FP64 self-interaction VJP at the substep input z; dg partials per chunk.
+// then the FP64 self-interaction VJP at the substep input z; dg partials per wavefront.
+// Workgroups of one wavefront (a quarter of a chunk): a wavefront that finishes frees its
+// SIMD slot for the next at once, so the two wavefronts of a SIMD drift apart and one loads
+// while the other computes.  (Workgroups of a whole chunk, summed in LDS behind a barrier,
+// started and ended four wavefronts together, which kept the loads and the arithmetic of a
+// SIMD's wavefronts in step.)
 template <typename T>
-__global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
+__global__ __launch_bounds__(kLanes) void k_sub_adj(const cx<T>* __restrict__ z,
                                                    const cx<double>* __restrict__ lin,
                                                    cx<double>* __restrict__ lout, LaunchGeom g, int axis, int qb,
                                                    double theta, double g0, double g1, double g2,
                                                    const double* __restrict__ pot, double mu,
                                                    double* __restrict__ part) {
-  const Site r = site_here(g);
+  constexpr int kWaves = kChunk / kLanes;
+  // wavefront unit u: quarter u % 4 of chunk u / 4, units of one XCD consecutive
+  const int u = chunk_of_block(blockIdx.x, gridDim.x);
+  Site r = site_of_chunk(g, u / kWaves);
+  r.s += (u % kWaves) * kLanes;   // site_of_chunk counts threadIdx.x from the chunk's start
+  r.ok = r.s < r.d.sites;
+  r.x = r.ok ? r.s % r.d.nx : 0;
+  r.y = r.ok ? (r.s / r.d.nx) % r.d.ny : 0;
+  r.z = r.ok ? r.s / (r.d.nx * r.d.ny) : 0;
   double dg[3] = {0.0, 0.0, 0.0};
   if (r.ok) {
     cx<double> la[5], lb[5];
@@ -359,7 +376,16 @@ __global__ __launch_bounds__(kChunk) void k_sub_adj(const cx<T>* __restrict__ z,
     potential_vjp(a, b, la, lb, theta, g0, g1, g2, dg, ext_here(r, pot, mu, theta));
     store_site(lout, r.d, r.s, la, lb);
   }
-  block_sum3(dg[0], dg[1], dg[2], part + 3 * (int64_t)r.c);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dg[k] += __shfl_xor(dg[k], o, kLanes);
+  }
+  if (threadIdx.x == 0) {
+    part[3 * (int64_t)u] = dg[0];
+    part[3 * (int64_t)u + 1] = dg[1];
+    part[3 * (int64_t)u + 2] = dg[2];
+  }
 }
 
 // The four adjoint substeps along x of a step, fused: for k = k0 + 3, ..., k0 (qubits a, a, b, b),
@@ -503,19 +529,34 @@ __global__ void k_x4_prefix(LaunchGeom g, int* __restrict__ xpre) {
 // acc[0..2] += sum over chunks of part (single block, fixed order).  Unrolling
 // issues the loads of eight chunks ahead of their additions; each thread still
 // adds its chunks in increasing order.
-__global__ __launch_bounds__(kChunk) void k_dg_accumulate(const double* __restrict__ part, int nchunks,
-                                                         double* __restrict__ acc) {
+// One workgroup of 1024 threads: thread t sums the partials t, t + 1024, ... (a serial chain of
+// a few dozen loads each), then the 16 wavefront sums are added in order.
+constexpr int kDgThreads = 1024;
+__global__ __launch_bounds__(kDgThreads) void k_dg_accumulate(const double* __restrict__ part, int nparts,
+                                                            double* __restrict__ acc) {
+  constexpr int kW = kDgThreads / kLanes;
+  __shared__ double red[3][kW];
+  const int lane = threadIdx.x & (kLanes - 1), wv = threadIdx.x >> 6;
   double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll 8
-  for (int c = threadIdx.x; c < nchunks; c += kChunk) {
+  for (int c = threadIdx.x; c < nparts; c += kDgThreads) {
     v[0] += part[3 * c];
     v[1] += part[3 * c + 1];
     v[2] += part[3 * c + 2];
   }
-  __shared__ double tot[3];
-  block_sum3(v[0], v[1], v[2], tot);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, kLanes);
+    if (lane == 0) red[k][wv] = v[k];
+  }
   __syncthreads();
-  if (threadIdx.x < 3) acc[threadIdx.x] += tot[threadIdx.x];
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kW; ++j) t += red[threadIdx.x][j];
+    acc[threadIdx.x] += t;
+  }
 }
 
 // Energy objective: lambda_a = lambda_b = 2 dE/dpsi* written in the canonical
@@ -688,7 +729,7 @@ hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom&
                        g2, ext.V, ext.mu, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, (const double*)part, g.nchunks, acc);
+  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kDgThreads), 0, st, (const double*)part, g.nchunks, acc);
   return hipGetLastError();
 }
 
@@ -696,11 +737,12 @@ hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* la
                           int qb, double theta, double g0, double g1, double g2, const ExtPot& ext, double* part,
                           hipStream_t st) {
   if (g.nchunks == 0) return hipSuccess;
+  const dim3 grid(g.nchunks * (kChunk / kLanes)), block(kLanes);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_sub_adj<float>, QLG_GRID, (const cx<float>*)z, (const cx<double>*)lam_in,
+    hipLaunchKernelGGL(k_sub_adj<float>, grid, block, 0, st, (const cx<float>*)z, (const cx<double>*)lam_in,
                        (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, ext.V, ext.mu, part);
   else
-    hipLaunchKernelGGL(k_sub_adj<double>, QLG_GRID, (const cx<double>*)z, (const cx<double>*)lam_in,
+    hipLaunchKernelGGL(k_sub_adj<double>, grid, block, 0, st, (const cx<double>*)z, (const cx<double>*)lam_in,
                        (cx<double>*)lam_out, g, axis, qb, theta, g0, g1, g2, ext.V, ext.mu, part);
   return hipGetLastError();
 }
@@ -746,7 +788,7 @@ hipError_t launch_adj_x4(int dtype, const void* const z[4], const void* lam_in, 
 }
 
 hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kChunk), 0, st, part, nparts, acc);
+  hipLaunchKernelGGL(k_dg_accumulate, dim3(1), dim3(kDgThreads), 0, st, part, nparts, acc);
   return hipGetLastError();
 }
 

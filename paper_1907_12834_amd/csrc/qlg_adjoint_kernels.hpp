@@ -16,7 +16,8 @@ hipError_t launch_sub_iprime_adj(const void* in, void* out, const LaunchGeom& g,
 hipError_t launch_sub_vjp(int dtype, const void* z, void* lam, const LaunchGeom& g, double theta, double g0,
                           double g1, double g2, const ExtPot& ext, double* part, double* acc, hipStream_t st);
 // Fused adjoint substep of the interleaved split: lam_out = (dU)^H I'_{axis,qb}^H lam_in at the
-// substep input z; per-chunk dg partials into part[nchunks][3] (no accumulation).
+// substep input z; dg partials per wavefront (a quarter of a chunk) into part[4 nchunks][3]
+// (no accumulation).
 hipError_t launch_sub_adj(int dtype, const void* z, const void* lam_in, void* lam_out, const LaunchGeom& g, int axis,
                           int qb, double theta, double g0, double g1, double g2, const ExtPot& ext, double* part,
                           hipStream_t st);

@@ -113,10 +113,10 @@ def _up256(v):
 ])
 @pytest.mark.parametrize("split", [0, 1])
 def test_adjoint_workspace_covers_kernel_partials(Q, ndim, nx, ny, nz, split):
-    """The reverse sweep's per-chunk substep kernels write 3 FP64 partials per 256-site chunk of
-    every instance for each substep they take (all 4 ndim of the plain split; the 4 (ndim - 1)
-    along z and y of the interleaved one), the kernel of the four fused x substeps 3 per
-    wavefront of 56 columns of one row; the workspace qlg_adjoint_query reports must hold them
+    """The reverse sweep's per-site substep kernels write 3 FP64 partials per 256-site chunk of
+    every instance for each substep of the plain split, and per 64-site wavefront (four per
+    chunk) for the 4 (ndim - 1) substeps along z and y of the interleaved one; the kernel of the
+    four fused x substeps 3 per wavefront of 56 columns of one row; the workspace qlg_adjoint_query reports must hold them
     beside the two sets of recorded inputs, the forward chain's two state copies, the two
     complex128 cotangents, the fused kernel's instance prefix table and the dL/dg accumulator."""
     lib = Q.lib()
@@ -135,7 +135,7 @@ def test_adjoint_workspace_covers_kernel_partials(Q, ndim, nx, ny, nz, split):
     nchunks = sum((s + 255) // 256 for s in sites)
     rows = [(y if ndim >= 2 else 1) * (z if ndim == 3 else 1) for y, z in zip(ny or [1] * len(nx), nz or [1] * len(nx))]
     nx4 = sum((x + 55) // 56 * r for x, r in zip(nx, rows))
-    nparts = nsub * nchunks if split == 1 else (nsub - 4) * nchunks + nx4
+    nparts = nsub * nchunks if split == 1 else (nsub - 4) * 4 * nchunks + nx4
     need = (2 * _up256(K * nrec * copy) + _up256(2 * copy) + _up256(2 * lam)
             + _up256(8 * 3 * nparts) + _up256(4 * (len(nx) + 1)) + _up256(8 * 4))
     assert wk.value >= need, (wk.value, need)
