@@ -11,6 +11,8 @@
 //
 // All kernels are one thread per site over 256-site chunks of each instance.
 
+#include <algorithm>
+
 #include "qlg_adjoint_kernels.hpp"
 #include "qlg_math.hpp"
 #include "qlg_vjp.hpp"
@@ -388,15 +390,67 @@ __global__ __launch_bounds__(kLanes) void k_sub_adj(const cx<T>* __restrict__ z,
   }
 }
 
+// Buffer-resource stores (a lane whose offset lies beyond the record count stores nothing), so
+// that every path through a loop issues the same memory instructions and the compiler's waits
+// for loads issued ahead stay exact.
+constexpr int kBufWord3 = 0x00020000;   // resource word 3 on gfx9: 32-bit data format, no swizzle
+constexpr uint32_t kOffNone = 0x80000000u;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+
+// A wavefront tile of the fused x kernels: 56 columns of one row of one instance plus 4 halo
+// columns on each side.  The instance is the last i with xpre[i] <= w; the tables are read
+// through the constant address space (scalar loads, not ordered behind vector memory).
+struct X4Tile {
+  InstDesc d;
+  int row;   // row of the instance (y + ny z)
+  int s;     // this lane's site (periodic column)
+  int x;     // this lane's column before the wrap
+  bool own;  // one of the 56 columns this tile writes
+};
+__device__ __forceinline__ X4Tile x4_tile(const LaunchGeom& g, const int* xpre_g, int w, int lane) {
+  typedef const __attribute__((address_space(4))) int32_t* CInt;
+  const CInt xpre = (CInt)xpre_g;
+  int lo = 0, hi = g.nbatch;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (xpre[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  static_assert(sizeof(InstDesc) % 4 == 0, "InstDesc is read as 32-bit words");
+  constexpr int kWords = (int)(sizeof(InstDesc) / 4);
+  const CInt words = (CInt)g.inst + kWords * lo;
+  int32_t buf[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) buf[i] = words[i];
+  X4Tile r;
+  __builtin_memcpy(&r.d, buf, sizeof(InstDesc));
+  const int t = w - xpre[lo];
+  const int ntx = (r.d.nx + kValid2D - 1) / kValid2D;
+  const int tx = t % ntx;
+  r.row = t / ntx;
+  r.x = tx * kValid2D - kHalo2D + lane;
+  const int xw = r.x < 0 ? r.x + r.d.nx * ((-r.x + r.d.nx - 1) / r.d.nx) : r.x % r.d.nx;
+  r.own = lane >= kHalo2D && lane < kLanes - kHalo2D && r.x < r.d.nx;
+  r.s = r.row * r.d.nx + xw;
+  return r;
+}
+
 // The four adjoint substeps along x of a step, fused: for k = k0 + 3, ..., k0 (qubits a, a, b, b),
 //   lambda <- (dU_k)^H I'^H_{x,q_k} lambda  at the recorded inputs z_k.
-// A wavefront takes 56 columns of one row (x tiles of each row, rows of each instance in order,
+// A tile is 56 columns of one row (x tiles of each row, rows of each instance in order,
 // instances by the prefix table xpre) plus 4 halo columns on each side: each I'^H reaches one
 // site, so after the four substeps the middle 56 lanes hold the cotangent of their sites, read
 // and written once instead of once per substep.  The x shifts are lane moves.  Only the 56 owned
-// lanes add to the dg partial of the wavefront (part[3 w + 0..2]).
-// (One wave per SIMD: its registers, 256 + about 100 accumulation registers, do not fit the
-// 256 of two waves without spilling to scratch, which measured 1.5x slower.)
+// lanes add to the dg partial of the tile (part[3 w + 0..2]).
+// One wavefront per SIMD (its registers, 256 + about 130 accumulation registers, do not fit the
+// 256 of two waves without spilling to scratch, which measured 1.5x slower), persistent: a
+// wavefront walks tiles of its XCD's contiguous range, and during a tile's last substep it loads
+// the next tile's cotangent, potential and first record, whose latency a wavefront alone on its
+// SIMD would otherwise wait out at the start of every tile.
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_adj_x4(const cx<T>* __restrict__ z3, const cx<T>* __restrict__ z2,
                                                   const cx<T>* __restrict__ z1, const cx<T>* __restrict__ z0,
@@ -406,58 +460,111 @@ __global__ __launch_bounds__(kChunk) void k_adj_x4(const cx<T>* __restrict__ z3,
                                                   const double* __restrict__ pot, double mu,
                                                   double* __restrict__ part) {
   constexpr int kWaves = kChunk / kLanes;
-  const int w = chunk_of_block(blockIdx.x, gridDim.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= nwaves) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kLanes - 1);
-  // instance: the last i with xpre[i] <= w (wavefront-uniform)
-  int lo = 0, hi = g.nbatch;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (xpre[mid] <= w) lo = mid;
-    else hi = mid;
+  // tiles [c0, c1) of this workgroup's XCD, taken with the stride of the XCD's wavefront count
+  // (a grid of fewer than 8 workgroups: each workgroup a group of its own)
+  const int nb = gridDim.x, ng = nb < kXcds ? nb : kXcds;
+  const int xcd = blockIdx.x % ng, lb = blockIdx.x / ng;
+  const int stride = (nb / ng + (xcd < nb % ng ? 1 : 0)) * kWaves;
+  const int per = nwaves / ng, extra = nwaves % ng;
+  const int c0 = xcd * per + (xcd < extra ? xcd : extra);
+  const int c1 = c0 + per + (xcd < extra ? 1 : 0);
+  int w = c0 + lb * kWaves + wv;
+  if (w >= c1) return;   // wavefront-uniform; no workgroup-level synchronisation below
+  // the potential's phase at a site: a resource of size 0 without a potential reads 0
+  auto ext_at = [&](const X4Tile& t) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t pr = buf_rsrc(pot ? pot + t.d.psi_off / 5 : nullptr,
+                                               pot ? (uint32_t)t.d.sites * 8u : 0u);
+    const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(pr, t.s * 8, 0, 0));
+    return theta * (v + mu);
+  };
+  // the records of substeps k0 + 2, k0 + 1, k0 as a pointer formed by arithmetic (a select
+  // between three pointers in a loop is otherwise made a table in private memory)
+  auto zrec = [&](int i) __attribute__((always_inline)) {
+    const uintptr_t p = (uintptr_t)z2 * (uintptr_t)(i == 0) + (uintptr_t)z1 * (uintptr_t)(i == 1) +
+                        (uintptr_t)z0 * (uintptr_t)(i == 2);
+    return (const cx<T>*)p;
+  };
+  cx<double> nla[5], nlb[5];
+  cx<T> na[5], nb5[5];
+  double next_ext;
+  {
+    const X4Tile t0 = x4_tile(g, xpre, w, lane);
+    load_site(lin, t0.d, t0.s, nla, nlb);
+    next_ext = ext_at(t0);
+    load_site_nt(z3, t0.d, t0.s, na, nb5);
   }
-  const InstDesc d = g.inst[lo];
-  const int t = w - xpre[lo];
-  const int ntx = (d.nx + kValid2D - 1) / kValid2D;
-  const int tx = t % ntx, row = t / ntx;
-  const int x = tx * kValid2D - kHalo2D + lane;
-  const int xw = x < 0 ? x + d.nx * ((-x + d.nx - 1) / d.nx) : x % d.nx;
-  const bool own = lane >= kHalo2D && lane < kLanes - kHalo2D && x < d.nx;
-  const int s = row * d.nx + xw;
-  cx<double> la[5], lb[5];
-  load_site(lin, d, s, la, lb);
-  const double ext = theta * ((pot ? pot[d.psi_off / 5 + s] : 0.0) + mu);
-  double dg[3] = {0.0, 0.0, 0.0};
-  // each substep's recorded input is loaded one substep ahead, so that its latency overlaps
-  // the previous substep's arithmetic (one wavefront per SIMD hides nothing by itself)
-  cx<T> na[5], nb[5];
-  load_site_nt(z3, d, s, na, nb);
-#pragma unroll 1
-  for (int i = 0; i < 4; ++i) {   // k0 + 3, k0 + 2 (qubit a), k0 + 1, k0 (qubit b)
-    cx<double> a[5], b[5];
+  for (;;) {
+    const X4Tile cur = x4_tile(g, xpre, w, lane);
+    cx<double> la[5], lb5[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      a[m] = cx<double>{(double)na[m].re, (double)na[m].im};
-      b[m] = cx<double>{(double)nb[m].re, (double)nb[m].im};
+      la[m] = nla[m];
+      lb5[m] = nlb[m];
     }
-    if (i < 3) load_site_nt(i == 0 ? z2 : i == 1 ? z1 : z0, d, s, na, nb);
-    if (i < 2) iprime_adj_lanes<0>(la, lb);
-    else iprime_adj_lanes<1>(la, lb);
-    double dgl[3] = {0.0, 0.0, 0.0};
-    potential_vjp<true>(a, b, la, lb, theta, g0, g1, g2, dgl, ext);
+    const double ext = next_ext;
+    double dg[3] = {0.0, 0.0, 0.0};
+    // substeps k0 + 3, k0 + 2 (qubit a), k0 + 1 (qubit b), each at the record in na, nb5 and
+    // loading the next one
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      cx<double> a[5], b[5];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dg[k] += own ? dgl[k] : 0.0;
-  }
-  if (own) store_site(lout, d, s, la, lb);
+      for (int m = 0; m < 5; ++m) {
+        a[m] = cx<double>{(double)na[m].re, (double)na[m].im};
+        b[m] = cx<double>{(double)nb5[m].re, (double)nb5[m].im};
+      }
+      load_site_nt(zrec(i), cur.d, cur.s, na, nb5);
+      if (i < 2) iprime_adj_lanes<0>(la, lb5);
+      else iprime_adj_lanes<1>(la, lb5);
+      double dgl[3] = {0.0, 0.0, 0.0};
+      potential_vjp<true>(a, b, la, lb5, theta, g0, g1, g2, dgl, ext);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 3; ++k) dg[k] += cur.own ? dgl[k] : 0.0;
+    }
+    // substep k0 (qubit b), with the next tile's cotangent, potential and first record loaded
+    // first (the last tile loads its own again: nothing writes lin, pot or the records)
+    const int wn = w + stride;
+    const bool more = wn < c1;
+    {
+      cx<double> a[5], b[5];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dg[k] += __shfl_xor(dg[k], o, kLanes);
-  }
-  if (lane == 0) {
-    part[3 * (int64_t)w] = dg[0];
-    part[3 * (int64_t)w + 1] = dg[1];
-    part[3 * (int64_t)w + 2] = dg[2];
+      for (int m = 0; m < 5; ++m) {
+        a[m] = cx<double>{(double)na[m].re, (double)na[m].im};
+        b[m] = cx<double>{(double)nb5[m].re, (double)nb5[m].im};
+      }
+      const X4Tile nt = x4_tile(g, xpre, more ? wn : w, lane);
+      load_site(lin, nt.d, nt.s, nla, nlb);
+      next_ext = ext_at(nt);
+      load_site_nt(z3, nt.d, nt.s, na, nb5);
+      iprime_adj_lanes<1>(la, lb5);
+      double dgl[3] = {0.0, 0.0, 0.0};
+      potential_vjp<true>(a, b, la, lb5, theta, g0, g1, g2, dgl, ext);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dg[k] += cur.own ? dgl[k] : 0.0;
+    }
+    // the owned columns' cotangents: one row of each plane, lanes outside it drop their stores
+    const uint32_t off = cur.own ? (uint32_t)cur.x * 16u : kOffNone;
+    const uint32_t rb = (uint32_t)cur.d.nx * 16u;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const cx<double>* pa = lout + cur.d.off + m * cur.d.stride + (int64_t)cur.row * cur.d.nx;
+      const cx<double>* pb = lout + cur.d.off + (5 + m) * cur.d.stride + (int64_t)cur.row * cur.d.nx;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, la[m]), buf_rsrc(pa, rb), (int)off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, lb5[m]), buf_rsrc(pb, rb), (int)off, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) dg[k] += __shfl_xor(dg[k], o, kLanes);
+    }
+    // lanes 0, 1, 2 store dg[0], dg[1], dg[2] of the tile
+    const double mine = lane == 0 ? dg[0] : lane == 1 ? dg[1] : dg[2];
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, mine), buf_rsrc(part + 3 * (int64_t)w, 24u),
+                                          (int)(lane < 3 ? (uint32_t)lane * 8u : kOffNone), 0, 0);
+    if (!more) break;
+    w = wn;
   }
 }
 
@@ -774,7 +881,9 @@ hipError_t launch_adj_x4(int dtype, const void* const z[4], const void* lam_in, 
                          const ExtPot& ext, double* part, hipStream_t st) {
   if (nwaves <= 0) return hipSuccess;
   constexpr int kWaves = kChunk / kLanes;
-  const dim3 grid((nwaves + kWaves - 1) / kWaves), block(kChunk);
+  // one wavefront per SIMD: at most one workgroup of four per CU, each walking several tiles
+  constexpr int kAdjX4Blocks = 256;
+  const dim3 grid(std::min((nwaves + kWaves - 1) / kWaves, kAdjX4Blocks)), block(kChunk);
   const double* pot = ext.V;
   if (dtype == 0)
     hipLaunchKernelGGL(k_adj_x4<float>, grid, block, 0, st, (const cx<float>*)z[0], (const cx<float>*)z[1],
