@@ -31,7 +31,8 @@ struct Sizes {
   int64_t nchunks = 0; // 256-site chunks of the per-site kernels
   int64_t nx4 = 0;     // wavefronts of the fused x substeps (56 columns of one row each)
   int64_t nparts = 0;  // dg partials (3 doubles each) of one step's reverse sweep
-  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_xpre = 0, off_acc = 0;
+  int64_t part_steps = 1;  // steps whose dg partials are kept before they are summed
+  size_t off_zrec = 0, off_y = 0, off_lam = 0, off_part = 0, off_xpre = 0, off_acc = 0, off_red = 0;
   size_t off_zrec2 = 0;  // the second record buffer: the end of the workspace without it
   size_t work = 0;
 };
@@ -86,10 +87,14 @@ qlg_status sizes_for(const qlg_params* p, int64_t nsteps, int32_t K, Sizes* s) {
   s->off_zrec = o;  o += up256((size_t)K * (size_t)s->nrec * s->copy);
   s->off_y = o;     o += up256(2 * s->copy);   // ping-pong of the forward chain
   s->off_lam = o;   o += up256(2 * s->lam);
-  // dg partials of one step: [nparts][3]
-  s->off_part = o;  o += up256(sizeof(double) * 3 * (size_t)std::max<int64_t>(s->nparts, 1));
+  // dg partials: [part_steps][nparts][3], a segment's steps for the interleaved split (summed once
+  // per segment), one step for the plain split (summed per step)
+  s->part_steps = p->split == QLG_SPLIT_PLAIN ? 1 : K;
+  s->off_part = o;
+  o += up256(sizeof(double) * 3 * (size_t)s->part_steps * (size_t)std::max<int64_t>(s->nparts, 1));
   s->off_xpre = o;  o += up256(sizeof(int) * ((size_t)p->nbatch + 1));   // k_adj_x4's instance prefix
   s->off_acc = o;   o += up256(sizeof(double) * 4);
+  s->off_red = o;   o += up256(sizeof(double) * 3 * (size_t)qlg::kDgBlocks);   // the segment sum's blocks
   // a second [K][nrec] record buffer, last, so that the next segment's inputs can be recomputed
   // while the reverse sweep reads the current one's
   s->off_zrec2 = o; o += up256((size_t)K * (size_t)s->nrec * s->copy);
@@ -197,8 +202,8 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   const bool plain = p.split == QLG_SPLIT_PLAIN;
   const int64_t nparts_ctx = plain ? (int64_t)s.nsub * v.geom.nchunks
                                    : (int64_t)(s.nsub - 4) * kSubAdjParts * v.geom.nchunks + s.nx4;
-  if (v.geom.nchunks != s.nchunks || (size_t)3 * std::max<int64_t>(nparts_ctx, 1) * sizeof(double) >
-                                         s.off_xpre - s.off_part)
+  if (v.geom.nchunks != s.nchunks ||
+      (size_t)3 * (size_t)s.part_steps * std::max<int64_t>(nparts_ctx, 1) * sizeof(double) > s.off_xpre - s.off_part)
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "adjoint partials exceed their workspace region");
   if (((uintptr_t)work_dev & 255) || ((uintptr_t)ckpt_dev & 255))
     return qlg::ctx_fail(ctx, QLG_ERR_ARG, "buffers must be 256-byte aligned");
@@ -210,6 +215,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   char* lam[2] = {W + s.off_lam, W + s.off_lam + s.lam};
   double* part = (double*)(W + s.off_part);
   double* acc = (double*)(W + s.off_acc);
+  double* red = (double*)(W + s.off_red);
   const qlg::LaunchGeom& g = v.geom;
   const hipStream_t str = v.stream;
   const int nd = p.ndim, dt = p.dtype, nsub = s.nsub, nrec = s.nrec;
@@ -311,12 +317,13 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
       if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
     }
     for (int j = n_in - 1; j >= 0; --j) {
+      double* pj = part + (size_t)3 * (plain ? 0 : (size_t)j * s.nparts);   // this step's partials
       if (!plain) {
         // the step's last four substeps (along x) in one kernel, their dg partials after those
         // of the nsub - 4 per-chunk substeps
         const void* zx[4] = {zbuf(b, j, nsub - 1), zbuf(b, j, nsub - 2), zbuf(b, j, nsub - 3), zbuf(b, j, nsub - 4)};
         e = qlg::launch_adj_x4(dt, zx, lam[lc], lam[1 - lc], g, xpre, (int)s.nx4, theta_u, p.g0, p.g1, p.g2,
-                               v.ext, part + (size_t)3 * (nsub - 4) * kSubAdjParts * nchunks, str);
+                               v.ext, pj + (size_t)3 * (nsub - 4) * kSubAdjParts * nchunks, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint x substeps kernel");
         lc = 1 - lc;
       }
@@ -327,7 +334,7 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         } else {
           // kinetic pull-back and self-interaction VJP of substep k in one kernel
           e = qlg::launch_sub_adj(dt, zbuf(b, j, k), lam[lc], lam[1 - lc], g, axis_of(k), qb_of(k), theta_u, p.g0,
-                                  p.g1, p.g2, v.ext, part + (size_t)3 * k * kSubAdjParts * nchunks, str);
+                                  p.g1, p.g2, v.ext, pj + (size_t)3 * k * kSubAdjParts * nchunks, str);
           if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint substep kernel");
         }
         lc = 1 - lc;
@@ -335,10 +342,12 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
       if (plain) {
         e = qlg::launch_sub_vjp(dt, zbuf(b, j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
-      } else {
-        e = qlg::launch_dg_accumulate(part, (int)s.nparts, acc, str);
-        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint parameter-gradient reduction");
       }
+    }
+    if (!plain) {
+      // the segment's dg partials, summed once in a fixed order
+      e = qlg::launch_dg_reduce(part, (int64_t)n_in * s.nparts, red, acc, str);
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint parameter-gradient reduction");
     }
     if (overlap && seg > 1) {
       e = hipEventRecord(ev[2], str);   // the sweep of this segment has read buffer b

@@ -666,6 +666,23 @@ __global__ __launch_bounds__(kDgThreads) void k_dg_accumulate(const double* __re
   }
 }
 
+// First stage of launch_dg_reduce: workgroup b sums the partials of its contiguous range
+// [b n / G, (b + 1) n / G) (thread t: entries t, t + 256, ... of the range; then the four
+// wavefront sums in order) into red[b][0..2].
+__global__ __launch_bounds__(kChunk) void k_dg_blocks(const double* __restrict__ part, int64_t n,
+                                                     double* __restrict__ red) {
+  const int64_t G = gridDim.x;
+  const int64_t lo = n * blockIdx.x / G, hi = n * (blockIdx.x + 1) / G;
+  double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int64_t c = lo + threadIdx.x; c < hi; c += kChunk) {
+    v[0] += part[3 * c];
+    v[1] += part[3 * c + 1];
+    v[2] += part[3 * c + 2];
+  }
+  block_sum3(v[0], v[1], v[2], red + 3 * (int64_t)blockIdx.x);
+}
+
 // Energy objective: lambda_a = lambda_b = 2 dE/dpsi* written in the canonical
 // complex128 qubits layout; per chunk partials part[6c + 0..3] of
 // eps^d x (E density, n^2/2, |F|^2/2, |sigma|^2/10).
@@ -894,6 +911,13 @@ hipError_t launch_adj_x4(int dtype, const void* const z[4], const void* lam_in, 
                        (const cx<double>*)z[2], (const cx<double>*)z[3], (const cx<double>*)lam_in,
                        (cx<double>*)lam_out, g, xpre, nwaves, theta, g0, g1, g2, pot, ext.mu, part);
   return hipGetLastError();
+}
+
+hipError_t launch_dg_reduce(const double* part, int64_t nparts, double* red, double* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_dg_blocks, dim3(kDgBlocks), dim3(kChunk), 0, st, part, nparts, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_dg_accumulate(red, kDgBlocks, acc, st);
 }
 
 hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hipStream_t st) {

@@ -38,6 +38,10 @@ hipError_t launch_chain_x4(int dtype, const void* in, void* out, void* const rec
 hipError_t launch_x4_prefix(const LaunchGeom& g, int* xpre, hipStream_t st);
 // acc[0..2] += sum of nparts consecutive 3-vectors of part (fixed order)
 hipError_t launch_dg_accumulate(const double* part, int nparts, double* acc, hipStream_t st);
+// The same for many partials: kDgBlocks workgroups sum contiguous ranges of part into
+// red[kDgBlocks][3] (fixed order), then one workgroup adds those to acc in order.
+constexpr int kDgBlocks = 256;
+hipError_t launch_dg_reduce(const double* part, int64_t nparts, double* red, double* acc, hipStream_t st);
 // energy objective: canonical complex128 cotangent + chunk partials [nchunks][4]
 hipError_t launch_energy_grad(int dtype, int ndim, const void* state, void* lam, const LaunchGeom& g, double eps,
                               double g0, double g1, double g2, const ExtPot& ext, double* part, hipStream_t st);

@@ -136,7 +136,9 @@ def test_adjoint_workspace_covers_kernel_partials(Q, ndim, nx, ny, nz, split):
     rows = [(y if ndim >= 2 else 1) * (z if ndim == 3 else 1) for y, z in zip(ny or [1] * len(nx), nz or [1] * len(nx))]
     nx4 = sum((x + 55) // 56 * r for x, r in zip(nx, rows))
     nparts = nsub * nchunks if split == 1 else (nsub - 4) * 4 * nchunks + nx4
+    part_steps = 1 if split == 1 else K   # the interleaved split sums a segment's partials at once
     need = (2 * _up256(K * nrec * copy) + _up256(2 * copy) + _up256(2 * lam)
-            + _up256(8 * 3 * nparts) + _up256(4 * (len(nx) + 1)) + _up256(8 * 4))
+            + _up256(8 * 3 * nparts * part_steps) + _up256(4 * (len(nx) + 1)) + _up256(8 * 4)
+            + _up256(8 * 3 * 256))
     assert wk.value >= need, (wk.value, need)
     assert ck.value == -(-nsteps // K) * copy
