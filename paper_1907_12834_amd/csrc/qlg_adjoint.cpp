@@ -10,7 +10,8 @@
 //       lambda <- (dU/dz)^H lambda       (FP64 Jacobian at the recomputed substep input)
 //   (plain split: one U with theta = eps^2 before the I' list, so only the step input is needed.)
 // With two record buffers the recompute of the segment before runs on the context's second
-// stream while the sweep pulls lambda back through the current one.  dL/dg accumulates in FP64
+// stream while the sweep pulls lambda back through the current one, its steps issued in step
+// with the sweep's.  dL/dg accumulates in FP64
 // on the device in a fixed order.
 #include <algorithm>
 #include <cmath>
@@ -229,53 +230,70 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   auto zbuf = [&](int b, int64_t j, int r) { return zrec[b] + ((size_t)j * nrec + r) * s.copy; };
   auto seg_steps = [&](int64_t seg) { return (int)std::min<int64_t>(K, nsteps - seg * K); };
 
-  // Forward chain of segment seg from its checkpoint into record buffer b, on stream q:
-  // substep k of step j is "I'_{k-1} then U_k" (the I' of the previous substep, none for the
-  // first one), recording every U input.
-  auto record_segment = [&](int64_t seg, int b, hipStream_t q) -> hipError_t {
-    const int n_in = seg_steps(seg);
-    const void* src = (const char*)ckpt_dev + (size_t)seg * s.copy;
-    int yb = 0;
+  // Forward chain of segment seg from its checkpoint into record buffer b: substep k of step j
+  // is "I'_{k-1} then U_k" (the I' of the previous substep, none for the first one), recording
+  // every U input.  A chain is issued in ranges of steps, in order: chain_to(c, j1, q) issues
+  // steps c.j .. j1 - 1 on stream q; src and yb carry the state between the calls.
+  struct Chain {
+    int64_t seg;
+    int b;
+    const void* src;
+    int yb;
+    int j;
+  };
+  auto chain_begin = [&](int64_t seg, int b) { return Chain{seg, b, (const char*)ckpt_dev + (size_t)seg * s.copy, 0, 0}; };
+  auto chain_to = [&](Chain& c, int j1, hipStream_t q) -> hipError_t {
+    const int n_in = seg_steps(c.seg);
+    const int b = c.b;
     hipError_t e = hipSuccess;
     if (!plain) {
       // interleaved split: link (0, 0) alone, then per step the links (j, 1 .. nsub - 4) one
       // launch each and the four links that apply x factors, (j, nsub - 3 .. nsub - 1) and
       // (j + 1, 0), in one launch (three in the segment's last step)
       const double tg0 = theta_u * p.g0, tg1 = theta_u * p.g1, tg25 = theta_u * p.g2 / 5.0;
-      e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(b, 0, 0), g, -1, 0, true, tg0, tg1, tg25, v.ext, theta_u, q);
-      src = ybuf[yb];
-      yb ^= 1;
-      for (int j = 0; j < n_in && e == hipSuccess; ++j) {
+      if (c.j == 0 && j1 > 0) {
+        e = qlg::launch_chain(dt, c.src, ybuf[c.yb], zbuf(b, 0, 0), g, -1, 0, true, tg0, tg1, tg25, v.ext, theta_u,
+                              q);
+        c.src = ybuf[c.yb];
+        c.yb ^= 1;
+      }
+      for (; c.j < j1 && e == hipSuccess; ++c.j) {
+        const int j = c.j;
         for (int k = 1; k <= nsub - 4 && e == hipSuccess; ++k) {
-          e = qlg::launch_chain(dt, src, ybuf[yb], zbuf(b, j, k), g, axis_of(k - 1), qb_of(k - 1), true, tg0, tg1,
-                                tg25, v.ext, theta_u, q);
-          src = ybuf[yb];
-          yb ^= 1;
+          e = qlg::launch_chain(dt, c.src, ybuf[c.yb], zbuf(b, j, k), g, axis_of(k - 1), qb_of(k - 1), true, tg0,
+                                tg1, tg25, v.ext, theta_u, q);
+          c.src = ybuf[c.yb];
+          c.yb ^= 1;
         }
         if (e != hipSuccess) break;
         void* const r[4] = {zbuf(b, j, nsub - 3), zbuf(b, j, nsub - 2), zbuf(b, j, nsub - 1),
                             j + 1 < n_in ? zbuf(b, j + 1, 0) : nullptr};
-        e = qlg::launch_chain_x4(dt, src, ybuf[yb], r, g, xpre, (int)s.nx4, tg0, tg1, tg25, v.ext, theta_u, q);
-        src = ybuf[yb];
-        yb ^= 1;
+        e = qlg::launch_chain_x4(dt, c.src, ybuf[c.yb], r, g, xpre, (int)s.nx4, tg0, tg1, tg25, v.ext, theta_u, q);
+        c.src = ybuf[c.yb];
+        c.yb ^= 1;
       }
       return e;
     }
-    for (int j = 0; j < n_in; ++j) {
+    for (; c.j < j1; ++c.j) {
+      const int j = c.j;
       for (int k = 0; k < nsub; ++k) {
         const int kp = k == 0 ? nsub - 1 : k - 1;
         const bool first = j == 0 && k == 0;
         const bool has_u = k == 0;
         if (j == n_in - 1 && k > 0) break;   // later links feed nothing recorded
-        e = qlg::launch_chain(dt, src, ybuf[yb], has_u ? zbuf(b, j, 0) : nullptr, g, first ? -1 : axis_of(kp),
+        e = qlg::launch_chain(dt, c.src, ybuf[c.yb], has_u ? zbuf(b, j, 0) : nullptr, g, first ? -1 : axis_of(kp),
                               qb_of(kp), has_u, theta_u * p.g0, theta_u * p.g1, theta_u * p.g2 / 5.0, v.ext,
                               theta_u, q);
         if (e != hipSuccess) return e;
-        src = ybuf[yb];
-        yb ^= 1;
+        c.src = ybuf[c.yb];
+        c.yb ^= 1;
       }
     }
     return e;
+  };
+  auto record_segment = [&](int64_t seg, int b, hipStream_t q) -> hipError_t {
+    Chain c = chain_begin(seg, b);
+    return chain_to(c, seg_steps(seg), q);
   };
 
   hipError_t e = qlg::launch_zero(acc, 4, str);
@@ -301,14 +319,17 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int n_in = seg_steps(seg);
     int b = 0;
+    // the next segment's chain, issued step by step with this segment's sweep (below), so that
+    // both streams hold work whatever the pace of the host's launches
+    const bool rec_next = overlap && seg > 0;
+    Chain nc{};
     if (overlap) {
       b = (int)((nseg - 1 - seg) & 1);
-      if (seg > 0) {
+      if (rec_next) {
         // the next segment's records go to the other buffer, once the sweep that read it ended
         if (seg + 1 < nseg) e = hipStreamWaitEvent(aux, ev[2], 0);
-        if (e == hipSuccess) e = record_segment(seg - 1, 1 - b, aux);
-        if (e == hipSuccess) e = hipEventRecord(ev[1 - b], aux);
-        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint stream order");
+        nc = chain_begin(seg - 1, 1 - b);
       }
       e = hipStreamWaitEvent(str, ev[b], 0);
       if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint stream order");
@@ -343,6 +364,16 @@ qlg_status qlg_adjoint_step(qlg_ctx* ctx, int64_t nsteps, int32_t K, const void*
         e = qlg::launch_sub_vjp(dt, zbuf(b, j, 0), lam[lc], g, theta_u, p.g0, p.g1, p.g2, v.ext, part, acc, str);
         if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint self-interaction kernel");
       }
+      if (rec_next) {
+        // the chain's steps in proportion to the sweep's (all of them with the sweep's last step)
+        const int64_t m = seg_steps(seg - 1), done = n_in - j;
+        e = chain_to(nc, (int)((m * done + n_in - 1) / n_in), aux);
+        if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint forward recompute");
+      }
+    }
+    if (rec_next) {
+      e = hipEventRecord(ev[1 - b], aux);
+      if (e != hipSuccess) return qlg::ctx_hip(ctx, e, "adjoint stream order");
     }
     if (!plain) {
       // the segment's dg partials, summed once in a fixed order
